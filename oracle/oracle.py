@@ -1,0 +1,199 @@
+"""ctypes binding of the CPU oracle (oracle/so3_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+CPU-baseline leg of bench.py.  Nothing in the GPU library imports it.
+
+All arrays are numpy; complex data is complex128 (the C side sees interleaved
+doubles).  ``prec`` selects the double build ("f64") or the x87 long-double
+build ("f80"); both take and return doubles.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+_SIGS = {
+    "so3o_weights": [ctypes.c_int, _dp],
+    "so3o_wigner_d": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp],
+    "so3o_wigner_d_grid": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp],
+    "so3o_dft2": [ctypes.c_int, ctypes.c_int, _dp],
+    "so3o_forward": [ctypes.c_int, _dp, _dp],
+    "so3o_inverse": [ctypes.c_int, _dp, _dp],
+    "so3o_adjoint": [ctypes.c_int, _dp, _dp],
+    "so3o_adjoint_inverse": [ctypes.c_int, _dp, _dp],
+    "so3o_separation_forward": [ctypes.c_int, _dp, _dp],
+    "so3o_idwt": [ctypes.c_int, _dp, _dp],
+    "so3o_inverse_slice": [ctypes.c_int, _dp, ctypes.c_int, _dp],
+    "so3o_forward_pairs": [ctypes.c_int, _dp, ctypes.c_int, _ip, _dp],
+    "so3o_num_threads": [],
+}
+
+
+def lib():
+    """Load (building on first use if needed) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        for name, args in _SIGS.items():
+            for suf in ("_f64", "_f80"):
+                fn = getattr(_lib, name + suf)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+    return _lib
+
+
+def _fn(name, prec):
+    if prec not in ("f64", "f80"):
+        raise ValueError("prec must be 'f64' or 'f80'")
+    return getattr(lib(), f"{name}_{prec}")
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise RuntimeError(f"oracle {name} failed with status {rc}")
+
+
+def num_coeffs(B):
+    """B(4B^2-1)/3 coefficients for bandwidth B (Sect. 2.4)."""
+    return B * (4 * B * B - 1) // 3
+
+
+def coeff_index(l, m, mp):
+    """Flat index of f°(l, m, m') in the l-major layout."""
+    return l * (4 * l * l - 1) // 3 + (m + l) * (2 * l + 1) + (mp + l)
+
+
+def num_threads(prec="f64"):
+    return int(_fn("so3o_num_threads", prec)())
+
+
+def weights(B, prec="f64"):
+    """Quadrature weights w_B(j), j < 2B (eq. "weights")."""
+    w = np.empty(2 * B)
+    _check(_fn("so3o_weights", prec)(B, _ptr(w)), "weights")
+    return w
+
+
+def wigner_d(B, m, mp, beta, prec="f64"):
+    """d(l, m, m'; beta) for l < B by seeds + three-term recurrence."""
+    d = np.empty(B)
+    _check(_fn("so3o_wigner_d", prec)(B, m, mp, float(beta), _ptr(d)), "wigner_d")
+    return d
+
+
+def wigner_d_grid(B, m, mp, j, prec="f64"):
+    """d(l, m, m'; beta_j) for l < B with beta_j = (2j+1)pi/(4B) formed in the
+    oracle's working precision."""
+    d = np.empty(B)
+    _check(_fn("so3o_wigner_d_grid", prec)(B, m, mp, j, _ptr(d)), "wigner_d_grid")
+    return d
+
+
+def dft2(a, sign, prec="f64"):
+    """Unnormalised 2-D DFT exp(sign 2 pi i (pq)/n) of a square complex array."""
+    a = _c128(a).copy()
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    _check(_fn("so3o_dft2", prec)(n, sign, _ptr(a.view(np.float64))), "dft2")
+    return a
+
+
+def _grid_shape(B):
+    return (2 * B, 2 * B, 2 * B)
+
+
+def forward(B, grid, prec="f64"):
+    """FSOFT: grid [2B,2B,2B] complex -> coefficients [B(4B^2-1)/3] complex."""
+    g = _c128(grid).reshape(-1)
+    assert g.size == (2 * B) ** 3
+    c = np.empty(num_coeffs(B), np.complex128)
+    _check(_fn("so3o_forward", prec)(B, _ptr(g.view(np.float64)), _ptr(c.view(np.float64))), "forward")
+    return c
+
+
+def inverse(B, coeffs, prec="f64"):
+    """iFSOFT: coefficients -> grid [2B,2B,2B] complex."""
+    c = _c128(coeffs).reshape(-1)
+    assert c.size == num_coeffs(B)
+    g = np.empty(_grid_shape(B), np.complex128)
+    _check(_fn("so3o_inverse", prec)(B, _ptr(c.view(np.float64)), _ptr(g.view(np.float64))), "inverse")
+    return g
+
+
+def adjoint(B, coeffs, prec="f64"):
+    """F^H = W I V: adjoint of the forward transform."""
+    c = _c128(coeffs).reshape(-1)
+    assert c.size == num_coeffs(B)
+    g = np.empty(_grid_shape(B), np.complex128)
+    _check(_fn("so3o_adjoint", prec)(B, _ptr(c.view(np.float64)), _ptr(g.view(np.float64))), "adjoint")
+    return g
+
+
+def adjoint_inverse(B, grid, prec="f64"):
+    """I^H = V^-1 F W^-1: adjoint of the inverse transform."""
+    g = _c128(grid).reshape(-1)
+    assert g.size == (2 * B) ** 3
+    c = np.empty(num_coeffs(B), np.complex128)
+    _check(_fn("so3o_adjoint_inverse", prec)(B, _ptr(g.view(np.float64)), _ptr(c.view(np.float64))),
+           "adjoint_inverse")
+    return c
+
+
+def separation_forward(B, grid, prec="f64"):
+    """S(m, m'; j) unweighted, shape [2B-1, 2B-1, 2B] indexed [m+B-1, m'+B-1, j]."""
+    g = _c128(grid).reshape(-1)
+    P, N = 2 * B - 1, 2 * B
+    S = np.empty((P, P, N), np.complex128)
+    _check(_fn("so3o_separation_forward", prec)(B, _ptr(g.view(np.float64)), _ptr(S.view(np.float64))),
+           "separation_forward")
+    return S
+
+
+def idwt(B, coeffs, prec="f64"):
+    """S'(j; m, m') = sum_l d f°, shape [2B-1, 2B-1, 2B] indexed [m+B-1, m'+B-1, j]."""
+    c = _c128(coeffs).reshape(-1)
+    P, N = 2 * B - 1, 2 * B
+    S = np.empty((P, P, N), np.complex128)
+    _check(_fn("so3o_idwt", prec)(B, _ptr(c.view(np.float64)), _ptr(S.view(np.float64))), "idwt")
+    return S
+
+
+def inverse_slice(B, coeffs, j, prec="f64"):
+    """f(alpha_i, beta_j, gamma_k) for all (i, k): one beta-slice of the inverse."""
+    c = _c128(coeffs).reshape(-1)
+    N = 2 * B
+    s = np.empty((N, N), np.complex128)
+    _check(_fn("so3o_inverse_slice", prec)(B, _ptr(c.view(np.float64)), int(j), _ptr(s.view(np.float64))),
+           "inverse_slice")
+    return s
+
+
+def forward_pairs(B, grid, pairs, prec="f64"):
+    """f°(l, m, m') for l < B of the listed (m, m') pairs: array [npairs, B]."""
+    g = _c128(grid).reshape(-1)
+    assert g.size == (2 * B) ** 3
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    out = np.empty((p.shape[0], B), np.complex128)
+    _check(_fn("so3o_forward_pairs", prec)(B, _ptr(g.view(np.float64)), p.shape[0],
+                                           p.ctypes.data_as(_ip), _ptr(out.view(np.float64))),
+           "forward_pairs")
+    return out
