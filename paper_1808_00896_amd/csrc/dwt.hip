@@ -1,0 +1,272 @@
+// dwt.hip -- discrete Wigner transform (DWT) and its transpose (iDWT) on
+// gfx950, in FP64, for every symmetry group of order pairs.
+//
+// Matrix form of Sect. 2.4: for each (m, m'),
+//   forward  f°(l) = (2l+1)/(8 pi B) sum_j d(l,m,m';b_j) w_B(j) S(m,m';j)   (V T W)
+//   inverse  S'(j) = sum_l d(l,m,m';b_j) f°(l)                              (T^T)
+// The weights were applied by the FFT pass and the (2l+1)/(8 pi B) factor and
+// the symmetry signs by the reorder pass, so the kernels here compute, for
+// the representative d_rep(l; b_j) of a group and its <= 8 member columns c,
+//   forward  G[l][c]  = sum_j d_rep(l; b_j) X[j][c]
+//   inverse  Y[j][c]  = sum_l d_rep(l; b_j) F[l][c]
+// (members at pi - beta were stored in reversed j order, eq. "Wigner_symmetries").
+//
+// d_rep is never stored: each lane owns one beta_j, seeds d(l0,l0,m';b_j)
+// (Sect. 2.2, evaluated in log space with double-double exponents) and runs
+// the three-term recurrence of eq. "Wigner_d_recurrence" in registers.  One
+// block handles one group, so one recurrence feeds all of its members.
+//   inverse: the contraction over l is a per-lane FMA chain against the
+//            coefficients, which are uniform across the wave (scalar loads);
+//   forward: the contraction over j is a reduction across lanes; every 16
+//            degrees the lanes park d in an LDS panel and v_mfma_f64_16x16x4
+//            reduces panel x X (16 l x 16 columns) over j at full FP64 rate.
+#include "soft_internal.h"
+
+namespace soft {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxB = 512;
+
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD two_prod(double a, double b) {
+    const double h = a * b;
+    return {h, fma(a, b, -h)};
+}
+__device__ __forceinline__ DD two_sum(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+// Seed d(l0, l0, m'; b_j) = sqrt((2 l0)!/((l0+m')!(l0-m')!)) cos^{l0+m'}(b/2)
+// sin^{l0-m'}(b/2) for the representative (l0 = m >= m' >= 0), Sect. 2.2.
+// The exponent is summed in double-double so only the final exp rounds.
+__device__ __forceinline__ double seed_d(const PlanView &p, int g, int m, int mp, int j) {
+    const double2 lb = p.lbin[g];
+    const double4 t = p.lcs[j];
+    const double P = (double)(m + mp), Q = (double)(m - mp);
+    DD a = two_prod(P, t.x);
+    a.lo = fma(P, t.y, a.lo);
+    DD c = two_prod(Q, t.z);
+    c.lo = fma(Q, t.w, c.lo);
+    const DD s1 = two_sum(lb.x, a.hi);
+    const DD s2 = two_sum(s1.hi, c.hi);
+    const double lo = lb.y + a.lo + c.lo + s1.lo + s2.lo;
+    if (s2.hi < -745.0) return 0.0;
+    return exp(s2.hi) * (1.0 + lo);  // exp(hi + lo) to O(lo^2), |lo| < 1e-12
+}
+
+// Recurrence coefficients of eq. "Wigner_d_recurrence" for l = l0 .. B-2:
+//   d(l+1) = (A x - C) d(l) - Bc d(l-1),
+//   A = (l+1)(2l+1)/sqrt(((l+1)^2-m^2)((l+1)^2-m'^2)), C = A m m'/(l(l+1)),
+//   Bc = (l+1) sqrt((l^2-m^2)(l^2-m'^2)) / (l sqrt(((l+1)^2-m^2)((l+1)^2-m'^2))),
+// with C = 0 at l = 0 and Bc = 0 at l = l0 (the d(l0-1) term vanishes).
+__device__ __forceinline__ void fill_coefs(int m, int mp, int B, double *cA, double *cC, double *cB, int nthreads) {
+    const int l0 = m;
+    const double M2 = (double)m * m, MP2 = (double)mp * mp, MMP = (double)m * mp;
+    for (int t = threadIdx.x; t < B - l0; t += nthreads) {
+        const int l = l0 + t;
+        const double L = l, L1 = l + 1;
+        const double den = sqrt((L1 * L1 - M2) * (L1 * L1 - MP2));
+        const double A = L1 * (2.0 * L + 1.0) / den;
+        cA[t] = A;
+        cC[t] = l > 0 ? A * (MMP / (L * L1)) : 0.0;
+        cB[t] = l > l0 ? L1 * sqrt((L * L - M2) * (L * L - MP2)) / (L * den) : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward DWT: panel x X on MFMA.
+// ---------------------------------------------------------------------------
+// Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
+// into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds
+// d(l0 + lp + r; b_j) for j-local jl; its LDS index is swizzled so that both
+// the per-lane row writes and the MFMA A-operand reads are conflict-free.
+__device__ __forceinline__ int panel_idx(int jl, int r) { return jl * 16 + (r ^ ((jl >> 1) & 15)); }
+
+template <int NW, int NSUB>
+__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *__restrict__ S,
+                                                    double2 *__restrict__ Cg) {
+    __shared__ double cA[kMaxB], cC[kMaxB], cB[kMaxB];
+    __shared__ double panel[NW][64 * 16];
+    const int g = blockIdx.x;
+    const GroupInfo gi = p.grp[g];
+    const int B = p.B, N = p.N;
+    const int m = gi.m, mp = gi.mp;
+    const int L = B - m;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    fill_coefs(m, mp, B, cA, cC, cB, NW * 64);
+
+    const double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
+    // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
+    const int col = lane & 15, krow = lane >> 4;
+    const bool col_present = (gi.mask >> (col >> 1)) & 1;
+    double xb[NSUB][16];
+    double x[NSUB], dcur[NSUB], dprev[NSUB];
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h) {
+        const int jbase = (wave * NSUB + h) * 64;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int j = jbase + 4 * s + krow;
+            double v = 0.0;
+            if (col_present && j < N) {
+                const double *e = reinterpret_cast<const double *>(Sg + (size_t)(col >> 1) * N + j);
+                v = e[col & 1];
+            }
+            xb[h][s] = v;
+        }
+        const int j = jbase + lane;
+        if (j < N) {
+            x[h] = p.cosb[j];
+            dcur[h] = seed_d(p, g, m, mp, j);
+        } else {
+            x[h] = 0.0;
+            dcur[h] = 0.0;
+        }
+        dprev[h] = 0.0;
+    }
+    __syncthreads();
+
+    double *pan = panel[wave];
+    double *red = &panel[0][0];
+    double *out = reinterpret_cast<double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
+    for (int lp = 0; lp < L; lp += 16) {
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < NSUB; ++h) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int li = lp + r;
+                pan[panel_idx(lane, r)] = li < L ? dcur[h] : 0.0;
+                if (li + 1 < L) {
+                    const double u = fma(cA[li], x[h], -cC[li]);
+                    const double dn = fma(u, dcur[h], -cB[li] * dprev[h]);
+                    dprev[h] = dcur[h];
+                    dcur[h] = dn;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const double a = pan[panel_idx(4 * s + krow, col)];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[h][s], acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // Sum the NW partial tiles.  For the FP64 16x16x4 MFMA, register r of
+        // lane holds C[lane/16 + 4 r][lane%16].
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave * 256 + (krow + 4 * r) * 16 + col] = acc[r];
+        __syncthreads();
+        for (int t = threadIdx.x; t < 256; t += NW * 64) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) sum += red[w * 256 + t];
+            const int row = t >> 4;
+            if (lp + row < L) out[(size_t)(lp + row) * 16 + (t & 15)] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse DWT: per-lane FMA chains, coefficients broadcast.
+// ---------------------------------------------------------------------------
+template <int NW, int JPL>
+__global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *__restrict__ Cg,
+                                                    double2 *__restrict__ S) {
+    __shared__ double cA[kMaxB], cC[kMaxB], cB[kMaxB];
+    const int g = blockIdx.x;
+    const GroupInfo gi = p.grp[g];
+    const int B = p.B, N = p.N;
+    const int m = gi.m, mp = gi.mp;
+    const int L = B - m;
+    fill_coefs(m, mp, B, cA, cC, cB, NW * 64);
+
+    double x[JPL], dcur[JPL], dprev[JPL], acc[JPL][16];
+#pragma unroll
+    for (int h = 0; h < JPL; ++h) {
+        const int j = threadIdx.x + h * NW * 64;
+        x[h] = j < N ? p.cosb[j] : 0.0;
+        dcur[h] = j < N ? seed_d(p, g, m, mp, j) : 0.0;
+        dprev[h] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[h][c] = 0.0;
+    }
+    __syncthreads();
+
+    const double *__restrict__ F =
+        reinterpret_cast<const double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
+    for (int li = 0; li < L; ++li) {
+        double f[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) f[c] = F[(size_t)li * 16 + c];
+#pragma unroll
+        for (int h = 0; h < JPL; ++h)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc[h][c] = fma(dcur[h], f[c], acc[h][c]);
+        if (li + 1 < L) {
+            const double a = cA[li], cc = cC[li], bb = cB[li];
+#pragma unroll
+            for (int h = 0; h < JPL; ++h) {
+                const double u = fma(a, x[h], -cc);
+                const double dn = fma(u, dcur[h], -bb * dprev[h]);
+                dprev[h] = dcur[h];
+                dcur[h] = dn;
+            }
+        }
+    }
+
+    double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
+#pragma unroll
+    for (int h = 0; h < JPL; ++h) {
+        const int j = threadIdx.x + h * NW * 64;
+        if (j >= N) continue;
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s)
+            if ((gi.mask >> s) & 1) Sg[(size_t)s * N + j] = make_double2(acc[h][2 * s], acc[h][2 * s + 1]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *Cg, hipStream_t s) {
+    if (p.B > kMaxB) return hipErrorInvalidValue;
+    dim3 grid(p.G, batch);
+    // waves x subsets of 64 j: N <= 64: 1x1; 128: 2x1; 256: 4x1; 512: 4x2; 1024: 8x2.
+    if (p.N <= 64)
+        hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, S, Cg);
+    else if (p.N == 128)
+        hipLaunchKernelGGL((k_dwt_fwd<2, 1>), grid, dim3(128), 0, s, p, S, Cg);
+    else if (p.N == 256)
+        hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, S, Cg);
+    else if (p.N == 512)
+        hipLaunchKernelGGL((k_dwt_fwd<4, 2>), grid, dim3(256), 0, s, p, S, Cg);
+    else
+        hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, S, Cg);
+    return hipGetLastError();
+}
+
+hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *Cg, double2 *S, hipStream_t s) {
+    if (p.B > kMaxB) return hipErrorInvalidValue;
+    dim3 grid(p.G, batch);
+    if (p.N <= 64)
+        hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, Cg, S);
+    else if (p.N == 128)
+        hipLaunchKernelGGL((k_dwt_inv<2, 1>), grid, dim3(128), 0, s, p, Cg, S);
+    else if (p.N == 256)
+        hipLaunchKernelGGL((k_dwt_inv<4, 1>), grid, dim3(256), 0, s, p, Cg, S);
+    else if (p.N == 512)
+        hipLaunchKernelGGL((k_dwt_inv<4, 2>), grid, dim3(256), 0, s, p, Cg, S);
+    else
+        hipLaunchKernelGGL((k_dwt_inv<8, 2>), grid, dim3(512), 0, s, p, Cg, S);
+    return hipGetLastError();
+}
+
+}  // namespace soft

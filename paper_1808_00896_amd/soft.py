@@ -1,0 +1,213 @@
+"""Thin Python binding of libsoft.so (C-ABI in include/soft.h).
+
+Argument marshalling only: every step of the transforms runs in the HIP
+library.  Tensors are torch complex128 CUDA (HIP) tensors; the binding passes
+their device pointers and the current torch stream.  Loading fails loudly if
+the library has not been built (``python -m paper_1808_00896_amd.build``);
+there is no fallback.
+
+The module-level functions mirror the C entry points one to one
+(``soft_plan``, ``soft_forward``, ...); ``Plan`` wraps a plan handle with
+shape checks and output allocation.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsoft.so")
+
+SOFT_FP64 = 0
+SOFT_OK = 0
+SOFT_ERR_INVALID = -1
+SOFT_ERR_UNSUPPORTED = -2
+SOFT_ERR_OOM = -3
+SOFT_ERR_HIP = -4
+
+_lib = None
+
+
+class SoftError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+def lib():
+    """Load libsoft.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1808_00896_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.soft_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(vp)]
+        L.soft_plan_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        for name in ("soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse"):
+            getattr(L, name).argtypes = [vp, vp, vp, vp]
+        L.soft_plan_destroy.argtypes = [vp]
+        L.soft_status_string.argtypes = [ctypes.c_int]
+        L.soft_status_string.restype = ctypes.c_char_p
+        for name in ("soft_plan", "soft_plan_sizes", "soft_forward", "soft_inverse", "soft_adjoint",
+                     "soft_adjoint_inverse", "soft_plan_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().soft_status_string(int(status)).decode()
+
+
+def _check(rc, what):
+    if rc != SOFT_OK:
+        raise SoftError(rc, what)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ---------------------------------------------------------------------------
+# One-to-one wrappers of the C entry points
+# ---------------------------------------------------------------------------
+
+def soft_plan(B, batch=1, precision=SOFT_FP64, flags=0):
+    """Create a plan on the current device; returns the opaque handle (int)."""
+    h = ctypes.c_void_p()
+    _check(lib().soft_plan(int(B), int(batch), int(precision), int(flags), ctypes.byref(h)), "soft_plan")
+    return h.value
+
+
+def soft_plan_sizes(plan):
+    """(grid_elems, coeff_elems, workspace_bytes) of a plan."""
+    g, c, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().soft_plan_sizes(ctypes.c_void_p(plan), ctypes.byref(g), ctypes.byref(c), ctypes.byref(w)),
+           "soft_plan_sizes")
+    return g.value, c.value, w.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def soft_forward(plan, grid, coeffs, stream=None):
+    _check(lib().soft_forward(ctypes.c_void_p(plan), _ptr(grid), _ptr(coeffs), _stream(stream)), "soft_forward")
+
+
+def soft_inverse(plan, coeffs, grid, stream=None):
+    _check(lib().soft_inverse(ctypes.c_void_p(plan), _ptr(coeffs), _ptr(grid), _stream(stream)), "soft_inverse")
+
+
+def soft_adjoint(plan, coeffs, grid, stream=None):
+    _check(lib().soft_adjoint(ctypes.c_void_p(plan), _ptr(coeffs), _ptr(grid), _stream(stream)), "soft_adjoint")
+
+
+def soft_adjoint_inverse(plan, grid, coeffs, stream=None):
+    _check(lib().soft_adjoint_inverse(ctypes.c_void_p(plan), _ptr(grid), _ptr(coeffs), _stream(stream)),
+           "soft_adjoint_inverse")
+
+
+def soft_plan_destroy(plan):
+    _check(lib().soft_plan_destroy(ctypes.c_void_p(plan)), "soft_plan_destroy")
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+
+def num_coeffs(B):
+    return B * (4 * B * B - 1) // 3
+
+
+class Plan:
+    """A plan for ``batch`` SO(3) transforms of bandwidth ``B`` on one device.
+
+    Grids are complex128 tensors of shape [batch, 2B, 2B, 2B] (or [2B, 2B, 2B]
+    when batch == 1); coefficient vectors are [batch, B(4B^2-1)/3] (or flat).
+    Calls are asynchronous on the current torch stream.
+    """
+
+    def __init__(self, B, batch=1, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.handle = soft_plan(B, batch, SOFT_FP64, 0)
+        self.B, self.batch, self.N = B, batch, 2 * B
+        self.nc = num_coeffs(B)
+
+    # shapes -------------------------------------------------------------
+    def grid_shape(self):
+        N = self.N
+        return (N, N, N) if self.batch == 1 else (self.batch, N, N, N)
+
+    def coeff_shape(self):
+        return (self.nc,) if self.batch == 1 else (self.batch, self.nc)
+
+    def _checked(self, t, shape, what):
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{what} must be a tensor on {self.device}")
+        if t.dtype != torch.complex128:
+            raise ValueError(f"{what} must be complex128, got {t.dtype}")
+        if t.numel() != int(torch.Size(shape).numel()):
+            raise ValueError(f"{what} has {t.numel()} elements, expected shape {shape}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return t
+
+    def _out(self, out, shape, what):
+        if out is None:
+            return torch.empty(shape, dtype=torch.complex128, device=self.device)
+        return self._checked(out, shape, what)
+
+    # transforms -----------------------------------------------------------
+    def forward(self, grid, out=None):
+        """FSOFT: coefficients of the sampled function(s)."""
+        g = self._checked(grid, self.grid_shape(), "grid")
+        c = self._out(out, self.coeff_shape(), "out")
+        soft_forward(self.handle, g, c)
+        return c
+
+    def inverse(self, coeffs, out=None):
+        """iFSOFT: grid samples of the band-limited function(s)."""
+        c = self._checked(coeffs, self.coeff_shape(), "coeffs")
+        g = self._out(out, self.grid_shape(), "out")
+        soft_inverse(self.handle, c, g)
+        return g
+
+    def adjoint(self, coeffs, out=None):
+        """F^H = W I V, adjoint of forward."""
+        c = self._checked(coeffs, self.coeff_shape(), "coeffs")
+        g = self._out(out, self.grid_shape(), "out")
+        soft_adjoint(self.handle, c, g)
+        return g
+
+    def adjoint_inverse(self, grid, out=None):
+        """I^H = V^-1 F W^-1, adjoint of inverse."""
+        g = self._checked(grid, self.grid_shape(), "grid")
+        c = self._out(out, self.coeff_shape(), "out")
+        soft_adjoint_inverse(self.handle, g, c)
+        return c
+
+    def workspace_bytes(self):
+        return soft_plan_sizes(self.handle)[2]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            soft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,59 @@
+"""The C-ABI library loads, exports every symbol include/soft.h declares, and
+rejects bad arguments before touching a GPU (CPU-only checks)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "soft.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(soft_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1808_00896_amd import soft
+    return soft.lib()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("soft_plan", "soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse",
+              "soft_plan_destroy", "soft_plan_sizes", "soft_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    from paper_1808_00896_amd import soft
+    assert soft.status_string(0) == "ok"
+    assert "invalid" in soft.status_string(-1)
+    assert "unsupported" in soft.status_string(-2)
+    assert soft.status_string(12345) == "unknown status"
+
+
+def test_argument_errors_need_no_gpu(L):
+    from paper_1808_00896_amd import soft
+    h = ctypes.c_void_p()
+    assert L.soft_plan(0, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 1, 0, 1, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 1, 7, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 1, 0, 0, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(6, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert L.soft_plan(1024, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert h.value is None
+    for name in ("soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse"):
+        assert getattr(L, name)(None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_sizes(None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_destroy(None) == soft.SOFT_OK

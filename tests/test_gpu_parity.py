@@ -1,0 +1,118 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bar: max |x - x_oracle| / max |x_oracle| over all outputs
+  * <= 1e-11 in FP64 for B <= 256 (against the double oracle),
+  * <= 1e-9 at B = 512 (against the long-double oracle, sampled).
+Inputs are seeded synthetic data from paper_1808_00896_amd.inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1808_00896_amd import inputs
+from paper_1808_00896_amd import soft
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def relerr(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(dev)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("B", [1, 2, 4, 8, 16, 32, 64])
+def test_inverse_matches_oracle(oracle, dev, B):
+    c = inputs.coeffs_uniform(B, 10 + B)
+    with soft.Plan(B) as p:
+        g = to_host(p.inverse(to_dev(c, dev)))
+    want = oracle.inverse(B, c)
+    assert relerr(g, want) <= TOL64
+
+
+@pytest.mark.parametrize("B", [1, 2, 4, 8, 16, 32, 64])
+def test_forward_matches_oracle(oracle, dev, B):
+    """Forward on a random, not band-limited grid: the quadrature sum itself."""
+    g = inputs.grid_random(B, 20 + B)
+    with soft.Plan(B) as p:
+        c = to_host(p.forward(to_dev(g, dev)))
+    want = oracle.forward(B, g)
+    assert relerr(c, want) <= TOL64
+
+
+@pytest.mark.parametrize("B", [2, 8, 32])
+def test_adjoints_match_oracle(oracle, dev, B):
+    c = inputs.coeffs_uniform(B, 30 + B)
+    g = inputs.grid_random(B, 40 + B)
+    with soft.Plan(B) as p:
+        ga = to_host(p.adjoint(to_dev(c, dev)))
+        ci = to_host(p.adjoint_inverse(to_dev(g, dev)))
+    assert relerr(ga, oracle.adjoint(B, c)) <= TOL64
+    assert relerr(ci, oracle.adjoint_inverse(B, g)) <= TOL64
+
+
+def test_round_trip_B16(oracle, dev):
+    """Round trip of uniform[-1, 1] coefficients at B = 16 (inverse, then forward)."""
+    B = 16
+    c = inputs.coeffs_uniform(B, 0)
+    with soft.Plan(B) as p:
+        g = p.inverse(to_dev(c, dev))
+        c2 = to_host(p.forward(g))
+        g = to_host(g)
+    assert relerr(g, oracle.inverse(B, c)) <= TOL64
+    assert relerr(c2, c) <= TOL64
+
+
+def test_batched_plan(oracle, dev):
+    B, n = 16, 3
+    cs = [inputs.coeffs_decay(B, 50 + i) for i in range(n)]
+    with soft.Plan(B, batch=n) as p:
+        g = p.inverse(to_dev(np.stack(cs), dev))
+        c2 = to_host(p.forward(g))
+        g = to_host(g)
+    for i in range(n):
+        assert relerr(g[i], oracle.inverse(B, cs[i])) <= TOL64
+        assert relerr(c2[i], cs[i]) <= TOL64
+
+
+def test_deterministic(dev):
+    B = 32
+    c = to_dev(inputs.coeffs_decay(B, 60), dev)
+    with soft.Plan(B) as p:
+        g1 = p.inverse(c).clone()
+        g2 = p.inverse(c)
+        c1 = p.forward(g1).clone()
+        c2 = p.forward(g2)
+        torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(c1, c2)
+
+
+def test_B128_full(oracle, dev):
+    """Full comparison at B = 128 (256^3 grid), the spec bandwidth."""
+    B = 128
+    c = inputs.coeffs_decay(B, 1)
+    with soft.Plan(B) as p:
+        gd = p.inverse(to_dev(c, dev))
+        cd = to_host(p.forward(gd))
+        g = to_host(gd)
+    want_g = oracle.inverse(B, c)
+    assert relerr(g, want_g) <= TOL64
+    want_c = oracle.forward(B, want_g)
+    assert relerr(cd, want_c) <= TOL64
+    assert relerr(cd, c) <= TOL64
