@@ -126,6 +126,45 @@ int soft_adjoint(soft_plan_t plan, const void *coeffs, void *grid, hipStream_t s
 int soft_adjoint_inverse(soft_plan_t plan, const void *grid, void *coeffs, hipStream_t stream);
 
 /*
+ * Stage timing (measurement support).  When enabled, every transform call
+ * records a HIP event on its stream before and after each kernel it enqueues;
+ * soft_plan_stage_times() waits for the recorded events and returns, per
+ * stage, the summed elapsed milliseconds and the number of launches timed.
+ * Stages (SOFT_STAGE_*):
+ *   0 gamma FFT (forward)     1 alpha FFT + weights (forward)
+ *   2 DWT (forward)           3 group-major -> l-major reorder
+ *   4 l-major -> group-major  5 iDWT
+ *   6 alpha FFT (inverse)     7 gamma FFT (inverse)
+ */
+enum {
+    SOFT_STAGE_FFT_GAMMA_FWD = 0,
+    SOFT_STAGE_FFT_ALPHA_FWD = 1,
+    SOFT_STAGE_DWT_FWD = 2,
+    SOFT_STAGE_REORDER_FWD = 3,
+    SOFT_STAGE_REORDER_INV = 4,
+    SOFT_STAGE_DWT_INV = 5,
+    SOFT_STAGE_FFT_ALPHA_INV = 6,
+    SOFT_STAGE_FFT_GAMMA_INV = 7,
+    SOFT_NUM_STAGES = 8
+};
+
+/*
+ * soft_plan_set_timing -- enable (1) or disable (0) stage timing for later
+ * calls on this plan.  Returns SOFT_OK or SOFT_ERR_INVALID.
+ */
+int soft_plan_set_timing(soft_plan_t plan, int enable);
+
+/*
+ * soft_plan_stage_times -- wait for all recorded stage events of this plan,
+ * add their durations to the plan's totals and copy the totals out:
+ * ms[s] = summed milliseconds, launches[s] = number of timed launches, for
+ * s < SOFT_NUM_STAGES (either pointer may be NULL).  reset != 0 clears the
+ * totals afterwards.  Blocks the host until the recorded work has run.
+ * Returns SOFT_OK, SOFT_ERR_INVALID or SOFT_ERR_HIP.
+ */
+int soft_plan_stage_times(soft_plan_t plan, double *ms, long long *launches, int reset);
+
+/*
  * soft_plan_destroy -- release the plan's device memory.  Synchronises the
  * device first so no enqueued work still uses the workspace.  NULL is
  * accepted and ignored.  Returns SOFT_OK or SOFT_ERR_HIP.

@@ -25,6 +25,16 @@ struct soft_plan_s {
     void *tables = nullptr;
     double2 *S = nullptr, *t1 = nullptr, *Cg = nullptr;
     size_t ws_bytes = 0;
+    // stage timing
+    struct Pending {
+        int stage;
+        hipEvent_t start, end;
+    };
+    bool timing = false;
+    std::vector<hipEvent_t> free_events, used_events;
+    std::vector<Pending> pending;
+    double stage_ms[SOFT_NUM_STAGES] = {};
+    long long stage_n[SOFT_NUM_STAGES] = {};
 };
 
 namespace {
@@ -36,6 +46,8 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 void free_plan(soft_plan_s *p) {
     if (!p) return;
+    for (hipEvent_t e : p->free_events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->used_events) (void)hipEventDestroy(e);
     if (p->tables) (void)hipFree(p->tables);
     if (p->S) (void)hipFree(p->S);
     if (p->t1) (void)hipFree(p->t1);
@@ -148,17 +160,57 @@ int check_call(soft_plan_t plan, const void *a, const void *b) {
     return SOFT_OK;
 }
 
+// Records one HIP event between consecutive kernels of a call when the plan
+// has timing enabled; stage s spans the events around its kernel.
+class StageClock {
+  public:
+    StageClock(soft_plan_s *p, hipStream_t s) : p_(p), s_(s) {}
+    hipError_t start() { return p_->timing ? record(&prev_) : hipSuccess; }
+    hipError_t lap(int stage) {
+        if (!p_->timing) return hipSuccess;
+        hipEvent_t e;
+        const hipError_t r = record(&e);
+        if (r == hipSuccess) p_->pending.push_back({stage, prev_, e});
+        prev_ = e;
+        return r;
+    }
+
+  private:
+    hipError_t record(hipEvent_t *out) {
+        hipEvent_t e;
+        if (!p_->free_events.empty()) {
+            e = p_->free_events.back();
+            p_->free_events.pop_back();
+        } else {
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        p_->used_events.push_back(e);
+        *out = e;
+        return hipEventRecord(e, s_);
+    }
+    soft_plan_s *p_;
+    hipStream_t s_;
+    hipEvent_t prev_ = nullptr;
+};
+
 // Forward-type transform: FFT (gamma, then alpha with optional W), DWT,
 // reorder (optional V).  soft_forward uses W and V; soft_adjoint_inverse
 // uses neither.
 int run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bool scaled) {
     const int rc = check_call(p, grid, coeffs);
     if (rc != SOFT_OK) return rc;
-    hipError_t e = soft::launch_fft_gamma_fwd(p->view, p->batch, static_cast<const double2 *>(grid), p->t1, s);
+    StageClock clk(p, s);
+    hipError_t e = clk.start();
+    if (e == hipSuccess) e = soft::launch_fft_gamma_fwd(p->view, p->batch, static_cast<const double2 *>(grid), p->t1, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_FWD);
     if (e == hipSuccess) e = soft::launch_fft_alpha_fwd(p->view, p->batch, p->t1, p->S, scaled, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_FWD);
     if (e == hipSuccess) e = soft::launch_dwt_fwd(p->view, p->batch, p->S, p->Cg, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
     if (e == hipSuccess)
         e = soft::launch_reorder_fwd(p->view, p->batch, p->Cg, static_cast<double2 *>(coeffs), scaled, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_REORDER_FWD);
     return hip_status(e);
 }
 
@@ -167,12 +219,18 @@ int run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bo
 int run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bool scaled) {
     const int rc = check_call(p, coeffs, grid);
     if (rc != SOFT_OK) return rc;
-    hipError_t e =
-        soft::launch_reorder_inv(p->view, p->batch, static_cast<const double2 *>(coeffs), p->Cg, scaled, s);
+    StageClock clk(p, s);
+    hipError_t e = clk.start();
+    if (e == hipSuccess)
+        e = soft::launch_reorder_inv(p->view, p->batch, static_cast<const double2 *>(coeffs), p->Cg, scaled, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_REORDER_INV);
     if (e == hipSuccess) e = soft::launch_dwt_inv(p->view, p->batch, p->Cg, p->S, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
     if (e == hipSuccess) e = soft::launch_fft_alpha_inv(p->view, p->batch, p->S, p->t1, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_INV);
     if (e == hipSuccess)
         e = soft::launch_fft_gamma_inv(p->view, p->batch, p->t1, static_cast<double2 *>(grid), scaled, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_INV);
     return hip_status(e);
 }
 
@@ -260,6 +318,40 @@ int soft_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s) {
 
 int soft_adjoint(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s) {
     return run_inverse(p, coeffs, grid, s, true);
+}
+
+int soft_plan_set_timing(soft_plan_t p, int enable) {
+    if (!p) return SOFT_ERR_INVALID;
+    p->timing = enable != 0;
+    return SOFT_OK;
+}
+
+int soft_plan_stage_times(soft_plan_t p, double *ms, long long *launches, int reset) {
+    if (!p) return SOFT_ERR_INVALID;
+    hipError_t err = hipSuccess;
+    for (const auto &r : p->pending) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.end);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.end);
+        if (e != hipSuccess) {
+            err = e;
+            continue;
+        }
+        p->stage_ms[r.stage] += t;
+        p->stage_n[r.stage] += 1;
+    }
+    p->pending.clear();
+    p->free_events.insert(p->free_events.end(), p->used_events.begin(), p->used_events.end());
+    p->used_events.clear();
+    for (int i = 0; i < SOFT_NUM_STAGES; ++i) {
+        if (ms) ms[i] = p->stage_ms[i];
+        if (launches) launches[i] = p->stage_n[i];
+        if (reset) {
+            p->stage_ms[i] = 0.0;
+            p->stage_n[i] = 0;
+        }
+    }
+    return hip_status(err);
 }
 
 int soft_plan_destroy(soft_plan_t p) {

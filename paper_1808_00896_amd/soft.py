@@ -47,10 +47,14 @@ def lib():
         for name in ("soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse"):
             getattr(L, name).argtypes = [vp, vp, vp, vp]
         L.soft_plan_destroy.argtypes = [vp]
+        L.soft_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.soft_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
         for name in ("soft_plan", "soft_plan_sizes", "soft_forward", "soft_inverse", "soft_adjoint",
-                     "soft_adjoint_inverse", "soft_plan_destroy"):
+                     "soft_adjoint_inverse", "soft_plan_destroy", "soft_plan_set_timing",
+                     "soft_plan_stage_times"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -109,6 +113,22 @@ def soft_adjoint(plan, coeffs, grid, stream=None):
 def soft_adjoint_inverse(plan, grid, coeffs, stream=None):
     _check(lib().soft_adjoint_inverse(ctypes.c_void_p(plan), _ptr(grid), _ptr(coeffs), _stream(stream)),
            "soft_adjoint_inverse")
+
+
+STAGES = ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "reorder_fwd",
+          "reorder_inv", "dwt_inv", "fft_alpha_inv", "fft_gamma_inv")
+
+
+def soft_plan_set_timing(plan, enable):
+    _check(lib().soft_plan_set_timing(ctypes.c_void_p(plan), int(bool(enable))), "soft_plan_set_timing")
+
+
+def soft_plan_stage_times(plan, reset=False):
+    """{stage name: (total ms, launches)} of the HIP-event stage timers."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_longlong * len(STAGES))()
+    _check(lib().soft_plan_stage_times(ctypes.c_void_p(plan), ms, n, int(bool(reset))), "soft_plan_stage_times")
+    return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
 
 
 def soft_plan_destroy(plan):
