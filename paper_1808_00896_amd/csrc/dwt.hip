@@ -61,22 +61,41 @@ __device__ __forceinline__ double seed_d(const PlanView &p, int g, int m, int mp
     return exp(s2.hi) * (1.0 + lo);  // exp(hi + lo) to O(lo^2), |lo| < 1e-12
 }
 
-// Recurrence coefficients of eq. "Wigner_d_recurrence" for l = l0 .. B-2:
-//   d(l+1) = (A x - C) d(l) - Bc d(l-1),
-//   A = (l+1)(2l+1)/sqrt(((l+1)^2-m^2)((l+1)^2-m'^2)), C = A m m'/(l(l+1)),
-//   Bc = (l+1) sqrt((l^2-m^2)(l^2-m'^2)) / (l sqrt(((l+1)^2-m^2)((l+1)^2-m'^2))),
-// with C = 0 at l = 0 and Bc = 0 at l = l0 (the d(l0-1) term vanishes).
-__device__ __forceinline__ void fill_coefs(int m, int mp, int B, double *cA, double *cC, double *cB, int nthreads) {
-    const int l0 = m;
+// Rescaled three-term recurrence.  Eq. "Wigner_d_recurrence" reads, for the
+// representative (m, m') and l >= l0,
+//   d(l+1) = (A_l x - C_l) d(l) - Bc_l d(l-1),
+//   A_l = (l+1)(2l+1)/sqrt(((l+1)^2-m^2)((l+1)^2-m'^2)),  C_l = A_l m m'/(l(l+1)),
+//   Bc_l = (l+1) sqrt((l^2-m^2)(l^2-m'^2)) / (l sqrt(((l+1)^2-m^2)((l+1)^2-m'^2))),
+// with C_0 = 0 and Bc_{l0} = 0 (the d(l0-1) term vanishes).  Writing
+// d(l) = s_l e(l) with s_{l0} = s_{l0+1} = 1 and s_{l+1} = Bc_l s_{l-1} turns it
+// into e(l+1) = (alpha_l x - gamma_l) e(l) - e(l-1), alpha_l = A_l s_l/s_{l+1},
+// gamma_l = C_l s_l/s_{l+1}: two FMAs per step and two coefficients.  The
+// kernels run e; the reorder passes apply s_l.  Row goff[g] + (l - l0) of the
+// table holds (alpha_l, gamma_l) and s_l; one thread per group fills it
+// (s is a running product).
+__global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__restrict__ rec,
+                                                        double *__restrict__ rscale) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= p.G) return;
+    const GroupInfo gi = p.grp[g];
+    const int m = gi.m, mp = gi.mp, l0 = m;
     const double M2 = (double)m * m, MP2 = (double)mp * mp, MMP = (double)m * mp;
-    for (int t = threadIdx.x; t < B - l0; t += nthreads) {
+    double2 *row = rec + p.goff[g];
+    double *srow = rscale + p.goff[g];
+    double s_prev = 0.0, s_cur = 1.0;  // s_{l-1}, s_l
+    for (int t = 0; t < p.B - l0; ++t) {
         const int l = l0 + t;
         const double L = l, L1 = l + 1;
         const double den = sqrt((L1 * L1 - M2) * (L1 * L1 - MP2));
         const double A = L1 * (2.0 * L + 1.0) / den;
-        cA[t] = A;
-        cC[t] = l > 0 ? A * (MMP / (L * L1)) : 0.0;
-        cB[t] = l > l0 ? L1 * sqrt((L * L - M2) * (L * L - MP2)) / (L * den) : 0.0;
+        const double C = l > 0 ? A * (MMP / (L * L1)) : 0.0;
+        const double Bc = l > l0 ? L1 * sqrt((L * L - M2) * (L * L - MP2)) / (L * den) : 0.0;
+        const double s_next = t == 0 ? 1.0 : Bc * s_prev;
+        const double r = s_cur / s_next;
+        row[t] = make_double2(A * r, C * r);
+        srow[t] = s_cur;
+        s_prev = s_cur;
+        s_cur = s_next;
     }
 }
 
@@ -85,29 +104,35 @@ __device__ __forceinline__ void fill_coefs(int m, int mp, int B, double *cA, dou
 // ---------------------------------------------------------------------------
 // Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
 // into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds
-// d(l0 + lp + r; b_j) for j-local jl; its LDS index is swizzled so that both
-// the per-lane row writes and the MFMA A-operand reads are conflict-free.
+// e(l0 + lp + r; b_j) for j-local jl in the wave's own LDS region; its index
+// is swizzled so that both the per-lane row writes and the MFMA A-operand
+// reads are conflict-free.  A wave's LDS operations complete in order, so the
+// panel needs no block barrier; the only barrier per panel is the one before
+// the cross-wave sum, whose buffer alternates between two halves.  The
+// recurrence coefficients of a panel (16 x (alpha, gamma)) sit in scalar
+// registers; the next panel's are loaded before the MFMA phase, which hides
+// their latency.  Four accumulators keep four MFMA chains in flight.
 __device__ __forceinline__ int panel_idx(int jl, int r) { return jl * 16 + (r ^ ((jl >> 1) & 15)); }
 
 template <int NW, int NSUB>
-__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *__restrict__ S,
-                                                    double2 *__restrict__ Cg) {
-    __shared__ double cA[kMaxB], cC[kMaxB], cB[kMaxB];
+__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *__restrict__ rec,
+                                                    const double2 *__restrict__ S, double2 *__restrict__ Cg) {
     __shared__ double panel[NW][64 * 16];
+    __shared__ double red[2][NW][256];
     const int g = blockIdx.x;
     const GroupInfo gi = p.grp[g];
-    const int B = p.B, N = p.N;
+    const int N = p.N;
     const int m = gi.m, mp = gi.mp;
-    const int L = B - m;
+    const int L = p.B - m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    fill_coefs(m, mp, B, cA, cC, cB, NW * 64);
+    const double2 *__restrict__ R = rec + p.goff[g];
 
     const double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
     // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
     const int col = lane & 15, krow = lane >> 4;
     const bool col_present = (gi.mask >> (col >> 1)) & 1;
     double xb[NSUB][16];
-    double x[NSUB], dcur[NSUB], dprev[NSUB];
+    double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int jbase = (wave * NSUB + h) * 64;
@@ -124,103 +149,112 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
         const int j = jbase + lane;
         if (j < N) {
             x[h] = p.cosb[j];
-            dcur[h] = seed_d(p, g, m, mp, j);
+            ecur[h] = seed_d(p, g, m, mp, j);
         } else {
             x[h] = 0.0;
-            dcur[h] = 0.0;
+            ecur[h] = 0.0;
         }
-        dprev[h] = 0.0;
+        eprev[h] = 0.0;
     }
-    __syncthreads();
+
+    double2 c[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[r] = R[r];  // the table is padded past the last group
 
     double *pan = panel[wave];
-    double *red = &panel[0][0];
     double *out = reinterpret_cast<double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
-    for (int lp = 0; lp < L; lp += 16) {
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
+    int buf = 0;
+    for (int lp = 0; lp < L; lp += 16, buf ^= 1) {
+        v4d acc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int li = lp + r;
-                pan[panel_idx(lane, r)] = li < L ? dcur[h] : 0.0;
-                if (li + 1 < L) {
-                    const double u = fma(cA[li], x[h], -cC[li]);
-                    const double dn = fma(u, dcur[h], -cB[li] * dprev[h]);
-                    dprev[h] = dcur[h];
-                    dcur[h] = dn;
-                }
+                pan[panel_idx(lane, r)] = lp + r < L ? ecur[h] : 0.0;
+                const double u = fma(c[r].x, x[h], -c[r].y);
+                const double en = fma(u, ecur[h], -eprev[h]);
+                eprev[h] = ecur[h];
+                ecur[h] = en;
             }
-            __syncthreads();
+            if (h == NSUB - 1) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) c[r] = R[lp + 16 + r];
+            }
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const double a = pan[panel_idx(4 * s + krow, col)];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[h][s], acc, 0, 0, 0);
+                acc[s & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[h][s], acc[s & 3], 0, 0, 0);
             }
-            __syncthreads();
         }
-        // Sum the NW partial tiles.  For the FP64 16x16x4 MFMA, register r of
-        // lane holds C[lane/16 + 4 r][lane%16].
+        const v4d tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        // For the FP64 16x16x4 MFMA, register r of lane holds C[lane/16 + 4 r][lane%16].
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[wave * 256 + (krow + 4 * r) * 16 + col] = acc[r];
+        for (int r = 0; r < 4; ++r) red[buf][wave][(krow + 4 * r) * 16 + col] = tot[r];
         __syncthreads();
         for (int t = threadIdx.x; t < 256; t += NW * 64) {
             double sum = 0.0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) sum += red[w * 256 + t];
+            for (int w = 0; w < NW; ++w) sum += red[buf][w][t];
             const int row = t >> 4;
             if (lp + row < L) out[(size_t)(lp + row) * 16 + (t & 15)] = sum;
         }
-        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Inverse DWT: per-lane FMA chains, coefficients broadcast.
 // ---------------------------------------------------------------------------
+// Lane owns JPL beta samples.  The group's coefficient rows (already scaled by
+// s_l) and the recurrence coefficients are wave-uniform and arrive through
+// scalar loads issued one degree ahead of their use.
 template <int NW, int JPL>
-__global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *__restrict__ Cg,
-                                                    double2 *__restrict__ S) {
-    __shared__ double cA[kMaxB], cC[kMaxB], cB[kMaxB];
+__global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *__restrict__ rec,
+                                                    const double2 *__restrict__ Cg, double2 *__restrict__ S) {
     const int g = blockIdx.x;
     const GroupInfo gi = p.grp[g];
-    const int B = p.B, N = p.N;
+    const int N = p.N;
     const int m = gi.m, mp = gi.mp;
-    const int L = B - m;
-    fill_coefs(m, mp, B, cA, cC, cB, NW * 64);
+    const int L = p.B - m;
+    const double2 *__restrict__ R = rec + p.goff[g];
+    const double *__restrict__ F =
+        reinterpret_cast<const double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
 
-    double x[JPL], dcur[JPL], dprev[JPL], acc[JPL][16];
+    double x[JPL], ecur[JPL], eprev[JPL], acc[JPL][16];
 #pragma unroll
     for (int h = 0; h < JPL; ++h) {
         const int j = threadIdx.x + h * NW * 64;
         x[h] = j < N ? p.cosb[j] : 0.0;
-        dcur[h] = j < N ? seed_d(p, g, m, mp, j) : 0.0;
-        dprev[h] = 0.0;
+        ecur[h] = j < N ? seed_d(p, g, m, mp, j) : 0.0;
+        eprev[h] = 0.0;
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[h][c] = 0.0;
     }
-    __syncthreads();
 
-    const double *__restrict__ F =
-        reinterpret_cast<const double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
+    double f[16];
+    double2 rc = R[0];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) f[c] = F[c];
     for (int li = 0; li < L; ++li) {
-        double f[16];
+        // Next degree's operands (rows past the group's end are padding or the
+        // next group's and are never used).
+        double fn[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) f[c] = F[(size_t)li * 16 + c];
+        for (int c = 0; c < 16; ++c) fn[c] = F[(size_t)(li + 1) * 16 + c];
+        const double2 rn = R[li + 1];
 #pragma unroll
-        for (int h = 0; h < JPL; ++h)
+        for (int h = 0; h < JPL; ++h) {
 #pragma unroll
-            for (int c = 0; c < 16; ++c) acc[h][c] = fma(dcur[h], f[c], acc[h][c]);
-        if (li + 1 < L) {
-            const double a = cA[li], cc = cC[li], bb = cB[li];
-#pragma unroll
-            for (int h = 0; h < JPL; ++h) {
-                const double u = fma(a, x[h], -cc);
-                const double dn = fma(u, dcur[h], -bb * dprev[h]);
-                dprev[h] = dcur[h];
-                dcur[h] = dn;
-            }
+            for (int c = 0; c < 16; ++c) acc[h][c] = fma(ecur[h], f[c], acc[h][c]);
+            const double u = fma(rc.x, x[h], -rc.y);
+            const double en = fma(u, ecur[h], -eprev[h]);
+            eprev[h] = ecur[h];
+            ecur[h] = en;
         }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) f[c] = fn[c];
+        rc = rn;
     }
 
     double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
@@ -236,36 +270,42 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *
 
 }  // namespace
 
+hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_recurrence, dim3((p.G + 255) / 256), dim3(256), 0, s, p, rec, rscale);
+    return hipGetLastError();
+}
+
 hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *Cg, hipStream_t s) {
     if (p.B > kMaxB) return hipErrorInvalidValue;
     dim3 grid(p.G, batch);
     // waves x subsets of 64 j: N <= 64: 1x1; 128: 2x1; 256: 4x1; 512: 4x2; 1024: 8x2.
     if (p.N <= 64)
-        hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, p.rec, S, Cg);
     else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_fwd<2, 1>), grid, dim3(128), 0, s, p, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<2, 1>), grid, dim3(128), 0, s, p, p.rec, S, Cg);
     else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, p.rec, S, Cg);
     else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_fwd<4, 2>), grid, dim3(256), 0, s, p, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<4, 2>), grid, dim3(256), 0, s, p, p.rec, S, Cg);
     else
-        hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, p.rec, S, Cg);
     return hipGetLastError();
 }
 
 hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *Cg, double2 *S, hipStream_t s) {
     if (p.B > kMaxB) return hipErrorInvalidValue;
     dim3 grid(p.G, batch);
+    // waves x beta samples per lane: N <= 64: 1x1; 128: 1x2; 256: 1x4; 512: 2x4; 1024: 4x4.
     if (p.N <= 64)
-        hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, p.rec, Cg, S);
     else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_inv<2, 1>), grid, dim3(128), 0, s, p, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<1, 2>), grid, dim3(64), 0, s, p, p.rec, Cg, S);
     else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_inv<4, 1>), grid, dim3(256), 0, s, p, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<1, 4>), grid, dim3(64), 0, s, p, p.rec, Cg, S);
     else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_inv<4, 2>), grid, dim3(256), 0, s, p, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<2, 4>), grid, dim3(128), 0, s, p, p.rec, Cg, S);
     else
-        hipLaunchKernelGGL((k_dwt_inv<8, 2>), grid, dim3(512), 0, s, p, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<4, 4>), grid, dim3(256), 0, s, p, p.rec, Cg, S);
     return hipGetLastError();
 }
 

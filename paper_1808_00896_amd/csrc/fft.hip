@@ -34,18 +34,20 @@ __device__ __forceinline__ double2 cmul_si(double2 a) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// Sequences per block for a length-N transform: enough work for 256 threads,
-// at least 8 neighbours (128-byte runs) and never more than N.
-constexpr int tile_for(int N) {
+// Sequences per block for a length-N transform: enough work for the block's
+// threads, at least 8 neighbours (128-byte runs) and never more than N.
+constexpr int tile_for(int N, bool /*transposed_in*/) {
     return N < 8 ? N : (1024 / N > 8 ? (1024 / N < N ? 1024 / N : N) : 8);
 }
 
-constexpr int kThreads = 256;
+// 512 threads for the 1024-point transform (its LDS tile allows one block per
+// CU), 256 otherwise.
+constexpr int threads_for(int N) { return N >= 1024 ? 512 : 256; }
 
 // In-place Stockham FFT of T sequences of length N held in LDS (row stride
 // N + 1 complex), X[q] = sum_p x[p] e^{SIGN 2 pi i p q / N}; tw[k] is
 // e^{SIGN 2 pi i k / N}.  Starts and ends with all threads synchronised.
-template <int N, int T, int SIGN>
+template <int N, int T, int NT, int SIGN>
 __device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict__ tw) {
     constexpr int LOGN = ilog2(N);
     constexpr int S = N + 1;
@@ -53,12 +55,12 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict_
     int logNs = 0;
     if constexpr (LOGN & 1) {  // radix-2 stage with Ns = 1 (no twiddles)
         constexpr int NB = T * N / 2;
-        constexpr int PER = (NB + kThreads - 1) / kThreads;
+        constexpr int PER = (NB + NT - 1) / NT;
         double2 v[PER][2];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * kThreads;
-            if (NB % kThreads == 0 || b < NB) {
+            const int b = tid + q * NT;
+            if (NB % NT == 0 || b < NB) {
                 const int t = b / (N / 2), jj = b % (N / 2);
                 v[q][0] = buf[t * S + jj];
                 v[q][1] = buf[t * S + jj + N / 2];
@@ -67,8 +69,8 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict_
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * kThreads;
-            if (NB % kThreads == 0 || b < NB) {
+            const int b = tid + q * NT;
+            if (NB % NT == 0 || b < NB) {
                 const int t = b / (N / 2), jj = b % (N / 2);
                 buf[t * S + 2 * jj] = cadd(v[q][0], v[q][1]);
                 buf[t * S + 2 * jj + 1] = csub(v[q][0], v[q][1]);
@@ -80,14 +82,14 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict_
 #pragma unroll
     for (int st = 0; st < LOGN / 2; ++st) {  // radix-4 stages
         constexpr int NB = T * N / 4;
-        constexpr int PER = (NB + kThreads - 1) / kThreads;
+        constexpr int PER = (NB + NT - 1) / NT;
         const int Ns = 1 << logNs;
         const int twstep = N >> (2 + logNs);  // N / (4 Ns)
         double2 v[PER][4];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * kThreads;
-            if (NB % kThreads == 0 || b < NB) {
+            const int b = tid + q * NT;
+            if (NB % NT == 0 || b < NB) {
                 const int t = b / (N / 4), jj = b % (N / 4);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[q][r] = buf[t * S + jj + r * (N / 4)];
@@ -96,8 +98,8 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict_
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * kThreads;
-            if (NB % kThreads == 0 || b < NB) {
+            const int b = tid + q * NT;
+            if (NB % NT == 0 || b < NB) {
                 const int t = b / (N / 4), jj = b % (N / 4);
                 const int k = jj & (Ns - 1);
                 if (logNs > 0) {
@@ -123,9 +125,10 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict_
 // gamma pass, forward: grid[i][j][k] -> t1[q][j][i], FFT along k, e^{+i}.
 // Block (i-tile, j, batch); q = N/2 (the +-B bin) is not stored.
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_fft_gamma_fwd(PlanView p, const double2 *__restrict__ grid,
+__global__ __launch_bounds__(threads_for(N)) void k_fft_gamma_fwd(PlanView p, const double2 *__restrict__ grid,
                                                            double2 *__restrict__ t1) {
-    constexpr int T = tile_for(N);
+    constexpr int T = tile_for(N, false);
+    constexpr int NT = threads_for(N);
     constexpr int S = N + 1;
     __shared__ double2 buf[T * S];
     const int it = blockIdx.x, j = blockIdx.y;
@@ -133,14 +136,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_gamma_fwd(PlanView p, const do
     const double2 *g = grid + blockIdx.z * N3;
     double2 *o = t1 + blockIdx.z * N3;
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e / N, n = e % N;
         buf[t * S + n] = g[((size_t)(it * T + t) * N + j) * N + n];
     }
     __syncthreads();
-    fft_lds<N, T, +1>(buf, p.twp);
+    fft_lds<N, T, NT, +1>(buf, p.twp);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e % T, q = e / T;
         if (q != N / 2) o[((size_t)q * N + j) * N + it * T + t] = buf[t * S + q];
     }
@@ -150,9 +153,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_gamma_fwd(PlanView p, const do
 // times w_B(j) when apply_w; j' = N-1-j for members at pi - beta.
 // Block (j-tile, q != N/2, batch).
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_fft_alpha_fwd(PlanView p, const double2 *__restrict__ t1,
+__global__ __launch_bounds__(threads_for(N)) void k_fft_alpha_fwd(PlanView p, const double2 *__restrict__ t1,
                                                            double2 *__restrict__ Sout, int apply_w) {
-    constexpr int T = tile_for(N);
+    constexpr int T = tile_for(N, false);
+    constexpr int NT = threads_for(N);
     constexpr int S = N + 1;
     constexpr int B = N / 2;
     __shared__ double2 buf[T * S];
@@ -162,20 +166,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_alpha_fwd(PlanView p, const do
     const double2 *in = t1 + blockIdx.z * N3 + ((size_t)q * N + jt * T) * N;
     double2 *o = Sout + blockIdx.z * ((size_t)p.G * kSlots * N);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e / N, n = e % N;
         buf[t * S + n] = in[e];
     }
     __syncthreads();
-    fft_lds<N, T, +1>(buf, p.twp);
+    fft_lds<N, T, NT, +1>(buf, p.twp);
     const int mp = q < B ? q : q - N;
-    const int *srow = p.slot + (mp + B - 1);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e % T, pi = e / T;
         if (pi == B) continue;
         const int m = pi < B ? pi : pi - N;
-        const int sl = srow[(m + B - 1) * (2 * B - 1)];
+        const int sl = slot_code(m, mp);
         const int j = jt * T + t;
         const int jj = (sl & 1) ? N - 1 - j : j;
         double2 v = buf[t * S + pi];
@@ -190,9 +193,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_alpha_fwd(PlanView p, const do
 
 // alpha pass, inverse: S'[slot][j'] -> t1[q][j][i], FFT along m, e^{-i}.
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_fft_alpha_inv(PlanView p, const double2 *__restrict__ Sin,
+__global__ __launch_bounds__(threads_for(N)) void k_fft_alpha_inv(PlanView p, const double2 *__restrict__ Sin,
                                                            double2 *__restrict__ t1) {
-    constexpr int T = tile_for(N);
+    constexpr int T = tile_for(N, true);
+    constexpr int NT = threads_for(N);
     constexpr int S = N + 1;
     constexpr int B = N / 2;
     __shared__ double2 buf[T * S];
@@ -202,14 +206,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_alpha_inv(PlanView p, const do
     const double2 *in = Sin + blockIdx.z * ((size_t)p.G * kSlots * N);
     double2 *o = t1 + blockIdx.z * N3 + ((size_t)q * N + jt * T) * N;
     const int mp = q < B ? q : q - N;
-    const int *srow = p.slot + (mp + B - 1);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e % T, pi = e / T;
         double2 v = make_double2(0.0, 0.0);
         if (pi != B) {
             const int m = pi < B ? pi : pi - N;
-            const int sl = srow[(m + B - 1) * (2 * B - 1)];
+            const int sl = slot_code(m, mp);
             const int j = jt * T + t;
             const int jj = (sl & 1) ? N - 1 - j : j;
             v = in[(size_t)(sl >> 1) * N + jj];
@@ -217,9 +220,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_alpha_inv(PlanView p, const do
         buf[t * S + pi] = v;
     }
     __syncthreads();
-    fft_lds<N, T, -1>(buf, p.twm);
+    fft_lds<N, T, NT, -1>(buf, p.twm);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e / N, n = e % N;
         o[e] = buf[t * S + n];
     }
@@ -228,9 +231,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_alpha_inv(PlanView p, const do
 // gamma pass, inverse: t1[q][j][i] -> grid[i][j][k], FFT along m', e^{-i},
 // times w_B(j) when apply_w.  Block (i-tile, j, batch).
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_fft_gamma_inv(PlanView p, const double2 *__restrict__ t1,
+__global__ __launch_bounds__(threads_for(N)) void k_fft_gamma_inv(PlanView p, const double2 *__restrict__ t1,
                                                            double2 *__restrict__ grid, int apply_w) {
-    constexpr int T = tile_for(N);
+    constexpr int T = tile_for(N, true);
+    constexpr int NT = threads_for(N);
     constexpr int S = N + 1;
     __shared__ double2 buf[T * S];
     const int it = blockIdx.x, j = blockIdx.y;
@@ -238,15 +242,15 @@ __global__ __launch_bounds__(kThreads) void k_fft_gamma_inv(PlanView p, const do
     const double2 *in = t1 + blockIdx.z * N3;
     double2 *g = grid + blockIdx.z * N3;
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e % T, q = e / T;
         buf[t * S + q] = q == N / 2 ? make_double2(0.0, 0.0) : in[((size_t)q * N + j) * N + it * T + t];
     }
     __syncthreads();
-    fft_lds<N, T, -1>(buf, p.twm);
+    fft_lds<N, T, NT, -1>(buf, p.twm);
     const double wj = apply_w ? p.w[j] : 1.0;
 #pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += kThreads) {
+    for (int e = threadIdx.x; e < T * N; e += NT) {
         const int t = e / N, n = e % N;
         double2 v = buf[t * S + n];
         v.x *= wj;
@@ -274,8 +278,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_gamma_inv(PlanView p, const do
 
 hipError_t launch_fft_gamma_fwd(const PlanView &p, int batch, const double2 *grid, double2 *t1, hipStream_t s) {
     SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN), NN, batch);
-        hipLaunchKernelGGL(k_fft_gamma_fwd<NN>, g, dim3(kThreads), 0, s, p, grid, t1);
+        dim3 g(NN / tile_for(NN, false), NN, batch);
+        hipLaunchKernelGGL(k_fft_gamma_fwd<NN>, g, dim3(threads_for(NN)), 0, s, p, grid, t1);
     });
     return hipGetLastError();
 }
@@ -283,16 +287,16 @@ hipError_t launch_fft_gamma_fwd(const PlanView &p, int batch, const double2 *gri
 hipError_t launch_fft_alpha_fwd(const PlanView &p, int batch, const double2 *t1, double2 *S, bool apply_w,
                                 hipStream_t s) {
     SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN), NN - 1, batch);
-        hipLaunchKernelGGL(k_fft_alpha_fwd<NN>, g, dim3(kThreads), 0, s, p, t1, S, (int)apply_w);
+        dim3 g(NN / tile_for(NN, false), NN - 1, batch);
+        hipLaunchKernelGGL(k_fft_alpha_fwd<NN>, g, dim3(threads_for(NN)), 0, s, p, t1, S, (int)apply_w);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_fft_alpha_inv(const PlanView &p, int batch, const double2 *S, double2 *t1, hipStream_t s) {
     SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN), NN - 1, batch);
-        hipLaunchKernelGGL(k_fft_alpha_inv<NN>, g, dim3(kThreads), 0, s, p, S, t1);
+        dim3 g(NN / tile_for(NN, true), NN - 1, batch);
+        hipLaunchKernelGGL(k_fft_alpha_inv<NN>, g, dim3(threads_for(NN)), 0, s, p, S, t1);
     });
     return hipGetLastError();
 }
@@ -300,8 +304,8 @@ hipError_t launch_fft_alpha_inv(const PlanView &p, int batch, const double2 *S, 
 hipError_t launch_fft_gamma_inv(const PlanView &p, int batch, const double2 *t1, double2 *grid, bool apply_w,
                                 hipStream_t s) {
     SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN), NN, batch);
-        hipLaunchKernelGGL(k_fft_gamma_inv<NN>, g, dim3(kThreads), 0, s, p, t1, grid, (int)apply_w);
+        dim3 g(NN / tile_for(NN, true), NN, batch);
+        hipLaunchKernelGGL(k_fft_gamma_inv<NN>, g, dim3(threads_for(NN)), 0, s, p, t1, grid, (int)apply_w);
     });
     return hipGetLastError();
 }

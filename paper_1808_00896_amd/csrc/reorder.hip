@@ -5,6 +5,8 @@
 // l-major, f°(l,m,m') at l(4l^2-1)/3 + (m+l)(2l+1) + (m'+l).  This pass maps
 // between them and applies what the DWT left out:
 //   * the symmetry sign of each member (eq. "Wigner_symmetries"),
+//   * the scale s_l of the rescaled recurrence (the DWT kernels run
+//     e(l) = d(l)/s_l),
 //   * the factor (2l+1)/(8 pi B) of V_B (Sect. 2.4) when asked.
 // One block per group: reads of the group's rows are contiguous; each
 // coefficient is one 16-byte store (forward) or load (inverse).
@@ -46,6 +48,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder_fwd(PlanView p, const doub
     const int L = p.B - gi.m;
     const double2 *rows = Cg + (size_t)blockIdx.y * p.rows * kSlots + (size_t)p.goff[g] * kSlots;
     double2 *out = coeffs + (size_t)blockIdx.y * p.Nc;
+    const double *sl = p.rscale + p.goff[g];
     const double v0 = 1.0 / (8.0 * M_PI * (double)p.B);
     for (int e = threadIdx.x; e < L * kSlots; e += kThreads) {
         const int s = e & (kSlots - 1), li = e >> 3;
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder_fwd(PlanView p, const doub
         int mm, mmp;
         double sign;
         member(s, gi.m, gi.mp, l, mm, mmp, sign);
-        const double f = apply_v ? sign * (2.0 * l + 1.0) * v0 : sign;
+        const double f = (apply_v ? sign * (2.0 * l + 1.0) * v0 : sign) * sl[li];
         const double2 v = rows[e];
         out[coeff_index(l, mm, mmp)] = make_double2(v.x * f, v.y * f);
     }
@@ -67,6 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder_inv(PlanView p, const doub
     const int L = p.B - gi.m;
     double2 *rows = Cg + (size_t)blockIdx.y * p.rows * kSlots + (size_t)p.goff[g] * kSlots;
     const double2 *in = coeffs + (size_t)blockIdx.y * p.Nc;
+    const double *sl = p.rscale + p.goff[g];
     const double v0 = 1.0 / (8.0 * M_PI * (double)p.B);
     for (int e = threadIdx.x; e < L * kSlots; e += kThreads) {
         const int s = e & (kSlots - 1), li = e >> 3;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder_inv(PlanView p, const doub
             int mm, mmp;
             double sign;
             member(s, gi.m, gi.mp, l, mm, mmp, sign);
-            const double f = apply_v ? sign * (2.0 * l + 1.0) * v0 : sign;
+            const double f = (apply_v ? sign * (2.0 * l + 1.0) * v0 : sign) * sl[li];
             const double2 c = in[coeff_index(l, mm, mmp)];
             v = make_double2(c.x * f, c.y * f);
         }

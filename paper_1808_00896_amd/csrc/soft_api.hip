@@ -24,6 +24,8 @@ struct soft_plan_s {
     // device allocations
     void *tables = nullptr;
     double2 *S = nullptr, *t1 = nullptr, *Cg = nullptr;
+    double2 *rec = nullptr;
+    double *rscale = nullptr;
     size_t ws_bytes = 0;
     // stage timing
     struct Pending {
@@ -52,6 +54,8 @@ void free_plan(soft_plan_s *p) {
     if (p->S) (void)hipFree(p->S);
     if (p->t1) (void)hipFree(p->t1);
     if (p->Cg) (void)hipFree(p->Cg);
+    if (p->rec) (void)hipFree(p->rec);
+    if (p->rscale) (void)hipFree(p->rscale);
     delete p;
 }
 
@@ -144,8 +148,8 @@ int build_tables(soft_plan_s *p, std::vector<unsigned char> &host, TableLayout &
             }
         }
     }
-    for (int i = 0; i < P * P; ++i)
-        if (slot[i] < 0) return SOFT_ERR_INVALID;  // pair not covered
+    for (int i = 0; i < P * P; ++i)  // every pair covered, and by the kernels' slot_code
+        if (slot[i] < 0 || slot[i] != soft::slot_code(i / P - (B - 1), i % P - (B - 1))) return SOFT_ERR_INVALID;
     p->rows = row;
     return SOFT_OK;
 }
@@ -263,15 +267,19 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
     const size_t N = p->N;
     const size_t s_elems = (size_t)batch * p->G * kSlots * N;
     const size_t t1_elems = (size_t)batch * N * N * N;
-    const size_t cg_elems = (size_t)batch * p->rows * kSlots;
+    const size_t cg_elems = ((size_t)batch * p->rows + soft::kPadRows) * kSlots;
+    const size_t rec_rows = (size_t)p->rows + soft::kPadRows;
     if (hipMalloc(&p->tables, lay.total) != hipSuccess || hipMalloc(&p->S, s_elems * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->t1, t1_elems * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->Cg, cg_elems * sizeof(double2)) != hipSuccess) {
+        hipMalloc(&p->Cg, cg_elems * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         free_plan(p);
         return SOFT_ERR_OOM;
     }
-    p->ws_bytes = lay.total + (s_elems + t1_elems + cg_elems) * sizeof(double2);
+    p->ws_bytes = lay.total + (s_elems + t1_elems + cg_elems) * sizeof(double2) +
+                  rec_rows * (sizeof(double2) + sizeof(double));
     if (hipMemcpy(p->tables, host.data(), lay.total, hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(p);
         return SOFT_ERR_HIP;
@@ -292,6 +300,16 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
     v.slot = reinterpret_cast<const int *>(base + lay.slot);
     v.twp = reinterpret_cast<const double2 *>(base + lay.twp);
     v.twm = reinterpret_cast<const double2 *>(base + lay.twm);
+    v.rec = p->rec;
+    v.rscale = p->rscale;
+    // Padding rows are read (never used) by prefetches; give them defined values.
+    if (hipMemset(p->rec, 0, rec_rows * sizeof(double2)) != hipSuccess ||
+        hipMemset(p->rscale, 0, rec_rows * sizeof(double)) != hipSuccess ||
+        hipMemset(p->Cg, 0, cg_elems * sizeof(double2)) != hipSuccess ||
+        soft::launch_fill_recurrence(v, p->rec, p->rscale, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        free_plan(p);
+        return SOFT_ERR_HIP;
+    }
     *out = p;
     return SOFT_OK;
 }

@@ -27,6 +27,30 @@ namespace soft {
 // |m|, |m'| < B belongs to exactly one (group, slot).
 constexpr int kSlots = 8;
 
+// Rows of padding after the last group in the per-row tables and the
+// group-major coefficient buffer: the DWT kernels prefetch up to 32 rows past
+// a group's end (the values are never used).
+constexpr int kPadRows = 32;
+
+// Group slot code of order pair (m, m'), |m|, |m'| < B: (g*8 + s)*2 + (s >= 4)
+// with g = a(a+1)/2 + b for the representative a = max(|m|,|m'|),
+// b = min(|m|,|m'|) (groups ordered by a, then b) and s the member slot above.
+__host__ __device__ inline int slot_code(int m, int mp) {
+    const int am = m < 0 ? -m : m, amp = mp < 0 ? -mp : mp;
+    int a, b, s;
+    if (am >= amp) {
+        a = am;
+        b = amp;
+        s = m >= 0 ? (mp >= 0 ? 0 : 5) : (mp > 0 ? 4 : 1);
+    } else {
+        a = amp;
+        b = am;
+        s = mp > 0 ? (m >= 0 ? 2 : 6) : (m <= 0 ? 3 : 7);
+    }
+    const int g = a * (a + 1) / 2 + b;
+    return (g * kSlots + s) * 2 + (s >= 4 ? 1 : 0);
+}
+
 struct GroupInfo {
     int m, mp;     // representative, m >= mp >= 0; lowest degree l0 = m
     int mask;      // bit s set when slot s is present
@@ -45,6 +69,8 @@ struct PlanView {
     const GroupInfo *grp;  // [G]
     const long long *goff; // [G]   first row of group g in the group-major coefficients
     const int *slot;       // [(2B-1)^2] (g*8 + s)*2 + (s >= 4), indexed (m+B-1)(2B-1) + (m'+B-1)
+    const double2 *rec;    // [rows + kPadRows] rescaled recurrence coefficients (alpha_l, gamma_l)
+    const double *rscale;  // [rows + kPadRows] s_l, with d(l) = s_l e(l)
     const double2 *twp;    // [N]   e^{+2 pi i k/N}
     const double2 *twm;    // [N]   e^{-2 pi i k/N}
 };
@@ -56,6 +82,7 @@ hipError_t launch_fft_alpha_inv(const PlanView &p, int batch, const double2 *S, 
 hipError_t launch_fft_gamma_inv(const PlanView &p, int batch, const double2 *t1, double2 *grid, bool apply_w, hipStream_t s);
 
 // Discrete Wigner transform and its transpose (Sect. 2.4 matrix form).
+hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s);
 hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *Cg, hipStream_t s);
 hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *Cg, double2 *S, hipStream_t s);
 
