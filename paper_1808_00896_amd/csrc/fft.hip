@@ -8,14 +8,19 @@
 // Each direction is two HBM passes of batched 1-D FFTs over N points:
 //   gamma pass:  rows along k (contiguous) <-> t1[q][j][i]   (q = m' mod N)
 //   alpha pass:  rows along i (contiguous in t1) <-> S[group slot][j]
-// A block holds T independent length-N sequences in LDS and transforms them
-// with a Stockham autosort FFT (one radix-2 stage when log2 N is odd, then
-// radix-4 stages).  The T sequences are neighbours along the axis that is
-// contiguous in the *other* layout, so every global load and store moves
-// runs of >= T * 16 bytes: the transposes cost no extra HBM pass.  The forward
-// alpha pass also multiplies by the quadrature weight w_B(j) (the W_B factor
-// of the DWT) and writes members at pi - beta in reversed j order, so the DWT
-// sees every member of a symmetry group against the same d(l; b_j).
+// A block transforms T independent length-N sequences that are neighbours
+// along the axis contiguous in the *other* layout, so every global access
+// moves runs of T * 16 bytes and the transposes cost no extra HBM pass.  The
+// forward alpha pass multiplies by the quadrature weight w_B(j) (the W_B
+// factor of the DWT) and writes members at pi - beta in reversed j order, so
+// the DWT sees every member of a symmetry group against the same d(l; b_j).
+//
+// The FFT is a Stockham autosort decomposition N = R0 x 16 x 16 ... (R0 in
+// {1, 2, 4, 8}); every thread keeps 16 points in registers and runs its
+// radix-R butterflies there.  Stage 0 reads HBM directly and the last stage
+// writes HBM directly, with the lane order (row index fastest, or tile index
+// fastest) chosen per side so that both stay coalesced; only the exchanges
+// between stages go through LDS (one for N <= 512, two for N = 1024).
 #include "soft_internal.h"
 
 namespace soft {
@@ -26,288 +31,358 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// (SIGN i) * a
-template <int SIGN>
-__device__ __forceinline__ double2 cmul_si(double2 a) {
-    return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
-}
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// Sequences per block for a length-N transform: enough work for the block's
-// threads, at least 8 neighbours (128-byte runs) and never more than N.
-constexpr int tile_for(int N, bool /*transposed_in*/) {
-    return N < 8 ? N : (1024 / N > 8 ? (1024 / N < N ? 1024 / N : N) : 8);
+// cos and sin of 2 pi j / 16, j = 0..15, correctly rounded.
+__device__ constexpr double kCos16[16] = {
+    1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898,
+    0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
+    -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898,
+    0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
+__device__ constexpr double kSin16[16] = {
+    0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867,
+    1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898,
+    0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
+    -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+
+// a * e^{SIGN 2 pi i j / R} for a compile-time j and R | 16.
+template <int R, int J, int SIGN>
+__device__ __forceinline__ double2 twc(double2 a) {
+    constexpr int jj = (J % R) * (16 / R);
+    if constexpr (jj == 0) {
+        return a;
+    } else if constexpr (jj == 4) {
+        return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+    } else if constexpr (jj == 8) {
+        return make_double2(-a.x, -a.y);
+    } else if constexpr (jj == 12) {
+        return SIGN > 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+    } else {
+        const double c = kCos16[jj], s = SIGN * kSin16[jj];
+        return make_double2(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
 }
 
-// 512 threads for the 1024-point transform (its LDS tile allows one block per
-// CU), 256 otherwise.
-constexpr int threads_for(int N) { return N >= 1024 ? 512 : 256; }
+// In-register DFT of R points: X[k] = sum_n x[n] e^{SIGN 2 pi i n k / R}.
+template <int R, int SIGN>
+__device__ __forceinline__ void dft(double2 *v) {
+    if constexpr (R == 1) {
+        return;
+    } else if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const double2 a2 = cadd(v[1], v[3]), a3 = twc<4, 1, SIGN>(csub(v[1], v[3]));
+        v[0] = cadd(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[2] = csub(a0, a2);
+        v[3] = csub(a1, a3);
+    } else {
+        // R = 4 * Bq: n = Bq n1 + n2, k = k1 + 4 k2; inner DFT-4 over n1,
+        // twiddle e^{SIGN 2 pi i n2 k1 / R}, outer DFT-Bq over n2.
+        constexpr int A = 4, Bq = R / 4;
+        double2 y[Bq][A];
+#pragma unroll
+        for (int n2 = 0; n2 < Bq; ++n2) {
+            double2 a[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) a[n1] = v[Bq * n1 + n2];
+            dft<A, SIGN>(a);
+            y[n2][0] = a[0];
+            if (n2 == 0) {
+                y[0][1] = a[1];
+                y[0][2] = a[2];
+                y[0][3] = a[3];
+            } else if (n2 == 1) {
+                y[n2][1] = twc<R, 1, SIGN>(a[1]);
+                y[n2][2] = twc<R, 2, SIGN>(a[2]);
+                y[n2][3] = twc<R, 3, SIGN>(a[3]);
+            } else if (n2 == 2) {
+                y[n2][1] = twc<R, 2, SIGN>(a[1]);
+                y[n2][2] = twc<R, 4, SIGN>(a[2]);
+                y[n2][3] = twc<R, 6, SIGN>(a[3]);
+            } else {
+                y[n2][1] = twc<R, 3, SIGN>(a[1]);
+                y[n2][2] = twc<R, 6, SIGN>(a[2]);
+                y[n2][3] = twc<R, 9, SIGN>(a[3]);
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            double2 b[Bq];
+#pragma unroll
+            for (int n2 = 0; n2 < Bq; ++n2) b[n2] = y[n2][k1];
+            dft<Bq, SIGN>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < Bq; ++k2) v[k1 + A * k2] = b[k2];
+        }
+    }
+}
 
-// In-place Stockham FFT of T sequences of length N held in LDS (row stride
-// N + 1 complex), X[q] = sum_p x[p] e^{SIGN 2 pi i p q / N}; tw[k] is
-// e^{SIGN 2 pi i k / N}.  Starts and ends with all threads synchronised.
-template <int N, int T, int NT, int SIGN>
-__device__ __forceinline__ void fft_lds(double2 *buf, const double2 *__restrict__ tw) {
-    constexpr int LOGN = ilog2(N);
-    constexpr int S = N + 1;
+// Shape of the transform of length N: E points per thread, P threads per
+// sequence, T sequences per block, radix R0 of the first stage, NSTAGE stages.
+template <int N>
+struct Shape {
+    static constexpr int E = N >= 16 ? 16 : N;
+    static constexpr int P = N / E;
+    static constexpr int LOG = ilog2(N);
+    static constexpr int R0 = N >= 16 ? (1 << (LOG % 4)) : N;  // 1, 2, 4, 8 (or N when N < 16)
+    static constexpr int NSTAGE = N >= 16 ? LOG / 4 + (LOG % 4 ? 1 : 0) : 1;
+    // Neighbouring sequences per block: 32 for N <= 64, 16 up to 256, 8 at 512,
+    // 4 at 1024 (LDS ~ 70 KB, two blocks per CU); never more than N.
+    static constexpr int T0 = N <= 64 ? 32 : (N <= 256 ? 16 : (N == 512 ? 8 : 4));
+    static constexpr int T = T0 < N ? T0 : N;
+    static constexpr int NT = T * P;
+    static constexpr int RS = N + N / 16 + 1;  // LDS row stride (complex), padded
+    static constexpr int LDS = P > 1 ? T * RS : 1;
+};
+
+// Radix of stage s: R0 first (when the decomposition needs it), then 16s.
+template <int N, int S>
+constexpr int radix_of() {
+    if constexpr (N < 16) {
+        return N;
+    } else if constexpr (Shape<N>::R0 > 1) {
+        return S == 0 ? Shape<N>::R0 : 16;
+    } else {
+        return 16;
+    }
+}
+template <int N, int S>
+constexpr int ns_of() {  // product of the radices before stage S
+    if constexpr (S == 0) {
+        return 1;
+    } else {
+        return ns_of<N, S - 1>() * radix_of<N, S - 1>();
+    }
+}
+
+__device__ __forceinline__ int lds_pos(int t, int idx, int RS) { return t * RS + idx + (idx >> 4); }
+
+// Twiddle and butterfly all of a thread's radix-R butterflies of stage S.
+template <int N, int S, int SIGN>
+__device__ __forceinline__ void run_stage(double2 (&v)[Shape<N>::E], int p, const double2 *__restrict__ tw) {
+    constexpr int R = radix_of<N, S>(), NS = ns_of<N, S>();
+    constexpr int P = Shape<N>::P, BPT = N / R / P;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        if constexpr (NS > 1) {
+            const int b = p + k * P;
+            const int kk = b % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[k * R + r] = cmul(v[k * R + r], tw[kk * r * (N / (R * NS))]);
+        }
+        dft<R, SIGN>(&v[k * R]);
+    }
+}
+
+// Stage S outputs -> LDS (row t), element (b/NS)*NS*R + b%NS + r*NS.
+template <int N, int S>
+__device__ __forceinline__ void put_stage(const double2 (&v)[Shape<N>::E], double2 *lds, int t, int p) {
+    constexpr int R = radix_of<N, S>(), NS = ns_of<N, S>();
+    constexpr int P = Shape<N>::P, BPT = N / R / P, RS = Shape<N>::RS;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int b = p + k * P;
+        const int base = (b / NS) * NS * R + b % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_pos(t, base + r * NS, RS)] = v[k * R + r];
+    }
+}
+
+// Stage S inputs <- LDS (row t), element b + r*N/R.
+template <int N, int S>
+__device__ __forceinline__ void get_stage(double2 (&v)[Shape<N>::E], const double2 *lds, int t, int p) {
+    constexpr int R = radix_of<N, S>();
+    constexpr int P = Shape<N>::P, BPT = N / R / P, RS = Shape<N>::RS;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int b = p + k * P;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k * R + r] = lds[lds_pos(t, b + r * (N / R), RS)];
+    }
+}
+
+// Pass kinds: where a block's T sequences come from and go to.
+enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
+
+template <int KIND>
+constexpr bool transposed_in() { return KIND == ALPHA_INV || KIND == GAMMA_INV; }
+template <int KIND>
+constexpr bool transposed_out() { return KIND == GAMMA_FWD || KIND == ALPHA_FWD; }
+
+// Block -> (tile, line, batch).  Consecutive logical blocks are placed on the
+// same XCD (the hardware deals blocks round-robin over the 8 XCDs), so the two
+// halves of a 128-byte line touched by neighbouring tiles meet in one L2.
+struct BlockPos {
+    int tile, line, batch;
+};
+__device__ __forceinline__ BlockPos block_pos(int ntile, int nline) {
+    const int per_batch = ntile * nline;
+    int lin = blockIdx.x + gridDim.x * blockIdx.y;
+    if (per_batch % 8 == 0) lin = (lin % 8) * (per_batch / 8) + lin / 8;
+    return {lin % ntile, lin / ntile, (int)blockIdx.z};
+}
+
+// One pass.  Element addresses per kind:
+//   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out t1[(q*N + j)*N + i]
+//   ALPHA_FWD: block (j-tile, q): in t1[(q*N + j)*N + i],   out S[slot*N + j']
+//   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],         out t1[(q*N + j)*N + i]
+//   GAMMA_INV: block (i-tile, j): in t1[(q*N + j)*N + i],    out grid[(i*N + j)*N + k]
+template <int N, int KIND, int SIGN>
+__global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const double2 *__restrict__ in,
+                                                     double2 *__restrict__ out, int apply_w) {
+    using Sh = Shape<N>;
+    constexpr int T = Sh::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
+    constexpr int B = N / 2;
+    constexpr int LAST = NSTG - 1;
+    constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
+    __shared__ double2 lds[Sh::LDS];
+    const double2 *tw = SIGN > 0 ? p.twp : p.twm;
+
+    // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
+    const BlockPos bp = block_pos(N / T, ALPHA ? N - 1 : N);
+    const int tile = bp.tile;
+    const int line = ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line;
+    const size_t N3 = (size_t)N * N * N;
+    const size_t SB = (size_t)p.G * kSlots * N;
     const int tid = threadIdx.x;
-    int logNs = 0;
-    if constexpr (LOGN & 1) {  // radix-2 stage with Ns = 1 (no twiddles)
-        constexpr int NB = T * N / 2;
-        constexpr int PER = (NB + NT - 1) / NT;
-        double2 v[PER][2];
+    const int mp_line = line < B ? line : line - N;  // m' of an alpha-pass block
+
+    double2 v[E];
+    // ---- stage 0 inputs from HBM: element b + r*N/R ----
+    const int t_in = transposed_in<KIND>() ? tid % T : tid / P;
+    const int p_in = transposed_in<KIND>() ? tid / T : tid % P;
+    {
+        constexpr int R = radix_of<N, 0>(), BPT = N / R / P;
+        const int row = tile * T + t_in;  // i (gamma) or j (alpha)
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * NT;
-            if (NB % NT == 0 || b < NB) {
-                const int t = b / (N / 2), jj = b % (N / 2);
-                v[q][0] = buf[t * S + jj];
-                v[q][1] = buf[t * S + jj + N / 2];
-            }
-        }
-        __syncthreads();
+        for (int k = 0; k < BPT; ++k) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * NT;
-            if (NB % NT == 0 || b < NB) {
-                const int t = b / (N / 2), jj = b % (N / 2);
-                buf[t * S + 2 * jj] = cadd(v[q][0], v[q][1]);
-                buf[t * S + 2 * jj + 1] = csub(v[q][0], v[q][1]);
-            }
-        }
-        __syncthreads();
-        logNs = 1;
-    }
-#pragma unroll
-    for (int st = 0; st < LOGN / 2; ++st) {  // radix-4 stages
-        constexpr int NB = T * N / 4;
-        constexpr int PER = (NB + NT - 1) / NT;
-        const int Ns = 1 << logNs;
-        const int twstep = N >> (2 + logNs);  // N / (4 Ns)
-        double2 v[PER][4];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * NT;
-            if (NB % NT == 0 || b < NB) {
-                const int t = b / (N / 4), jj = b % (N / 4);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[q][r] = buf[t * S + jj + r * (N / 4)];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int b = tid + q * NT;
-            if (NB % NT == 0 || b < NB) {
-                const int t = b / (N / 4), jj = b % (N / 4);
-                const int k = jj & (Ns - 1);
-                if (logNs > 0) {
-#pragma unroll
-                    for (int r = 1; r < 4; ++r) v[q][r] = cmul(v[q][r], tw[k * r * twstep]);
+            for (int r = 0; r < R; ++r) {
+                const int n = p_in + k * P + r * (N / R);
+                double2 x;
+                if constexpr (KIND == GAMMA_FWD) {
+                    x = in[bp.batch * N3 + ((size_t)row * N + line) * N + n];
+                } else if constexpr (KIND == ALPHA_FWD) {
+                    x = in[bp.batch * N3 + ((size_t)line * N + row) * N + n];
+                } else if constexpr (KIND == ALPHA_INV) {
+                    if (n == B) {
+                        x = make_double2(0.0, 0.0);
+                    } else {
+                        const int sl = slot_code(n < B ? n : n - N, mp_line);
+                        const int jj = (sl & 1) ? N - 1 - row : row;
+                        x = in[bp.batch * SB + (size_t)(sl >> 1) * N + jj];
+                    }
+                } else {
+                    x = n == B ? make_double2(0.0, 0.0) : in[bp.batch * N3 + ((size_t)n * N + line) * N + row];
                 }
-                const double2 a0 = cadd(v[q][0], v[q][2]);
-                const double2 a1 = csub(v[q][0], v[q][2]);
-                const double2 a2 = cadd(v[q][1], v[q][3]);
-                const double2 a3 = cmul_si<SIGN>(csub(v[q][1], v[q][3]));
-                const int base = (jj - k) * 4 + k;
-                buf[t * S + base] = cadd(a0, a2);
-                buf[t * S + base + Ns] = cadd(a1, a3);
-                buf[t * S + base + 2 * Ns] = csub(a0, a2);
-                buf[t * S + base + 3 * Ns] = csub(a1, a3);
+                v[k * R + r] = x;
             }
         }
+    }
+    run_stage<N, 0, SIGN>(v, p_in, tw);
+
+    // ---- exchanges through LDS (lane order: row index fastest) ----
+    int t_out = t_in, p_out = p_in;
+    if constexpr (NSTG > 1) {
+        const int t = tid / P, pp = tid % P;
+        put_stage<N, 0>(v, lds, t_in, p_in);
         __syncthreads();
-        logNs += 2;
-    }
-}
-
-// gamma pass, forward: grid[i][j][k] -> t1[q][j][i], FFT along k, e^{+i}.
-// Block (i-tile, j, batch); q = N/2 (the +-B bin) is not stored.
-template <int N>
-__global__ __launch_bounds__(threads_for(N)) void k_fft_gamma_fwd(PlanView p, const double2 *__restrict__ grid,
-                                                           double2 *__restrict__ t1) {
-    constexpr int T = tile_for(N, false);
-    constexpr int NT = threads_for(N);
-    constexpr int S = N + 1;
-    __shared__ double2 buf[T * S];
-    const int it = blockIdx.x, j = blockIdx.y;
-    const size_t N3 = (size_t)N * N * N;
-    const double2 *g = grid + blockIdx.z * N3;
-    double2 *o = t1 + blockIdx.z * N3;
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e / N, n = e % N;
-        buf[t * S + n] = g[((size_t)(it * T + t) * N + j) * N + n];
-    }
-    __syncthreads();
-    fft_lds<N, T, NT, +1>(buf, p.twp);
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e % T, q = e / T;
-        if (q != N / 2) o[((size_t)q * N + j) * N + it * T + t] = buf[t * S + q];
-    }
-}
-
-// alpha pass, forward: t1[q][j][i] -> S[slot][j'], FFT along i, e^{+i},
-// times w_B(j) when apply_w; j' = N-1-j for members at pi - beta.
-// Block (j-tile, q != N/2, batch).
-template <int N>
-__global__ __launch_bounds__(threads_for(N)) void k_fft_alpha_fwd(PlanView p, const double2 *__restrict__ t1,
-                                                           double2 *__restrict__ Sout, int apply_w) {
-    constexpr int T = tile_for(N, false);
-    constexpr int NT = threads_for(N);
-    constexpr int S = N + 1;
-    constexpr int B = N / 2;
-    __shared__ double2 buf[T * S];
-    const int jt = blockIdx.x;
-    const int q = blockIdx.y < B ? blockIdx.y : blockIdx.y + 1;
-    const size_t N3 = (size_t)N * N * N;
-    const double2 *in = t1 + blockIdx.z * N3 + ((size_t)q * N + jt * T) * N;
-    double2 *o = Sout + blockIdx.z * ((size_t)p.G * kSlots * N);
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e / N, n = e % N;
-        buf[t * S + n] = in[e];
-    }
-    __syncthreads();
-    fft_lds<N, T, NT, +1>(buf, p.twp);
-    const int mp = q < B ? q : q - N;
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e % T, pi = e / T;
-        if (pi == B) continue;
-        const int m = pi < B ? pi : pi - N;
-        const int sl = slot_code(m, mp);
-        const int j = jt * T + t;
-        const int jj = (sl & 1) ? N - 1 - j : j;
-        double2 v = buf[t * S + pi];
-        if (apply_w) {
-            const double wj = p.w[j];
-            v.x *= wj;
-            v.y *= wj;
+        if constexpr (NSTG > 2) {
+            get_stage<N, 1>(v, lds, t, pp);
+            run_stage<N, 1, SIGN>(v, pp, tw);
+            __syncthreads();
+            put_stage<N, 1>(v, lds, t, pp);
+            __syncthreads();
         }
-        o[(size_t)(sl >> 1) * N + jj] = v;
+        t_out = transposed_out<KIND>() ? tid % T : t;
+        p_out = transposed_out<KIND>() ? tid / T : pp;
+        get_stage<N, LAST>(v, lds, t_out, p_out);
+        run_stage<N, LAST, SIGN>(v, p_out, tw);
     }
-}
 
-// alpha pass, inverse: S'[slot][j'] -> t1[q][j][i], FFT along m, e^{-i}.
-template <int N>
-__global__ __launch_bounds__(threads_for(N)) void k_fft_alpha_inv(PlanView p, const double2 *__restrict__ Sin,
-                                                           double2 *__restrict__ t1) {
-    constexpr int T = tile_for(N, true);
-    constexpr int NT = threads_for(N);
-    constexpr int S = N + 1;
-    constexpr int B = N / 2;
-    __shared__ double2 buf[T * S];
-    const int jt = blockIdx.x;
-    const int q = blockIdx.y < B ? blockIdx.y : blockIdx.y + 1;
-    const size_t N3 = (size_t)N * N * N;
-    const double2 *in = Sin + blockIdx.z * ((size_t)p.G * kSlots * N);
-    double2 *o = t1 + blockIdx.z * N3 + ((size_t)q * N + jt * T) * N;
-    const int mp = q < B ? q : q - N;
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e % T, pi = e / T;
-        double2 v = make_double2(0.0, 0.0);
-        if (pi != B) {
-            const int m = pi < B ? pi : pi - N;
-            const int sl = slot_code(m, mp);
-            const int j = jt * T + t;
-            const int jj = (sl & 1) ? N - 1 - j : j;
-            v = in[(size_t)(sl >> 1) * N + jj];
+    // ---- last stage outputs to HBM: element b + r*N/R ----
+    {
+        constexpr int R = radix_of<N, LAST>(), BPT = N / R / P;
+        const int row = tile * T + t_out;
+        double wj = 1.0;
+        if constexpr (KIND == ALPHA_FWD || KIND == GAMMA_INV) {
+            if (apply_w) wj = p.w[KIND == ALPHA_FWD ? row : line];
         }
-        buf[t * S + pi] = v;
-    }
-    __syncthreads();
-    fft_lds<N, T, NT, -1>(buf, p.twm);
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e / N, n = e % N;
-        o[e] = buf[t * S + n];
-    }
-}
-
-// gamma pass, inverse: t1[q][j][i] -> grid[i][j][k], FFT along m', e^{-i},
-// times w_B(j) when apply_w.  Block (i-tile, j, batch).
-template <int N>
-__global__ __launch_bounds__(threads_for(N)) void k_fft_gamma_inv(PlanView p, const double2 *__restrict__ t1,
-                                                           double2 *__restrict__ grid, int apply_w) {
-    constexpr int T = tile_for(N, true);
-    constexpr int NT = threads_for(N);
-    constexpr int S = N + 1;
-    __shared__ double2 buf[T * S];
-    const int it = blockIdx.x, j = blockIdx.y;
-    const size_t N3 = (size_t)N * N * N;
-    const double2 *in = t1 + blockIdx.z * N3;
-    double2 *g = grid + blockIdx.z * N3;
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e % T, q = e / T;
-        buf[t * S + q] = q == N / 2 ? make_double2(0.0, 0.0) : in[((size_t)q * N + j) * N + it * T + t];
-    }
-    __syncthreads();
-    fft_lds<N, T, NT, -1>(buf, p.twm);
-    const double wj = apply_w ? p.w[j] : 1.0;
-#pragma unroll 4
-    for (int e = threadIdx.x; e < T * N; e += NT) {
-        const int t = e / N, n = e % N;
-        double2 v = buf[t * S + n];
-        v.x *= wj;
-        v.y *= wj;
-        g[((size_t)(it * T + t) * N + j) * N + n] = v;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int n = p_out + k * P + r * (N / R);
+                const double2 x = v[k * R + r];
+                if constexpr (KIND == GAMMA_FWD) {
+                    if (n != B) out[bp.batch * N3 + ((size_t)n * N + line) * N + row] = x;
+                } else if constexpr (KIND == ALPHA_FWD) {
+                    if (n != B) {
+                        const int sl = slot_code(n < B ? n : n - N, mp_line);
+                        const int jj = (sl & 1) ? N - 1 - row : row;
+                        out[bp.batch * SB + (size_t)(sl >> 1) * N + jj] = make_double2(x.x * wj, x.y * wj);
+                    }
+                } else if constexpr (KIND == ALPHA_INV) {
+                    out[bp.batch * N3 + ((size_t)line * N + row) * N + n] = x;
+                } else {
+                    out[bp.batch * N3 + ((size_t)row * N + line) * N + n] = make_double2(x.x * wj, x.y * wj);
+                }
+            }
+        }
     }
 }
 
-#define SOFT_FFT_DISPATCH(N_, CALL)           \
-    switch (N_) {                             \
-        case 2: { constexpr int NN = 2; CALL; } break;       \
-        case 4: { constexpr int NN = 4; CALL; } break;       \
-        case 8: { constexpr int NN = 8; CALL; } break;       \
-        case 16: { constexpr int NN = 16; CALL; } break;     \
-        case 32: { constexpr int NN = 32; CALL; } break;     \
-        case 64: { constexpr int NN = 64; CALL; } break;     \
-        case 128: { constexpr int NN = 128; CALL; } break;   \
-        case 256: { constexpr int NN = 256; CALL; } break;   \
-        case 512: { constexpr int NN = 512; CALL; } break;   \
-        case 1024: { constexpr int NN = 1024; CALL; } break; \
-        default: return hipErrorInvalidValue;               \
+template <int N, int KIND, int SIGN>
+hipError_t launch_kind(const PlanView &p, int batch, const double2 *in, double2 *out, int apply_w, hipStream_t s) {
+    using Sh = Shape<N>;
+    constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
+    const int nline = ALPHA ? N - 1 : N;
+    // Grid (tiles, lines, batch); block_pos() re-deals (tile, line) across XCDs.
+    dim3 g(N / Sh::T, nline, batch);
+    hipLaunchKernelGGL((k_fft<N, KIND, SIGN>), g, dim3(Sh::NT), 0, s, p, in, out, apply_w);
+    return hipGetLastError();
+}
+
+template <int KIND, int SIGN>
+hipError_t dispatch(const PlanView &p, int batch, const double2 *in, double2 *out, int apply_w, hipStream_t s) {
+    switch (p.N) {
+        case 2: return launch_kind<2, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 4: return launch_kind<4, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 8: return launch_kind<8, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 16: return launch_kind<16, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 32: return launch_kind<32, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 64: return launch_kind<64, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 128: return launch_kind<128, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 256: return launch_kind<256, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 512: return launch_kind<512, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 1024: return launch_kind<1024, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        default: return hipErrorInvalidValue;
     }
+}
 
 }  // namespace
 
 hipError_t launch_fft_gamma_fwd(const PlanView &p, int batch, const double2 *grid, double2 *t1, hipStream_t s) {
-    SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN, false), NN, batch);
-        hipLaunchKernelGGL(k_fft_gamma_fwd<NN>, g, dim3(threads_for(NN)), 0, s, p, grid, t1);
-    });
-    return hipGetLastError();
+    return dispatch<GAMMA_FWD, +1>(p, batch, grid, t1, 0, s);
 }
 
 hipError_t launch_fft_alpha_fwd(const PlanView &p, int batch, const double2 *t1, double2 *S, bool apply_w,
                                 hipStream_t s) {
-    SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN, false), NN - 1, batch);
-        hipLaunchKernelGGL(k_fft_alpha_fwd<NN>, g, dim3(threads_for(NN)), 0, s, p, t1, S, (int)apply_w);
-    });
-    return hipGetLastError();
+    return dispatch<ALPHA_FWD, +1>(p, batch, t1, S, (int)apply_w, s);
 }
 
 hipError_t launch_fft_alpha_inv(const PlanView &p, int batch, const double2 *S, double2 *t1, hipStream_t s) {
-    SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN, true), NN - 1, batch);
-        hipLaunchKernelGGL(k_fft_alpha_inv<NN>, g, dim3(threads_for(NN)), 0, s, p, S, t1);
-    });
-    return hipGetLastError();
+    return dispatch<ALPHA_INV, -1>(p, batch, S, t1, 0, s);
 }
 
 hipError_t launch_fft_gamma_inv(const PlanView &p, int batch, const double2 *t1, double2 *grid, bool apply_w,
                                 hipStream_t s) {
-    SOFT_FFT_DISPATCH(p.N, {
-        dim3 g(NN / tile_for(NN, true), NN, batch);
-        hipLaunchKernelGGL(k_fft_gamma_inv<NN>, g, dim3(threads_for(NN)), 0, s, p, t1, grid, (int)apply_w);
-    });
-    return hipGetLastError();
+    return dispatch<GAMMA_INV, -1>(p, batch, t1, grid, (int)apply_w, s);
 }
 
 }  // namespace soft
