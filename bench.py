@@ -4,7 +4,7 @@
 
 A step is one inverse (coefficients -> grid) followed by one forward (grid ->
 coefficients) of one function at bandwidth B in FP64: the whole hot path
-(reorder, iDWT, two FFT passes, two FFT passes, DWT, reorder).  Inputs are
+(iDWT, two FFT passes, two FFT passes, DWT).  Inputs are
 seeded synthetic band-limited coefficients (i.i.d. normal parts scaled by
 (1+l)^-1) already resident in HBM when the timed region starts.
 
@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 (vector and matrix), published
 METRIC = "SOFT fwd+inv/sec at B=128 & 512: FP64 plain vs batched FP32-split @ ≤1e-6 err"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = {"fft": "fft.hip", "dwt": "dwt.hip", "reorder": "reorder.hip"}
+KERNEL_SOURCES = {"fft": "fft.hip", "dwt": "dwt.hip"}
 
 
 def num_coeffs(B):
@@ -53,8 +53,6 @@ def stage_work(B, batch=1):
         "fft_gamma_fwd": ("hbm", 16.0 * (N ** 3 + N * N * (N - 1))),
         "fft_alpha_fwd": ("hbm", 16.0 * (N * N * (N - 1) + N * P * P)),
         "dwt_fwd": ("flop", dwt_flops),
-        "reorder_fwd": ("hbm", 32.0 * nc),
-        "reorder_inv": ("hbm", 32.0 * nc),
         "dwt_inv": ("flop", dwt_flops),
         "fft_alpha_inv": ("hbm", 16.0 * (N * P * P + N * N * (N - 1))),
         "fft_gamma_inv": ("hbm", 16.0 * (N * N * (N - 1) + N ** 3)),
@@ -77,7 +75,7 @@ def measured_traffic(stage, B):
     rec = data.get(f"B{B}", {}).get(stage)
     if not rec:
         return None
-    kind = "fft" if stage.startswith("fft") else ("dwt" if stage.startswith("dwt") else "reorder")
+    kind = "fft" if stage.startswith("fft") else "dwt"
     if rec.get("source_sha") != source_digest(kind):
         return None
     return rec.get("bytes_per_launch")

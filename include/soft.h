@@ -72,8 +72,9 @@ typedef enum {
  *   precision  SOFT_FP64.
  *   flags      must be 0.
  *   out        receives the plan handle; unchanged on error.
- * Allocates the plan's device workspace (about 16 (2B)^3 + 16 B^3 + 8 B^3/3
- * bytes per function) and its FP64 tables (quadrature weights, Wigner-d seed
+ * Allocates the plan's device workspace (about 16 (2B)^3 bytes for the FFT
+ * intermediate plus 16 (2B)^3 for the per-order-pair beta samples, per
+ * function, and 4 B^3 bytes of recurrence tables) and its FP64 tables (quadrature weights, Wigner-d seed
  * constants, FFT twiddles), on the current HIP device; later calls must run
  * with the same device current.  Synchronous.
  * Returns SOFT_OK, SOFT_ERR_INVALID, SOFT_ERR_UNSUPPORTED, SOFT_ERR_OOM or
@@ -130,22 +131,19 @@ int soft_adjoint_inverse(soft_plan_t plan, const void *grid, void *coeffs, hipSt
  * records a HIP event on its stream before and after each kernel it enqueues;
  * soft_plan_stage_times() waits for the recorded events and returns, per
  * stage, the summed elapsed milliseconds and the number of launches timed.
- * Stages (SOFT_STAGE_*):
- *   0 gamma FFT (forward)     1 alpha FFT + weights (forward)
- *   2 DWT (forward)           3 group-major -> l-major reorder
- *   4 l-major -> group-major  5 iDWT
- *   6 alpha FFT (inverse)     7 gamma FFT (inverse)
+ * Stages (SOFT_STAGE_*), each one kernel:
+ *   0 gamma FFT (forward)      1 alpha FFT + weights (forward)
+ *   2 DWT, writing f° (fwd)    3 iDWT, reading f° (inverse)
+ *   4 alpha FFT (inverse)      5 gamma FFT (inverse)
  */
 enum {
     SOFT_STAGE_FFT_GAMMA_FWD = 0,
     SOFT_STAGE_FFT_ALPHA_FWD = 1,
     SOFT_STAGE_DWT_FWD = 2,
-    SOFT_STAGE_REORDER_FWD = 3,
-    SOFT_STAGE_REORDER_INV = 4,
-    SOFT_STAGE_DWT_INV = 5,
-    SOFT_STAGE_FFT_ALPHA_INV = 6,
-    SOFT_STAGE_FFT_GAMMA_INV = 7,
-    SOFT_NUM_STAGES = 8
+    SOFT_STAGE_DWT_INV = 3,
+    SOFT_STAGE_FFT_ALPHA_INV = 4,
+    SOFT_STAGE_FFT_GAMMA_INV = 5,
+    SOFT_NUM_STAGES = 6
 };
 
 /*

@@ -4,12 +4,15 @@
 // Matrix form of Sect. 2.4: for each (m, m'),
 //   forward  f°(l) = (2l+1)/(8 pi B) sum_j d(l,m,m';b_j) w_B(j) S(m,m';j)   (V T W)
 //   inverse  S'(j) = sum_l d(l,m,m';b_j) f°(l)                              (T^T)
-// The weights were applied by the FFT pass and the (2l+1)/(8 pi B) factor and
-// the symmetry signs by the reorder pass, so the kernels here compute, for
-// the representative d_rep(l; b_j) of a group and its <= 8 member columns c,
+// The weights are applied by the FFT pass; the core of both kernels works on
+// the representative d_rep(l; b_j) of a symmetry group and its <= 8 member
+// columns c,
 //   forward  G[l][c]  = sum_j d_rep(l; b_j) X[j][c]
 //   inverse  Y[j][c]  = sum_l d_rep(l; b_j) F[l][c]
-// (members at pi - beta were stored in reversed j order, eq. "Wigner_symmetries").
+// (members at pi - beta were stored in reversed j order, eq. "Wigner_symmetries"),
+// and the move between the l-major coefficient layout and the group columns,
+// with each member's symmetry sign and the (2l+1)/(8 pi B) factor of V_B, is
+// fused into the forward epilogue and the inverse staging.
 //
 // d_rep is never stored: each lane owns one beta_j, seeds d(l0,l0,m';b_j)
 // (Sect. 2.2, evaluated in log space with double-double exponents) and runs
@@ -70,7 +73,7 @@ __device__ __forceinline__ double seed_d(const PlanView &p, int g, int m, int mp
 // d(l) = s_l e(l) with s_{l0} = s_{l0+1} = 1 and s_{l+1} = Bc_l s_{l-1} turns it
 // into e(l+1) = (alpha_l x - gamma_l) e(l) - e(l-1), alpha_l = A_l s_l/s_{l+1},
 // gamma_l = C_l s_l/s_{l+1}: two FMAs per step and two coefficients.  The
-// kernels run e; the reorder passes apply s_l.  Row goff[g] + (l - l0) of the
+// kernels run e; s_l is applied where coefficients enter or leave.  Row goff[g] + (l - l0) of the
 // table holds (alpha_l, gamma_l) and s_l; one thread per group fills it
 // (s is a running product).
 __global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__restrict__ rec,
@@ -116,10 +119,12 @@ __device__ __forceinline__ int panel_idx(int jl, int r) { return jl * 16 + (r ^ 
 
 template <int NW, int NSUB>
 __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *__restrict__ rec,
-                                                    const double2 *__restrict__ S, double2 *__restrict__ Cg) {
+                                                    const double2 *__restrict__ S, double2 *__restrict__ coeffs,
+                                                    int apply_v) {
     __shared__ double panel[NW][64 * 16];
     __shared__ double red[2][NW][256];
-    const int g = blockIdx.x;
+    __shared__ double srow[kMaxB];
+    const int g = group_of_block(blockIdx.x, p.G);
     const GroupInfo gi = p.grp[g];
     const int N = p.N;
     const int m = gi.m, mp = gi.mp;
@@ -161,8 +166,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = R[r];  // the table is padded past the last group
 
+    // s_l of the group's rows, read in the panel epilogues (visible after the
+    // first panel's barrier).
+    for (int t = threadIdx.x; t < L; t += NW * 64) srow[t] = p.rscale[p.goff[g] + t];
     double *pan = panel[wave];
-    double *out = reinterpret_cast<double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
+    double *out = reinterpret_cast<double *>(coeffs + (size_t)blockIdx.y * p.Nc);
+    const double *sl = srow;
+    const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
     int buf = 0;
     for (int lp = 0; lp < L; lp += 16, buf ^= 1) {
         v4d acc[4];
@@ -193,38 +203,109 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[buf][wave][(krow + 4 * r) * 16 + col] = tot[r];
         __syncthreads();
+        // Epilogue (the reorder): column c = 2 slot + part of row lp + r is
+        // f°(l, member of slot) up to the slot's symmetry sign, s_l and V_B.
         for (int t = threadIdx.x; t < 256; t += NW * 64) {
             double sum = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) sum += red[buf][w][t];
-            const int row = t >> 4;
-            if (lp + row < L) out[(size_t)(lp + row) * 16 + (t & 15)] = sum;
+            const int li = lp + (t >> 4), slot = (t & 15) >> 1;
+            if (li < L && ((gi.mask >> slot) & 1)) {
+                const int l = m + li;
+                int mm, mmp;
+                double sign;
+                group_member(slot, m, mp, l, mm, mmp, sign);
+                const double f = sign * sl[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
+                out[2 * coeff_index(l, mm, mmp) + (t & 1)] = sum * f;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Inverse DWT: per-lane FMA chains, coefficients broadcast.
+// Inverse DWT: per-lane FMA chains, coefficients broadcast from LDS.
 // ---------------------------------------------------------------------------
-// Lane owns JPL beta samples.  The group's coefficient rows (already scaled by
-// s_l) and the recurrence coefficients are wave-uniform and arrive through
-// scalar loads issued one degree ahead of their use.
+// Lane owns JPL beta samples.  The block gathers its group's coefficients
+// straight from the l-major layout (the inverse reorder: symmetry sign, s_l
+// and optionally V_B applied on the way) together with the recurrence
+// coefficients into LDS, CH degrees at a time, double-buffered and issued two
+// chunks ahead, so HBM latency is paid once per chunk and not once per
+// degree.  Row r of a chunk holds the 16 member values (re, im) and
+// (alpha, gamma); every lane reads it by broadcast.
+constexpr int kChunk = 32;
+constexpr int kRowD = 18;  // doubles per staged row
+
+template <int NT>
+struct InvStage {
+    static constexpr int PER = kChunk * kSlots / NT > 0 ? kChunk * kSlots / NT : 1;  // elements per thread
+    double2 v[PER];
+    double2 r;  // (alpha, gamma) for row threadIdx.x, when < kChunk
+};
+
+// Gather chunk c of group g into registers.
+template <int NT>
+__device__ __forceinline__ void inv_gather(InvStage<NT> &st, const PlanView &p, const double2 *__restrict__ rec,
+                                           const double2 *__restrict__ cin, const GroupInfo &gi, int g, int L,
+                                           int c, double v0) {
+#pragma unroll
+    for (int k = 0; k < InvStage<NT>::PER; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int row = e >> 3, slot = e & 7;
+        const int li = c * kChunk + row;
+        double2 val = make_double2(0.0, 0.0);
+        if (e < kChunk * kSlots && li < L && ((gi.mask >> slot) & 1)) {
+            const int l = gi.m + li;
+            int mm, mmp;
+            double sign;
+            group_member(slot, gi.m, gi.mp, l, mm, mmp, sign);
+            const double f = sign * p.rscale[p.goff[g] + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
+            const double2 a = cin[coeff_index(l, mm, mmp)];
+            val = make_double2(a.x * f, a.y * f);
+        }
+        st.v[k] = val;
+    }
+    if (threadIdx.x < kChunk) st.r = rec[p.goff[g] + c * kChunk + threadIdx.x];  // padded table
+}
+
+template <int NT>
+__device__ __forceinline__ void inv_put(const InvStage<NT> &st, double *buf) {
+#pragma unroll
+    for (int k = 0; k < InvStage<NT>::PER; ++k) {
+        const int e = threadIdx.x + k * NT;
+        if (e < kChunk * kSlots) {
+            const int row = e >> 3, slot = e & 7;
+            buf[row * kRowD + 2 * slot] = st.v[k].x;
+            buf[row * kRowD + 2 * slot + 1] = st.v[k].y;
+        }
+    }
+    if (threadIdx.x < kChunk) {
+        buf[threadIdx.x * kRowD + 16] = st.r.x;
+        buf[threadIdx.x * kRowD + 17] = st.r.y;
+    }
+}
+
 template <int NW, int JPL>
 __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *__restrict__ rec,
-                                                    const double2 *__restrict__ Cg, double2 *__restrict__ S) {
-    const int g = blockIdx.x;
+                                                    const double2 *__restrict__ coeffs, double2 *__restrict__ S,
+                                                    int apply_v) {
+    constexpr int NT = NW * 64;
+    __shared__ __align__(16) double stage[2][kChunk * kRowD];
+    const int g = group_of_block(blockIdx.x, p.G);
     const GroupInfo gi = p.grp[g];
     const int N = p.N;
     const int m = gi.m, mp = gi.mp;
     const int L = p.B - m;
-    const double2 *__restrict__ R = rec + p.goff[g];
-    const double *__restrict__ F =
-        reinterpret_cast<const double *>(Cg + (size_t)blockIdx.y * p.rows * kSlots) + (size_t)p.goff[g] * 16;
+    const int nchunk = (L + kChunk - 1) / kChunk;
+    const double2 *cin = coeffs + (size_t)blockIdx.y * p.Nc;
+    const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
+
+    InvStage<NT> st;
+    inv_gather<NT>(st, p, rec, cin, gi, g, L, 0, v0);
 
     double x[JPL], ecur[JPL], eprev[JPL], acc[JPL][16];
 #pragma unroll
     for (int h = 0; h < JPL; ++h) {
-        const int j = threadIdx.x + h * NW * 64;
+        const int j = threadIdx.x + h * NT;
         x[h] = j < N ? p.cosb[j] : 0.0;
         ecur[h] = j < N ? seed_d(p, g, m, mp, j) : 0.0;
         eprev[h] = 0.0;
@@ -232,35 +313,43 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *
         for (int c = 0; c < 16; ++c) acc[h][c] = 0.0;
     }
 
-    double f[16];
-    double2 rc = R[0];
+    inv_put<NT>(st, stage[0]);
+    if (nchunk > 1) inv_gather<NT>(st, p, rec, cin, gi, g, L, 1, v0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const double *buf = stage[c & 1];
+        const int rows = L - c * kChunk < kChunk ? L - c * kChunk : kChunk;
+        for (int r = 0; r < rows; ++r) {
+            const double *row = buf + r * kRowD;
+            double f[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) f[c] = F[c];
-    for (int li = 0; li < L; ++li) {
-        // Next degree's operands (rows past the group's end are padding or the
-        // next group's and are never used).
-        double fn[16];
+            for (int q = 0; q < 8; ++q) {
+                const double2 t = *reinterpret_cast<const double2 *>(row + 2 * q);
+                f[2 * q] = t.x;
+                f[2 * q + 1] = t.y;
+            }
+            const double2 ag = *reinterpret_cast<const double2 *>(row + 16);
 #pragma unroll
-        for (int c = 0; c < 16; ++c) fn[c] = F[(size_t)(li + 1) * 16 + c];
-        const double2 rn = R[li + 1];
+            for (int h = 0; h < JPL; ++h) {
 #pragma unroll
-        for (int h = 0; h < JPL; ++h) {
-#pragma unroll
-            for (int c = 0; c < 16; ++c) acc[h][c] = fma(ecur[h], f[c], acc[h][c]);
-            const double u = fma(rc.x, x[h], -rc.y);
-            const double en = fma(u, ecur[h], -eprev[h]);
-            eprev[h] = ecur[h];
-            ecur[h] = en;
+                for (int q = 0; q < 16; ++q) acc[h][q] = fma(ecur[h], f[q], acc[h][q]);
+                const double u = fma(ag.x, x[h], -ag.y);
+                const double en = fma(u, ecur[h], -eprev[h]);
+                eprev[h] = ecur[h];
+                ecur[h] = en;
+            }
         }
-#pragma unroll
-        for (int c = 0; c < 16; ++c) f[c] = fn[c];
-        rc = rn;
+        if (c + 1 < nchunk) {
+            inv_put<NT>(st, stage[(c + 1) & 1]);
+            if (c + 2 < nchunk) inv_gather<NT>(st, p, rec, cin, gi, g, L, c + 2, v0);
+        }
+        __syncthreads();
     }
 
     double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
 #pragma unroll
     for (int h = 0; h < JPL; ++h) {
-        const int j = threadIdx.x + h * NW * 64;
+        const int j = threadIdx.x + h * NT;
         if (j >= N) continue;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s)
@@ -275,37 +364,41 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
     return hipGetLastError();
 }
 
-hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *Cg, hipStream_t s) {
+hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *coeffs, bool apply_v,
+                          hipStream_t s) {
+    const int av = apply_v;
     if (p.B > kMaxB) return hipErrorInvalidValue;
     dim3 grid(p.G, batch);
     // waves x subsets of 64 j: N <= 64: 1x1; 128: 2x1; 256: 4x1; 512: 4x2; 1024: 8x2.
     if (p.N <= 64)
-        hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, p.rec, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, p.rec, S, coeffs, av);
     else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_fwd<2, 1>), grid, dim3(128), 0, s, p, p.rec, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<2, 1>), grid, dim3(128), 0, s, p, p.rec, S, coeffs, av);
     else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, p.rec, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, p.rec, S, coeffs, av);
     else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_fwd<4, 2>), grid, dim3(256), 0, s, p, p.rec, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<4, 2>), grid, dim3(256), 0, s, p, p.rec, S, coeffs, av);
     else
-        hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, p.rec, S, Cg);
+        hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, p.rec, S, coeffs, av);
     return hipGetLastError();
 }
 
-hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *Cg, double2 *S, hipStream_t s) {
+hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *coeffs, double2 *S, bool apply_v,
+                          hipStream_t s) {
+    const int av = apply_v;
     if (p.B > kMaxB) return hipErrorInvalidValue;
     dim3 grid(p.G, batch);
     // waves x beta samples per lane: N <= 64: 1x1; 128: 1x2; 256: 1x4; 512: 2x4; 1024: 4x4.
     if (p.N <= 64)
-        hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, p.rec, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
     else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_inv<1, 2>), grid, dim3(64), 0, s, p, p.rec, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<1, 2>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
     else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_inv<1, 4>), grid, dim3(64), 0, s, p, p.rec, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<1, 4>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
     else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_inv<2, 4>), grid, dim3(128), 0, s, p, p.rec, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<2, 4>), grid, dim3(128), 0, s, p, p.rec, coeffs, S, av);
     else
-        hipLaunchKernelGGL((k_dwt_inv<4, 4>), grid, dim3(256), 0, s, p, p.rec, Cg, S);
+        hipLaunchKernelGGL((k_dwt_inv<4, 4>), grid, dim3(256), 0, s, p, p.rec, coeffs, S, av);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ struct soft_plan_s {
     soft::PlanView view{};
     // device allocations
     void *tables = nullptr;
-    double2 *S = nullptr, *t1 = nullptr, *Cg = nullptr;
+    double2 *S = nullptr, *t1 = nullptr;
     double2 *rec = nullptr;
     double *rscale = nullptr;
     size_t ws_bytes = 0;
@@ -53,7 +53,6 @@ void free_plan(soft_plan_s *p) {
     if (p->tables) (void)hipFree(p->tables);
     if (p->S) (void)hipFree(p->S);
     if (p->t1) (void)hipFree(p->t1);
-    if (p->Cg) (void)hipFree(p->Cg);
     if (p->rec) (void)hipFree(p->rec);
     if (p->rscale) (void)hipFree(p->rscale);
     delete p;
@@ -198,8 +197,8 @@ class StageClock {
     hipEvent_t prev_ = nullptr;
 };
 
-// Forward-type transform: FFT (gamma, then alpha with optional W), DWT,
-// reorder (optional V).  soft_forward uses W and V; soft_adjoint_inverse
+// Forward-type transform: FFT (gamma, then alpha with optional W), DWT with
+// the reorder (optional V) in its epilogue.  soft_forward uses W and V; soft_adjoint_inverse
 // uses neither.
 int run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bool scaled) {
     const int rc = check_call(p, grid, coeffs);
@@ -210,25 +209,22 @@ int run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bo
     if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_FWD);
     if (e == hipSuccess) e = soft::launch_fft_alpha_fwd(p->view, p->batch, p->t1, p->S, scaled, s);
     if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_FWD);
-    if (e == hipSuccess) e = soft::launch_dwt_fwd(p->view, p->batch, p->S, p->Cg, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
     if (e == hipSuccess)
-        e = soft::launch_reorder_fwd(p->view, p->batch, p->Cg, static_cast<double2 *>(coeffs), scaled, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_REORDER_FWD);
+        e = soft::launch_dwt_fwd(p->view, p->batch, p->S, static_cast<double2 *>(coeffs), scaled, s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
     return hip_status(e);
 }
 
-// Inverse-type transform: reorder (optional V), iDWT, FFT (alpha, then gamma
-// with optional W).  soft_inverse uses neither; soft_adjoint uses both.
+// Inverse-type transform: iDWT (gathering the l-major coefficients, optional
+// V), FFT (alpha, then gamma with optional W).  soft_inverse uses neither
+// factor; soft_adjoint uses both.
 int run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bool scaled) {
     const int rc = check_call(p, coeffs, grid);
     if (rc != SOFT_OK) return rc;
     StageClock clk(p, s);
     hipError_t e = clk.start();
     if (e == hipSuccess)
-        e = soft::launch_reorder_inv(p->view, p->batch, static_cast<const double2 *>(coeffs), p->Cg, scaled, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_REORDER_INV);
-    if (e == hipSuccess) e = soft::launch_dwt_inv(p->view, p->batch, p->Cg, p->S, s);
+        e = soft::launch_dwt_inv(p->view, p->batch, static_cast<const double2 *>(coeffs), p->S, scaled, s);
     if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
     if (e == hipSuccess) e = soft::launch_fft_alpha_inv(p->view, p->batch, p->S, p->t1, s);
     if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_INV);
@@ -267,18 +263,16 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
     const size_t N = p->N;
     const size_t s_elems = (size_t)batch * p->G * kSlots * N;
     const size_t t1_elems = (size_t)batch * N * N * N;
-    const size_t cg_elems = ((size_t)batch * p->rows + soft::kPadRows) * kSlots;
     const size_t rec_rows = (size_t)p->rows + soft::kPadRows;
     if (hipMalloc(&p->tables, lay.total) != hipSuccess || hipMalloc(&p->S, s_elems * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->t1, t1_elems * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->Cg, cg_elems * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         free_plan(p);
         return SOFT_ERR_OOM;
     }
-    p->ws_bytes = lay.total + (s_elems + t1_elems + cg_elems) * sizeof(double2) +
+    p->ws_bytes = lay.total + (s_elems + t1_elems) * sizeof(double2) +
                   rec_rows * (sizeof(double2) + sizeof(double));
     if (hipMemcpy(p->tables, host.data(), lay.total, hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(p);
@@ -305,7 +299,6 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
     // Padding rows are read (never used) by prefetches; give them defined values.
     if (hipMemset(p->rec, 0, rec_rows * sizeof(double2)) != hipSuccess ||
         hipMemset(p->rscale, 0, rec_rows * sizeof(double)) != hipSuccess ||
-        hipMemset(p->Cg, 0, cg_elems * sizeof(double2)) != hipSuccess ||
         soft::launch_fill_recurrence(v, p->rec, p->rscale, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         free_plan(p);
         return SOFT_ERR_HIP;

@@ -115,8 +115,7 @@ def soft_adjoint_inverse(plan, grid, coeffs, stream=None):
            "soft_adjoint_inverse")
 
 
-STAGES = ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "reorder_fwd",
-          "reorder_inv", "dwt_inv", "fft_alpha_inv", "fft_gamma_inv")
+STAGES = ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "dwt_inv", "fft_alpha_inv", "fft_gamma_inv")
 
 
 def soft_plan_set_timing(plan, enable):
