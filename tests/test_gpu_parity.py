@@ -116,3 +116,63 @@ def test_B128_full(oracle, dev):
     want_c = oracle.forward(B, want_g)
     assert relerr(cd, want_c) <= TOL64
     assert relerr(cd, c) <= TOL64
+
+
+def test_B256_sampled(oracle, dev):
+    """B = 256 (512^3 grid): sampled beta-slices of the inverse and sampled
+    order pairs of the forward against the double oracle; round trip."""
+    B = 256
+    c = inputs.coeffs_decay(B, 2)
+    with soft.Plan(B) as p:
+        gd = p.inverse(to_dev(c, dev))
+        cd = to_host(p.forward(gd))
+        g = to_host(gd)
+        del gd
+    for j in (0, 1, 255, 256, 511):
+        want = oracle.inverse_slice(B, c, j)
+        assert relerr(g[:, j, :], want) <= TOL64, j
+    assert relerr(cd, c) <= TOL64
+    pairs = [(0, 0), (1, -1), (37, 200), (-128, 5), (255, -255), (-3, 254)]
+    want = oracle.forward_pairs(B, g, pairs)
+    for p_, (m, mp) in enumerate(pairs):
+        l0 = max(abs(m), abs(mp))
+        got = np.array([cd[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
+        assert np.abs(got - want[p_, l0:]).max() <= TOL64 * np.abs(c).max(), (m, mp)
+
+
+def test_B512_sampled(oracle, dev):
+    """B = 512 (1024^3 complex128 grid, 16 GiB): sampled inverse slices against
+    the long-double oracle (gate 1e-9), forward on sampled order pairs, and the
+    round trip over all 1.8e8 coefficients."""
+    B = 512
+    c = inputs.coeffs_decay(B, 3)
+    with soft.Plan(B) as p:
+        gd = p.inverse(to_dev(c, dev))
+        cd = to_host(p.forward(gd))
+        g = to_host(gd)
+        del gd
+        torch.cuda.empty_cache()
+    assert relerr(cd, c) <= 1e-9
+    for j in (0, 700):
+        want = oracle.inverse_slice(B, c, j, prec="f80")
+        assert relerr(g[:, j, :], want) <= 1e-9, j
+    pairs = [(0, 0), (511, -511), (-300, 17), (64, 63)]
+    want = oracle.forward_pairs(B, g, pairs)
+    for p_, (m, mp) in enumerate(pairs):
+        l0 = max(abs(m), abs(mp))
+        got = np.array([cd[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
+        assert np.abs(got - want[p_, l0:]).max() <= 1e-9 * np.abs(c).max(), (m, mp)
+
+
+def test_plan_errors_on_gpu(dev):
+    with pytest.raises(soft.SoftError):
+        soft.Plan(3)
+    with pytest.raises(soft.SoftError):
+        soft.Plan(1024)
+    p = soft.Plan(4)
+    with pytest.raises(ValueError):
+        p.inverse(torch.zeros(10, dtype=torch.complex128, device=dev))
+    with pytest.raises(ValueError):
+        p.forward(torch.zeros((8, 8, 8), dtype=torch.complex64, device=dev))
+    p.close()
+    p.close()
