@@ -107,15 +107,27 @@ __global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__
 // ---------------------------------------------------------------------------
 // Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
 // into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds
-// e(l0 + lp + r; b_j) for j-local jl in the wave's own LDS region; its index
-// is swizzled so that both the per-lane row writes and the MFMA A-operand
-// reads are conflict-free.  A wave's LDS operations complete in order, so the
+// e(l0 + lp + r; b_j) for j-local jl in the wave's own LDS region.  Panel rows
+// past the group's last degree hold values of the continued recurrence; they
+// only reach output rows that are never written.  A wave's LDS operations complete in order, so the
 // panel needs no block barrier; the only barrier per panel is the one before
 // the cross-wave sum, whose buffer alternates between two halves.  The
 // recurrence coefficients of a panel (16 x (alpha, gamma)) sit in scalar
 // registers; the next panel's are loaded before the MFMA phase, which hides
 // their latency.  Four accumulators keep four MFMA chains in flight.
-__device__ __forceinline__ int panel_idx(int jl, int r) { return jl * 16 + (r ^ ((jl >> 1) & 15)); }
+// The swizzle f(jl) = (jl + jl/16) mod 16 keeps the per-lane row writes
+// (jl = lane), the forward A reads (jl = 4s + k, r = lane%16) and the inverse A
+// reads (jl = 16t + lane%16, r = 4s + k) free of bank conflicts whether the LDS
+// serves 16 or 32 lanes of 8 bytes per clock.
+__device__ __forceinline__ int panel_idx(int jl, int r) { return jl * 16 + (r ^ ((jl + (jl >> 4)) & 15)); }
+
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), fenced so the
+// scheduler keeps later loads behind it.
+__device__ __forceinline__ void lds_wait_all() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 template <int NW, int NSUB>
 __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *__restrict__ rec,
@@ -182,21 +194,27 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
         for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                pan[panel_idx(lane, r)] = lp + r < L ? ecur[h] : 0.0;
+                pan[panel_idx(lane, r)] = ecur[h];
                 const double u = fma(c[r].x, x[h], -c[r].y);
                 const double en = fma(u, ecur[h], -eprev[h]);
                 eprev[h] = ecur[h];
                 ecur[h] = en;
             }
+            double a[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) a[s] = pan[panel_idx(4 * s + krow, col)];
             if (h == NSUB - 1) {
+                // LDS and scalar loads share one wait counter: take the A
+                // operands first, then issue the next panel's coefficient loads,
+                // whose latency the MFMAs below then cover.
+                lds_wait_all();
 #pragma unroll
                 for (int r = 0; r < 16; ++r) c[r] = R[lp + 16 + r];
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const double a = pan[panel_idx(4 * s + krow, col)];
-                acc[s & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[h][s], acc[s & 3], 0, 0, 0);
-            }
+            for (int s = 0; s < 16; ++s)
+                acc[s & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xb[h][s], acc[s & 3], 0, 0, 0);
         }
         const v4d tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         // For the FP64 16x16x4 MFMA, register r of lane holds C[lane/16 + 4 r][lane%16].
@@ -223,137 +241,165 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
 }
 
 // ---------------------------------------------------------------------------
-// Inverse DWT: per-lane FMA chains, coefficients broadcast from LDS.
+// Inverse DWT on MFMA: Y[j][c] = sum_l e(l; b_j) F[l][c].
 // ---------------------------------------------------------------------------
-// Lane owns JPL beta samples.  The block gathers its group's coefficients
-// straight from the l-major layout (the inverse reorder: symmetry sign, s_l
-// and optionally V_B applied on the way) together with the recurrence
-// coefficients into LDS, CH degrees at a time, double-buffered and issued two
-// chunks ahead, so HBM latency is paid once per chunk and not once per
-// degree.  Row r of a chunk holds the 16 member values (re, im) and
-// (alpha, gamma); every lane reads it by broadcast.
+// Wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64) outright, so waves only
+// share the staged coefficients.  Every 16 degrees each lane parks e(l; b_j)
+// in the wave's LDS panel; the MFMA A operand is 16 beta samples x 4 degrees
+// of it and the B operand 4 degrees x 16 member columns of the group's
+// coefficients.  Those are gathered by the whole block straight from the
+// l-major layout (the inverse reorder: symmetry sign, s_l and optionally V_B
+// applied on the way) into double-buffered LDS chunks of 32 degrees, issued
+// one chunk ahead; rows past the group's end are zero, so panel rows past it
+// (the continued recurrence) contribute nothing.  The recurrence coefficients
+// arrive through scalar loads issued after the panel's LDS reads.
 constexpr int kChunk = 32;
-constexpr int kRowD = 18;  // doubles per staged row
 
 template <int NT>
-struct InvStage {
-    static constexpr int PER = kChunk * kSlots / NT > 0 ? kChunk * kSlots / NT : 1;  // elements per thread
-    double2 v[PER];
-    double2 r;  // (alpha, gamma) for row threadIdx.x, when < kChunk
+struct InvGather {
+    static constexpr int PER = (kChunk * 16 + NT - 1) / NT;  // doubles per thread
+    double v[PER];
 };
 
-// Gather chunk c of group g into registers.
+// Gather chunk c (degrees c*32 .. c*32+31) of group g: element e = row*16 + col.
 template <int NT>
-__device__ __forceinline__ void inv_gather(InvStage<NT> &st, const PlanView &p, const double2 *__restrict__ rec,
-                                           const double2 *__restrict__ cin, const GroupInfo &gi, int g, int L,
-                                           int c, double v0) {
+__device__ __forceinline__ void inv_gather(InvGather<NT> &st, const PlanView &p, const double *__restrict__ cin,
+                                           const GroupInfo &gi, int g, int L, int c, double v0) {
 #pragma unroll
-    for (int k = 0; k < InvStage<NT>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
-        const int row = e >> 3, slot = e & 7;
+        const int row = e >> 4, col = e & 15, slot = col >> 1;
         const int li = c * kChunk + row;
-        double2 val = make_double2(0.0, 0.0);
-        if (e < kChunk * kSlots && li < L && ((gi.mask >> slot) & 1)) {
+        double val = 0.0;
+        if (e < kChunk * 16 && li < L && ((gi.mask >> slot) & 1)) {
             const int l = gi.m + li;
             int mm, mmp;
             double sign;
             group_member(slot, gi.m, gi.mp, l, mm, mmp, sign);
             const double f = sign * p.rscale[p.goff[g] + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
-            const double2 a = cin[coeff_index(l, mm, mmp)];
-            val = make_double2(a.x * f, a.y * f);
+            val = cin[2 * coeff_index(l, mm, mmp) + (col & 1)] * f;
         }
         st.v[k] = val;
     }
-    if (threadIdx.x < kChunk) st.r = rec[p.goff[g] + c * kChunk + threadIdx.x];  // padded table
 }
 
 template <int NT>
-__device__ __forceinline__ void inv_put(const InvStage<NT> &st, double *buf) {
+__device__ __forceinline__ void inv_put(const InvGather<NT> &st, double *buf) {
 #pragma unroll
-    for (int k = 0; k < InvStage<NT>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
-        if (e < kChunk * kSlots) {
-            const int row = e >> 3, slot = e & 7;
-            buf[row * kRowD + 2 * slot] = st.v[k].x;
-            buf[row * kRowD + 2 * slot + 1] = st.v[k].y;
-        }
-    }
-    if (threadIdx.x < kChunk) {
-        buf[threadIdx.x * kRowD + 16] = st.r.x;
-        buf[threadIdx.x * kRowD + 17] = st.r.y;
+        if (e < kChunk * 16) buf[e] = st.v[k];
     }
 }
 
-template <int NW, int JPL>
+template <int NW, int NSUB>
 __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *__restrict__ rec,
                                                     const double2 *__restrict__ coeffs, double2 *__restrict__ S,
                                                     int apply_v) {
     constexpr int NT = NW * 64;
-    __shared__ __align__(16) double stage[2][kChunk * kRowD];
+    __shared__ double panel[NW][64 * 16];
+    __shared__ double stage[2][kChunk * 16];
     const int g = group_of_block(blockIdx.x, p.G);
     const GroupInfo gi = p.grp[g];
     const int N = p.N;
     const int m = gi.m, mp = gi.mp;
     const int L = p.B - m;
     const int nchunk = (L + kChunk - 1) / kChunk;
-    const double2 *cin = coeffs + (size_t)blockIdx.y * p.Nc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, krow = lane >> 4;
+    const double2 *__restrict__ R = rec + p.goff[g];
+    const double *__restrict__ cin = reinterpret_cast<const double *>(coeffs + (size_t)blockIdx.y * p.Nc);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
 
-    InvStage<NT> st;
-    inv_gather<NT>(st, p, rec, cin, gi, g, L, 0, v0);
+    InvGather<NT> st;
+    inv_gather<NT>(st, p, cin, gi, g, L, 0, v0);
 
-    double x[JPL], ecur[JPL], eprev[JPL], acc[JPL][16];
+    double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
-    for (int h = 0; h < JPL; ++h) {
-        const int j = threadIdx.x + h * NT;
+    for (int h = 0; h < NSUB; ++h) {
+        const int j = (wave * NSUB + h) * 64 + lane;
         x[h] = j < N ? p.cosb[j] : 0.0;
         ecur[h] = j < N ? seed_d(p, g, m, mp, j) : 0.0;
         eprev[h] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) acc[h][c] = 0.0;
     }
+    v4d acc[NSUB][4];
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[h][t] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    double2 c[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[r] = R[r];  // the table is padded past the last group
 
     inv_put<NT>(st, stage[0]);
-    if (nchunk > 1) inv_gather<NT>(st, p, rec, cin, gi, g, L, 1, v0);
+    if (nchunk > 1) inv_gather<NT>(st, p, cin, gi, g, L, 1, v0);
     __syncthreads();
-    for (int c = 0; c < nchunk; ++c) {
-        const double *buf = stage[c & 1];
-        const int rows = L - c * kChunk < kChunk ? L - c * kChunk : kChunk;
-        for (int r = 0; r < rows; ++r) {
-            const double *row = buf + r * kRowD;
-            double f[16];
+
+    double *pan = panel[wave];
+    for (int lp = 0; lp < L; lp += 16) {
+        const int ch = lp / kChunk;
+        const double *fb = stage[ch & 1] + (lp - ch * kChunk) * 16;
+        double bop[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const double2 t = *reinterpret_cast<const double2 *>(row + 2 * q);
-                f[2 * q] = t.x;
-                f[2 * q + 1] = t.y;
-            }
-            const double2 ag = *reinterpret_cast<const double2 *>(row + 16);
+        for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
 #pragma unroll
-            for (int h = 0; h < JPL; ++h) {
+        for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) acc[h][q] = fma(ecur[h], f[q], acc[h][q]);
-                const double u = fma(ag.x, x[h], -ag.y);
+            for (int r = 0; r < 16; ++r) {
+                pan[panel_idx(lane, r)] = ecur[h];
+                const double u = fma(c[r].x, x[h], -c[r].y);
                 const double en = fma(u, ecur[h], -eprev[h]);
                 eprev[h] = ecur[h];
                 ecur[h] = en;
             }
+            double a[4][4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a[t][s] = pan[panel_idx(16 * t + col, 4 * s + krow)];
+            if (h == NSUB - 1) {
+                lds_wait_all();
+#pragma unroll
+                for (int r = 0; r < 16; ++r) c[r] = R[lp + 16 + r];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], bop[s], acc[h][t], 0, 0, 0);
         }
-        if (c + 1 < nchunk) {
-            inv_put<NT>(st, stage[(c + 1) & 1]);
-            if (c + 2 < nchunk) inv_gather<NT>(st, p, rec, cin, gi, g, L, c + 2, v0);
+        // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
+        if (lp + 16 - ch * kChunk == kChunk || lp + 16 >= L) {
+            if (ch + 1 < nchunk) {
+                inv_put<NT>(st, stage[(ch + 1) & 1]);
+                if (ch + 2 < nchunk) inv_gather<NT>(st, p, cin, gi, g, L, ch + 2, v0);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
+    // Register r of lane holds Y[j = 16 t + krow + 4 r][c = col] of tile t.
+    // Transpose through the wave's panel (pairs (re, im) swizzled by j) and
+    // store each slot's beta samples contiguously.
     double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
+    const int slot = col >> 1, part = col & 1;
 #pragma unroll
-    for (int h = 0; h < JPL; ++h) {
-        const int j = threadIdx.x + h * NT;
-        if (j >= N) continue;
+    for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s)
-            if ((gi.mask >> s) & 1) Sg[(size_t)s * N + j] = make_double2(acc[h][2 * s], acc[h][2 * s + 1]);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int jl = 16 * t + krow + 4 * r;
+                pan[jl * 16 + 2 * (slot ^ (jl & 7)) + part] = acc[h][t][r];
+            }
+        const int j = (wave * NSUB + h) * 64 + lane;
+#pragma unroll
+        for (int s2 = 0; s2 < kSlots; ++s2) {
+            const double2 v = *reinterpret_cast<const double2 *>(pan + lane * 16 + 2 * (s2 ^ (lane & 7)));
+            if (j < N && ((gi.mask >> s2) & 1)) Sg[(size_t)s2 * N + j] = v;
+        }
     }
 }
 
@@ -369,7 +415,7 @@ hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double
     const int av = apply_v;
     if (p.B > kMaxB) return hipErrorInvalidValue;
     dim3 grid(p.G, batch);
-    // waves x subsets of 64 j: N <= 64: 1x1; 128: 2x1; 256: 4x1; 512: 4x2; 1024: 8x2.
+    // waves x subsets of 64 j: N <= 64: 1x1; 128: 2x1; 256: 4x1; 512: 8x1; 1024: 8x2.
     if (p.N <= 64)
         hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, p.rec, S, coeffs, av);
     else if (p.N == 128)
@@ -377,7 +423,7 @@ hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double
     else if (p.N == 256)
         hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, p.rec, S, coeffs, av);
     else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_fwd<4, 2>), grid, dim3(256), 0, s, p, p.rec, S, coeffs, av);
+        hipLaunchKernelGGL((k_dwt_fwd<8, 1>), grid, dim3(512), 0, s, p, p.rec, S, coeffs, av);
     else
         hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, p.rec, S, coeffs, av);
     return hipGetLastError();
@@ -385,20 +431,20 @@ hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double
 
 hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *coeffs, double2 *S, bool apply_v,
                           hipStream_t s) {
-    const int av = apply_v;
     if (p.B > kMaxB) return hipErrorInvalidValue;
+    const int av = apply_v;
     dim3 grid(p.G, batch);
-    // waves x beta samples per lane: N <= 64: 1x1; 128: 1x2; 256: 1x4; 512: 2x4; 1024: 4x4.
+    // waves x subsets of 64 j, as for the forward DWT.
     if (p.N <= 64)
         hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
     else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_inv<1, 2>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
+        hipLaunchKernelGGL((k_dwt_inv<2, 1>), grid, dim3(128), 0, s, p, p.rec, coeffs, S, av);
     else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_inv<1, 4>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
+        hipLaunchKernelGGL((k_dwt_inv<4, 1>), grid, dim3(256), 0, s, p, p.rec, coeffs, S, av);
     else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_inv<2, 4>), grid, dim3(128), 0, s, p, p.rec, coeffs, S, av);
+        hipLaunchKernelGGL((k_dwt_inv<8, 1>), grid, dim3(512), 0, s, p, p.rec, coeffs, S, av);
     else
-        hipLaunchKernelGGL((k_dwt_inv<4, 4>), grid, dim3(256), 0, s, p, p.rec, coeffs, S, av);
+        hipLaunchKernelGGL((k_dwt_inv<8, 2>), grid, dim3(512), 0, s, p, p.rec, coeffs, S, av);
     return hipGetLastError();
 }
 
