@@ -23,9 +23,12 @@
  *   coeffs  complex, B(4B^2-1)/3 entries (the count of Sect. 2.4), f°(l,m,m')
  *           at index l(4l^2-1)/3 + (m+l)(2l+1) + (m'+l), 0 <= l < B,
  *           -l <= m, m' <= l.
- *   complex numbers are interleaved (re, im): double2 for SOFT_FP64.
- *   A plan for `batch` functions of one bandwidth expects `batch` grids and
- *   `batch` coefficient vectors stored back to back.
+ *   complex numbers are interleaved (re, im): double2 for SOFT_FP64,
+ *   float2 for SOFT_FP32 and SOFT_FP32_SPLIT.
+ *   A plan for n functions (one bandwidth with soft_plan, mixed bandwidths
+ *   with soft_plan_uneven) expects the n grids back to back, and the n
+ *   coefficient vectors back to back, in the order the functions were given;
+ *   soft_plan_offsets() returns where each one starts.
  *
  * Streams: every transform call is stream-ordered and asynchronous; it
  * enqueues kernels on `stream` and returns.  No call synchronises the device
@@ -52,13 +55,32 @@ extern "C" {
 
 typedef struct soft_plan_s *soft_plan_t;
 
+/*
+ * Arithmetic of a plan.  The recurrence for d (eq. "Wigner_d_recurrence"),
+ * its seeds and the quadrature weights are FP64 in every mode; the modes
+ * differ in the storage of grids, coefficients and intermediates and in the
+ * arithmetic of the FFT and of the DWT contraction (the matrix products of
+ * Sect. 2.4).
+ *   SOFT_FP64        complex128 data; FP64 FFT and FP64 matrix-core DWT.
+ *   SOFT_FP32        complex64 data; FP32 FFT; the DWT contracts FP32 data
+ *                    with d rounded to FP32 on FP32 matrix cores and adds
+ *                    the FP32 partial sums (at most 32 beta samples in the
+ *                    forward, 16 degrees in the inverse) in FP64.
+ *   SOFT_FP32_SPLIT  as SOFT_FP32, but d is split into an FP32 head and an
+ *                    FP32 tail (d = hi + lo to about 2^-48 relative), both
+ *                    contracted, so the DWT error is that of FP32 data rather
+ *                    than of FP32 d; relative error about 1e-6 or below at
+ *                    B <= 512 for data of unit scale.
+ */
 typedef enum {
-    SOFT_FP64 = 0 /* complex128 grids/coefficients, FP64 arithmetic throughout */
+    SOFT_FP64 = 0,
+    SOFT_FP32 = 1,
+    SOFT_FP32_SPLIT = 2
 } soft_precision;
 
 typedef enum {
     SOFT_OK = 0,
-    SOFT_ERR_INVALID = -1,     /* null pointer, B < 1, batch < 1, unknown flag */
+    SOFT_ERR_INVALID = -1,     /* null pointer, B < 1, batch < 1, unknown precision or flag, wrong device */
     SOFT_ERR_UNSUPPORTED = -2, /* valid for the paper but not built here: B not a power of two or B > 512 */
     SOFT_ERR_OOM = -3,         /* device or host allocation failed at plan time */
     SOFT_ERR_HIP = -4          /* a HIP runtime call or kernel launch failed */
@@ -69,23 +91,39 @@ typedef enum {
  * of bandwidth B lives in H_B, degrees l < B).
  *   B          bandwidth, a power of two with 1 <= B <= 512.
  *   batch      number of functions per call (>= 1).
- *   precision  SOFT_FP64.
+ *   precision  a soft_precision.
  *   flags      must be 0.
  *   out        receives the plan handle; unchanged on error.
- * Allocates the plan's device workspace (about 16 (2B)^3 bytes for the FFT
- * intermediate plus 16 (2B)^3 for the per-order-pair beta samples, per
- * function, and 4 B^3 bytes of recurrence tables) and its FP64 tables (quadrature weights, Wigner-d seed
- * constants, FFT twiddles), on the current HIP device; later calls must run
- * with the same device current.  Synchronous.
+ * Allocates the plan's device workspace (per function, about 2 (2B)^3
+ * complex elements for the FFT intermediate and the per-order-pair beta
+ * samples, plus 12 bytes per recurrence row, about B^3/6 rows per bandwidth)
+ * and its tables (quadrature weights, Wigner-d seed constants, FFT
+ * twiddles, symmetry groups, work lists) on the current HIP device; later
+ * calls must run with the same device current.  Synchronous.
  * Returns SOFT_OK, SOFT_ERR_INVALID, SOFT_ERR_UNSUPPORTED, SOFT_ERR_OOM or
  * SOFT_ERR_HIP.
  */
 int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out);
 
 /*
+ * soft_plan_uneven -- plan one call over n functions of mixed bandwidths
+ * (the batched transform over uneven bandwidths: each function keeps its own
+ * B, grid and coefficient count).
+ *   B_list     host array of n bandwidths, each a power of two <= 512, in
+ *              the order the functions are stored; read during the call only.
+ *   n          number of functions (>= 1).
+ *   precision, flags, out   as for soft_plan.
+ * Functions of equal B share one set of tables.  The FFT passes run once
+ * per distinct B; the DWT runs as one launch over all functions with
+ * 2B <= 256 (largest recurrence first) plus one per larger bandwidth.
+ * Returns as soft_plan.
+ */
+int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, soft_plan_t *out);
+
+/*
  * soft_plan_sizes -- element counts of one call's buffers.
- *   grid_elems   complex elements of all grids of the batch (batch * (2B)^3).
- *   coeff_elems  complex elements of all coefficient vectors (batch * B(4B^2-1)/3).
+ *   grid_elems   complex elements of all grids of the plan (sum of (2B)^3).
+ *   coeff_elems  complex elements of all coefficient vectors (sum of B(4B^2-1)/3).
  *   workspace_bytes  device bytes the plan holds.
  * Any output pointer may be NULL.  Returns SOFT_OK or SOFT_ERR_INVALID.
  */
@@ -93,10 +131,21 @@ int soft_plan_sizes(soft_plan_t plan, size_t *grid_elems, size_t *coeff_elems,
                     size_t *workspace_bytes);
 
 /*
+ * soft_plan_offsets -- start of each function's grid and coefficients.
+ *   grid_offsets   host array of n+1 entries (or NULL): element offset of
+ *                  function f's grid in the grid buffer; entry n = total.
+ *   coeff_offsets  host array of n+1 entries (or NULL): the same for the
+ *                  coefficient buffer.
+ * Offsets count complex elements of the plan's precision.
+ * Returns SOFT_OK or SOFT_ERR_INVALID.
+ */
+int soft_plan_offsets(soft_plan_t plan, size_t *grid_offsets, size_t *coeff_offsets);
+
+/*
  * soft_forward -- FSOFT (eq. "quadrature" via Sect. 2.4): coefficients of
  * the sampled functions.
- *   grid    device pointer, batch grids (read only).
- *   coeffs  device pointer, batch coefficient vectors (written).
+ *   grid    device pointer, the plan's grids (read only).
+ *   coeffs  device pointer, the plan's coefficient vectors (written).
  *   stream  HIP stream the work is enqueued on (0 = null stream).
  * The input grid need not be band-limited; the result is the quadrature sum.
  */
@@ -105,8 +154,8 @@ int soft_forward(soft_plan_t plan, const void *grid, void *coeffs, hipStream_t s
 /*
  * soft_inverse -- iFSOFT (eq. "fourier_representation" sampled on the grid,
  * computed as T_B^T per order pair then a 2-D FFT per beta sample).
- *   coeffs  device pointer, batch coefficient vectors (read only).
- *   grid    device pointer, batch grids (written).
+ *   coeffs  device pointer, the plan's coefficient vectors (read only).
+ *   grid    device pointer, the plan's grids (written).
  */
 int soft_inverse(soft_plan_t plan, const void *coeffs, void *grid, hipStream_t stream);
 
@@ -131,7 +180,9 @@ int soft_adjoint_inverse(soft_plan_t plan, const void *grid, void *coeffs, hipSt
  * records a HIP event on its stream before and after each kernel it enqueues;
  * soft_plan_stage_times() waits for the recorded events and returns, per
  * stage, the summed elapsed milliseconds and the number of launches timed.
- * Stages (SOFT_STAGE_*), each one kernel:
+ * A plan of several bandwidths launches the FFT stages once per distinct B
+ * and the DWT stages once per launch shape; each launch counts once.
+ * Stages (SOFT_STAGE_*):
  *   0 gamma FFT (forward)      1 alpha FFT + weights (forward)
  *   2 DWT, writing f° (fwd)    3 iDWT, reading f° (inverse)
  *   4 alpha FFT (inverse)      5 gamma FFT (inverse)

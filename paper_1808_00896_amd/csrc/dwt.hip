@@ -1,5 +1,7 @@
 // dwt.hip -- discrete Wigner transform (DWT) and its transpose (iDWT) on
-// gfx950, in FP64, for every symmetry group of order pairs.
+// gfx950 for every symmetry group of order pairs: FP64 (v_mfma_f64_16x16x4)
+// or, for complex64 plans, FP32 MFMA (v_mfma_f32_16x16x4) with d rounded to
+// FP32 or split into hi + lo FP32 parts.
 //
 // Matrix form of Sect. 2.4: for each (m, m'),
 //   forward  f°(l) = (2l+1)/(8 pi B) sum_j d(l,m,m';b_j) w_B(j) S(m,m';j)   (V T W)
@@ -16,19 +18,24 @@
 //
 // d_rep is never stored: each lane owns one beta_j, seeds d(l0,l0,m';b_j)
 // (Sect. 2.2, evaluated in log space with double-double exponents) and runs
-// the three-term recurrence of eq. "Wigner_d_recurrence" in registers.  One
-// block handles one group, so one recurrence feeds all of its members.
-//   inverse: the contraction over l is a per-lane FMA chain against the
-//            coefficients, which are uniform across the wave (scalar loads);
-//   forward: the contraction over j is a reduction across lanes; every 16
-//            degrees the lanes park d in an LDS panel and v_mfma_f64_16x16x4
-//            reduces panel x X (16 l x 16 columns) over j at full FP64 rate.
+// the three-term recurrence of eq. "Wigner_d_recurrence" in FP64 registers.
+// One block handles one (function, group) work item, so one recurrence feeds
+// all members.  Every 16 degrees the lanes park the recurrence values in an
+// LDS panel, which becomes the A operand of the MFMA contraction:
+//   forward: 16 degrees x 4 beta samples (A) times 4 samples x 16 member
+//            columns (B, the FFT output) reduce over beta; waves own disjoint
+//            beta ranges and are summed in FP64 once per panel;
+//   inverse: 16 samples x 4 degrees (A) times 4 degrees x 16 columns (B, the
+//            coefficients) reduce over degrees inside each wave.
+// In the FP32 modes the partial sums over one k-slot (16 beta samples) or one
+// panel (16 degrees) are FP32 and are combined in FP64.
 #include "soft_internal.h"
 
 namespace soft {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxB = 512;
 
@@ -103,18 +110,8 @@ __global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__
 }
 
 // ---------------------------------------------------------------------------
-// Forward DWT: panel x X on MFMA.
+// Shared pieces
 // ---------------------------------------------------------------------------
-// Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
-// into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds
-// e(l0 + lp + r; b_j) for j-local jl in the wave's own LDS region.  Panel rows
-// past the group's last degree hold values of the continued recurrence; they
-// only reach output rows that are never written.  A wave's LDS operations complete in order, so the
-// panel needs no block barrier; the only barrier per panel is the one before
-// the cross-wave sum, whose buffer alternates between two halves.  The
-// recurrence coefficients of a panel (16 x (alpha, gamma)) sit in scalar
-// registers; the next panel's are loaded before the MFMA phase, which hides
-// their latency.  Four accumulators keep four MFMA chains in flight.
 // The swizzle f(jl) = (jl + jl/16) mod 16 keeps the per-lane row writes
 // (jl = lane), the forward A reads (jl = 4s + k, r = lane%16) and the inverse A
 // reads (jl = 16t + lane%16, r = 4s + k) free of bank conflicts whether the LDS
@@ -129,26 +126,78 @@ __device__ __forceinline__ void lds_wait_all() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int NW, int NSUB>
-__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *__restrict__ rec,
-                                                    const double2 *__restrict__ S, double2 *__restrict__ coeffs,
-                                                    int apply_v) {
+// Work item of a block: runs of 64 items are re-dealt so that one XCD gets 8
+// consecutive items (8 neighbouring groups of one function, whose scattered
+// 16-byte coefficient accesses then meet in one L2); the list itself is
+// largest-cost first.
+__device__ __forceinline__ int item_of_block(int b, int n) {
+    if (b >= (n & ~63)) return b;
+    return (b & ~63) + ((b & 7) << 3) + ((b >> 3) & 7);
+}
+
+// Panel entry for the precision: FP64 stores e; FP32 stores (hi, lo) floats
+// in the same 8 bytes (lo = e - hi, used by the split mode).
+template <int PR>
+__device__ __forceinline__ void panel_put(double *slotp, double e) {
+    if constexpr (PR == P64) {
+        *slotp = e;
+    } else {
+        const float hi = (float)e;
+        const float lo = PR == P32S ? (float)(e - (double)hi) : 0.0f;
+        *reinterpret_cast<float2 *>(slotp) = make_float2(hi, lo);
+    }
+}
+
+// MFMA output rows: FP64 16x16x4 puts C[lane/16 + 4 r] in register r, FP32
+// 16x16x4 puts C[4 (lane/16) + r].
+template <int PR>
+__device__ __forceinline__ int out_row(int krow, int r) {
+    return PR == P64 ? krow + 4 * r : 4 * krow + r;
+}
+
+// ---------------------------------------------------------------------------
+// Forward DWT: panel x X on MFMA.
+// ---------------------------------------------------------------------------
+// Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
+// into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds the
+// recurrence value at degree l0 + lp + r for j-local jl in the wave's own LDS
+// region.  Panel rows past the group's last degree hold values of the
+// continued recurrence; they only reach output rows that are never written.
+// A wave's LDS operations complete in order, so the panel needs no block
+// barrier; the only barrier per panel is the one before the cross-wave FP64
+// sum, whose buffer alternates between two halves.  The recurrence
+// coefficients of a panel (16 x (alpha, gamma)) sit in scalar registers; the
+// next panel's are loaded after this panel's LDS reads, behind the MFMAs.
+// Four accumulators keep four MFMA chains in flight (in the FP32 modes each
+// covers 16 beta samples; the split mode keeps the lo products apart).
+template <int NW, int NSUB, int PR>
+__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(const PlanView *__restrict__ views,
+                                                    const WorkItem *__restrict__ items, int nitems,
+                                                    const double2 *__restrict__ rec,
+                                                    const typename PrecT<PR>::C *__restrict__ S,
+                                                    typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
+    using C = typename PrecT<PR>::C;
+    using R = typename PrecT<PR>::R;
     __shared__ double panel[NW][64 * 16];
     __shared__ double red[2][NW][256];
     __shared__ double srow[kMaxB];
-    const int g = group_of_block(blockIdx.x, p.G);
+    const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
+    const PlanView p = views[it.band];
+    const FuncInfo fi = p.funcs[it.func];
+    const int g = it.g;
     const GroupInfo gi = p.grp[g];
     const int N = p.N;
     const int m = gi.m, mp = gi.mp;
     const int L = p.B - m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double2 *__restrict__ R = rec + p.goff[g];
+    const long long goff = p.goff[g];
+    const double2 *__restrict__ Rr = rec + goff;
 
-    const double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
+    const C *Sg = S + fi.s_off + (size_t)g * kSlots * N;
     // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
     const int col = lane & 15, krow = lane >> 4;
     const bool col_present = (gi.mask >> (col >> 1)) & 1;
-    double xb[NSUB][16];
+    R xb[NSUB][16];
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
@@ -156,11 +205,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const int j = jbase + 4 * s + krow;
-            double v = 0.0;
-            if (col_present && j < N) {
-                const double *e = reinterpret_cast<const double *>(Sg + (size_t)(col >> 1) * N + j);
-                v = e[col & 1];
-            }
+            R v = 0;
+            if (col_present && j < N) v = reinterpret_cast<const R *>(Sg + (size_t)(col >> 1) * N + j)[col & 1];
             xb[h][s] = v;
         }
         const int j = jbase + lane;
@@ -176,50 +222,87 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
 
     double2 c[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) c[r] = R[r];  // the table is padded past the last group
+    for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
 
     // s_l of the group's rows, read in the panel epilogues (visible after the
     // first panel's barrier).
-    for (int t = threadIdx.x; t < L; t += NW * 64) srow[t] = p.rscale[p.goff[g] + t];
+    for (int t = threadIdx.x; t < L; t += NW * 64) srow[t] = p.rscale[goff + t];
     double *pan = panel[wave];
-    double *out = reinterpret_cast<double *>(coeffs + (size_t)blockIdx.y * p.Nc);
-    const double *sl = srow;
+    R *out = reinterpret_cast<R *>(coeffs + fi.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
     int buf = 0;
     for (int lp = 0; lp < L; lp += 16, buf ^= 1) {
-        v4d acc[4];
+        double tot[4];
+        if constexpr (PR == P64) {
+            v4d acc[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) acc[a] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int a = 0; a < 4; ++a) acc[a] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int h = 0; h < NSUB; ++h) {
+            for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                pan[panel_idx(lane, r)] = ecur[h];
-                const double u = fma(c[r].x, x[h], -c[r].y);
-                const double en = fma(u, ecur[h], -eprev[h]);
-                eprev[h] = ecur[h];
-                ecur[h] = en;
+                for (int r = 0; r < 16; ++r) {
+                    panel_put<PR>(&pan[panel_idx(lane, r)], ecur[h]);
+                    const double u = fma(c[r].x, x[h], -c[r].y);
+                    const double en = fma(u, ecur[h], -eprev[h]);
+                    eprev[h] = ecur[h];
+                    ecur[h] = en;
+                }
+                double a[16];
+#pragma unroll
+                for (int s = 0; s < 16; ++s) a[s] = pan[panel_idx(4 * s + krow, col)];
+                if (h == NSUB - 1) {
+                    lds_wait_all();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int s = 0; s < 16; ++s)
+                    acc[s & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xb[h][s], acc[s & 3], 0, 0, 0);
             }
-            double a[16];
 #pragma unroll
-            for (int s = 0; s < 16; ++s) a[s] = pan[panel_idx(4 * s + krow, col)];
-            if (h == NSUB - 1) {
-                // LDS and scalar loads share one wait counter: take the A
-                // operands first, then issue the next panel's coefficient loads,
-                // whose latency the MFMAs below then cover.
-                lds_wait_all();
+            for (int r = 0; r < 4; ++r) tot[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+        } else {
+            v4f acc[4], acl[4];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) c[r] = R[lp + 16 + r];
-                __builtin_amdgcn_sched_barrier(0);
+            for (int a = 0; a < 4; ++a) acc[a] = acl[a] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int h = 0; h < NSUB; ++h) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    panel_put<PR>(&pan[panel_idx(lane, r)], ecur[h]);
+                    const double u = fma(c[r].x, x[h], -c[r].y);
+                    const double en = fma(u, ecur[h], -eprev[h]);
+                    eprev[h] = ecur[h];
+                    ecur[h] = en;
+                }
+                float2 a[16];
+#pragma unroll
+                for (int s = 0; s < 16; ++s)
+                    a[s] = *reinterpret_cast<const float2 *>(&pan[panel_idx(4 * s + krow, col)]);
+                if (h == NSUB - 1) {
+                    lds_wait_all();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    acc[s & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s].x, xb[h][s], acc[s & 3], 0, 0, 0);
+                    if constexpr (PR == P32S)
+                        acl[s & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s].y, xb[h][s], acl[s & 3], 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
-                acc[s & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xb[h][s], acc[s & 3], 0, 0, 0);
+            for (int r = 0; r < 4; ++r) {
+                double t = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) t += (double)acc[a][r] + (PR == P32S ? (double)acl[a][r] : 0.0);
+                tot[r] = t;
+            }
         }
-        const v4d tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        // For the FP64 16x16x4 MFMA, register r of lane holds C[lane/16 + 4 r][lane%16].
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[buf][wave][(krow + 4 * r) * 16 + col] = tot[r];
+        for (int r = 0; r < 4; ++r) red[buf][wave][out_row<PR>(krow, r) * 16 + col] = tot[r];
         __syncthreads();
         // Epilogue (the reorder): column c = 2 slot + part of row lp + r is
         // f°(l, member of slot) up to the slot's symmetry sign, s_l and V_B.
@@ -233,8 +316,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
                 int mm, mmp;
                 double sign;
                 group_member(slot, m, mp, l, mm, mmp, sign);
-                const double f = sign * sl[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
-                out[2 * coeff_index(l, mm, mmp) + (t & 1)] = sum * f;
+                const double f = sign * srow[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
+                out[2 * coeff_index(l, mm, mmp) + (t & 1)] = (R)(sum * f);
             }
         }
     }
@@ -244,29 +327,30 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(PlanView p, const double2 *
 // Inverse DWT on MFMA: Y[j][c] = sum_l e(l; b_j) F[l][c].
 // ---------------------------------------------------------------------------
 // Wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64) outright, so waves only
-// share the staged coefficients.  Every 16 degrees each lane parks e(l; b_j)
-// in the wave's LDS panel; the MFMA A operand is 16 beta samples x 4 degrees
-// of it and the B operand 4 degrees x 16 member columns of the group's
-// coefficients.  Those are gathered by the whole block straight from the
-// l-major layout (the inverse reorder: symmetry sign, s_l and optionally V_B
-// applied on the way) into double-buffered LDS chunks of 32 degrees, issued
-// one chunk ahead; rows past the group's end are zero, so panel rows past it
-// (the continued recurrence) contribute nothing.  The recurrence coefficients
-// arrive through scalar loads issued after the panel's LDS reads.
+// share the staged coefficients.  Every 16 degrees each lane parks its
+// recurrence values in the wave's LDS panel; the MFMA A operand is 16 beta
+// samples x 4 degrees of it and the B operand 4 degrees x 16 member columns of
+// the group's coefficients.  Those are gathered by the whole block straight
+// from the l-major layout (the inverse reorder: symmetry sign, s_l and
+// optionally V_B applied on the way) into double-buffered LDS chunks of 32
+// degrees, issued one chunk ahead; rows past the group's end are zero, so
+// panel rows past it (the continued recurrence) contribute nothing.  The
+// recurrence coefficients arrive through scalar loads issued after the
+// panel's LDS reads.  FP32 modes sum each panel in FP32 and the panels in FP64.
 constexpr int kChunk = 32;
 
-template <int NT>
+template <int NT, typename R>
 struct InvGather {
-    static constexpr int PER = (kChunk * 16 + NT - 1) / NT;  // doubles per thread
-    double v[PER];
+    static constexpr int PER = (kChunk * 16 + NT - 1) / NT;  // values per thread
+    R v[PER];
 };
 
 // Gather chunk c (degrees c*32 .. c*32+31) of group g: element e = row*16 + col.
-template <int NT>
-__device__ __forceinline__ void inv_gather(InvGather<NT> &st, const PlanView &p, const double *__restrict__ cin,
-                                           const GroupInfo &gi, int g, int L, int c, double v0) {
+template <int NT, typename R, typename C>
+__device__ __forceinline__ void inv_gather(InvGather<NT, R> &st, const PlanView &p, const R *__restrict__ cin,
+                                           const GroupInfo &gi, long long goff, int L, int c, double v0) {
 #pragma unroll
-    for (int k = 0; k < InvGather<NT>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
         const int row = e >> 4, col = e & 15, slot = col >> 1;
         const int li = c * kChunk + row;
@@ -276,30 +360,37 @@ __device__ __forceinline__ void inv_gather(InvGather<NT> &st, const PlanView &p,
             int mm, mmp;
             double sign;
             group_member(slot, gi.m, gi.mp, l, mm, mmp, sign);
-            const double f = sign * p.rscale[p.goff[g] + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
-            val = cin[2 * coeff_index(l, mm, mmp) + (col & 1)] * f;
+            const double f = sign * p.rscale[goff + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
+            val = (double)cin[2 * coeff_index(l, mm, mmp) + (col & 1)] * f;
         }
-        st.v[k] = val;
+        st.v[k] = (R)val;
     }
 }
 
-template <int NT>
-__device__ __forceinline__ void inv_put(const InvGather<NT> &st, double *buf) {
+template <int NT, typename R>
+__device__ __forceinline__ void inv_put(const InvGather<NT, R> &st, R *buf) {
 #pragma unroll
-    for (int k = 0; k < InvGather<NT>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
         if (e < kChunk * 16) buf[e] = st.v[k];
     }
 }
 
-template <int NW, int NSUB>
-__global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *__restrict__ rec,
-                                                    const double2 *__restrict__ coeffs, double2 *__restrict__ S,
-                                                    int apply_v) {
+template <int NW, int NSUB, int PR>
+__global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict__ views,
+                                                    const WorkItem *__restrict__ items, int nitems,
+                                                    const double2 *__restrict__ rec,
+                                                    const typename PrecT<PR>::C *__restrict__ coeffs,
+                                                    typename PrecT<PR>::C *__restrict__ S, int apply_v) {
+    using C = typename PrecT<PR>::C;
+    using R = typename PrecT<PR>::R;
     constexpr int NT = NW * 64;
     __shared__ double panel[NW][64 * 16];
-    __shared__ double stage[2][kChunk * 16];
-    const int g = group_of_block(blockIdx.x, p.G);
+    __shared__ R stage[2][kChunk * 16];
+    const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
+    const PlanView p = views[it.band];
+    const FuncInfo fi = p.funcs[it.func];
+    const int g = it.g;
     const GroupInfo gi = p.grp[g];
     const int N = p.N;
     const int m = gi.m, mp = gi.mp;
@@ -307,12 +398,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *
     const int nchunk = (L + kChunk - 1) / kChunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
-    const double2 *__restrict__ R = rec + p.goff[g];
-    const double *__restrict__ cin = reinterpret_cast<const double *>(coeffs + (size_t)blockIdx.y * p.Nc);
+    const long long goff = p.goff[g];
+    const double2 *__restrict__ Rr = rec + goff;
+    const R *__restrict__ cin = reinterpret_cast<const R *>(coeffs + fi.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
 
-    InvGather<NT> st;
-    inv_gather<NT>(st, p, cin, gi, g, L, 0, v0);
+    InvGather<NT, R> st;
+    inv_gather<NT, R, C>(st, p, cin, gi, goff, L, 0, v0);
 
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
@@ -330,60 +422,87 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *
 
     double2 c[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) c[r] = R[r];  // the table is padded past the last group
+    for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
 
-    inv_put<NT>(st, stage[0]);
-    if (nchunk > 1) inv_gather<NT>(st, p, cin, gi, g, L, 1, v0);
+    inv_put<NT, R>(st, stage[0]);
+    if (nchunk > 1) inv_gather<NT, R, C>(st, p, cin, gi, goff, L, 1, v0);
     __syncthreads();
 
     double *pan = panel[wave];
     for (int lp = 0; lp < L; lp += 16) {
         const int ch = lp / kChunk;
-        const double *fb = stage[ch & 1] + (lp - ch * kChunk) * 16;
-        double bop[4];
+        const R *fb = stage[ch & 1] + (lp - ch * kChunk) * 16;
+        R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
 #pragma unroll
         for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                pan[panel_idx(lane, r)] = ecur[h];
+                panel_put<PR>(&pan[panel_idx(lane, r)], ecur[h]);
                 const double u = fma(c[r].x, x[h], -c[r].y);
                 const double en = fma(u, ecur[h], -eprev[h]);
                 eprev[h] = ecur[h];
                 ecur[h] = en;
             }
-            double a[4][4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) a[t][s] = pan[panel_idx(16 * t + col, 4 * s + krow)];
-            if (h == NSUB - 1) {
-                lds_wait_all();
-#pragma unroll
-                for (int r = 0; r < 16; ++r) c[r] = R[lp + 16 + r];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
+            if constexpr (PR == P64) {
+                double a[4][4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], bop[s], acc[h][t], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) a[t][s] = pan[panel_idx(16 * t + col, 4 * s + krow)];
+                if (h == NSUB - 1) {
+                    lds_wait_all();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], bop[s], acc[h][t], 0, 0, 0);
+            } else {
+                float2 a[4][4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        a[t][s] = *reinterpret_cast<const float2 *>(&pan[panel_idx(16 * t + col, 4 * s + krow)]);
+                if (h == NSUB - 1) {
+                    lds_wait_all();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    v4f ap = {0.f, 0.f, 0.f, 0.f}, al = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        ap = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s].x, bop[s], ap, 0, 0, 0);
+                        if constexpr (PR == P32S)
+                            al = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s].y, bop[s], al, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[h][t][r] += (double)ap[r] + (PR == P32S ? (double)al[r] : 0.0);
+                }
+            }
         }
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
         if (lp + 16 - ch * kChunk == kChunk || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
-                inv_put<NT>(st, stage[(ch + 1) & 1]);
-                if (ch + 2 < nchunk) inv_gather<NT>(st, p, cin, gi, g, L, ch + 2, v0);
+                inv_put<NT, R>(st, stage[(ch + 1) & 1]);
+                if (ch + 2 < nchunk) inv_gather<NT, R, C>(st, p, cin, gi, goff, L, ch + 2, v0);
             }
             __syncthreads();
         }
     }
 
-    // Register r of lane holds Y[j = 16 t + krow + 4 r][c = col] of tile t.
+    // Register r of lane holds Y[j = 16 t + out_row(krow, r)][c = col] of tile t.
     // Transpose through the wave's panel (pairs (re, im) swizzled by j) and
     // store each slot's beta samples contiguously.
-    double2 *Sg = S + (size_t)blockIdx.y * ((size_t)p.G * kSlots * N) + (size_t)g * kSlots * N;
+    C *Sg = S + fi.s_off + (size_t)g * kSlots * N;
     const int slot = col >> 1, part = col & 1;
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
@@ -391,14 +510,17 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(PlanView p, const double2 *
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int jl = 16 * t + krow + 4 * r;
+                const int jl = 16 * t + out_row<PR>(krow, r);
                 pan[jl * 16 + 2 * (slot ^ (jl & 7)) + part] = acc[h][t][r];
             }
         const int j = (wave * NSUB + h) * 64 + lane;
 #pragma unroll
         for (int s2 = 0; s2 < kSlots; ++s2) {
             const double2 v = *reinterpret_cast<const double2 *>(pan + lane * 16 + 2 * (s2 ^ (lane & 7)));
-            if (j < N && ((gi.mask >> s2) & 1)) Sg[(size_t)s2 * N + j] = v;
+            C o;
+            o.x = (R)v.x;
+            o.y = (R)v.y;
+            if (j < N && ((gi.mask >> s2) & 1)) Sg[(size_t)s2 * N + j] = o;
         }
     }
 }
@@ -410,42 +532,59 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
     return hipGetLastError();
 }
 
-hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *coeffs, bool apply_v,
-                          hipStream_t s) {
+// Launch shapes (waves x subsets of 64 beta samples): 1x1, 2x1, 4x1, 8x1, 8x2
+// for 2B <= 64, 128, 256, 512, 1024.
+template <int PR>
+hipError_t launch_dwt_fwd(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
+                          const double2 *rec, const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs,
+                          bool apply_v, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
     const int av = apply_v;
-    if (p.B > kMaxB) return hipErrorInvalidValue;
-    dim3 grid(p.G, batch);
-    // waves x subsets of 64 j: N <= 64: 1x1; 128: 2x1; 256: 4x1; 512: 8x1; 1024: 8x2.
-    if (p.N <= 64)
-        hipLaunchKernelGGL((k_dwt_fwd<1, 1>), grid, dim3(64), 0, s, p, p.rec, S, coeffs, av);
-    else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_fwd<2, 1>), grid, dim3(128), 0, s, p, p.rec, S, coeffs, av);
-    else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_fwd<4, 1>), grid, dim3(256), 0, s, p, p.rec, S, coeffs, av);
-    else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_fwd<8, 1>), grid, dim3(512), 0, s, p, p.rec, S, coeffs, av);
-    else
-        hipLaunchKernelGGL((k_dwt_fwd<8, 2>), grid, dim3(512), 0, s, p, p.rec, S, coeffs, av);
-    return hipGetLastError();
+    const dim3 grid(nitems);
+#define SOFT_DWT_FWD(NW_, NS_)                                                                               \
+    if (nw == NW_ && nsub == NS_) {                                                                          \
+        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, views, items, nitems, rec, \
+                           S, coeffs, av);                                                                   \
+        return hipGetLastError();                                                                            \
+    }
+    SOFT_DWT_FWD(1, 1)
+    SOFT_DWT_FWD(2, 1)
+    SOFT_DWT_FWD(4, 1)
+    SOFT_DWT_FWD(8, 1)
+    SOFT_DWT_FWD(8, 2)
+#undef SOFT_DWT_FWD
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *coeffs, double2 *S, bool apply_v,
-                          hipStream_t s) {
-    if (p.B > kMaxB) return hipErrorInvalidValue;
+template <int PR>
+hipError_t launch_dwt_inv(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
+                          const double2 *rec, const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S,
+                          bool apply_v, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
     const int av = apply_v;
-    dim3 grid(p.G, batch);
-    // waves x subsets of 64 j, as for the forward DWT.
-    if (p.N <= 64)
-        hipLaunchKernelGGL((k_dwt_inv<1, 1>), grid, dim3(64), 0, s, p, p.rec, coeffs, S, av);
-    else if (p.N == 128)
-        hipLaunchKernelGGL((k_dwt_inv<2, 1>), grid, dim3(128), 0, s, p, p.rec, coeffs, S, av);
-    else if (p.N == 256)
-        hipLaunchKernelGGL((k_dwt_inv<4, 1>), grid, dim3(256), 0, s, p, p.rec, coeffs, S, av);
-    else if (p.N == 512)
-        hipLaunchKernelGGL((k_dwt_inv<8, 1>), grid, dim3(512), 0, s, p, p.rec, coeffs, S, av);
-    else
-        hipLaunchKernelGGL((k_dwt_inv<8, 2>), grid, dim3(512), 0, s, p, p.rec, coeffs, S, av);
-    return hipGetLastError();
+    const dim3 grid(nitems);
+#define SOFT_DWT_INV(NW_, NS_)                                                                               \
+    if (nw == NW_ && nsub == NS_) {                                                                          \
+        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, views, items, nitems, rec, \
+                           coeffs, S, av);                                                                   \
+        return hipGetLastError();                                                                            \
+    }
+    SOFT_DWT_INV(1, 1)
+    SOFT_DWT_INV(2, 1)
+    SOFT_DWT_INV(4, 1)
+    SOFT_DWT_INV(8, 1)
+    SOFT_DWT_INV(8, 2)
+#undef SOFT_DWT_INV
+    return hipErrorInvalidValue;
 }
+
+#define SOFT_DWT_INSTANTIATE(PR)                                                                              \
+    template hipError_t launch_dwt_fwd<PR>(const PlanView *, const WorkItem *, int, int, int, const double2 *, \
+                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);           \
+    template hipError_t launch_dwt_inv<PR>(const PlanView *, const WorkItem *, int, int, int, const double2 *, \
+                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);
+SOFT_DWT_INSTANTIATE(P64)
+SOFT_DWT_INSTANTIATE(P32)
+SOFT_DWT_INSTANTIATE(P32S)
 
 }  // namespace soft

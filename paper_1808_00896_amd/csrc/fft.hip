@@ -26,11 +26,41 @@
 namespace soft {
 namespace {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex helpers for double2 (FP64 plans) and float2 (FP32 plans).
+template <typename C>
+__device__ __forceinline__ C mk(double x, double y);
+template <>
+__device__ __forceinline__ double2 mk<double2>(double x, double y) { return make_double2(x, y); }
+template <>
+__device__ __forceinline__ float2 mk<float2>(double x, double y) { return make_float2((float)x, (float)y); }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+    C r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+    C r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <typename C>
+__device__ __forceinline__ C cscale(C a, double w) {
+    C r;
+    r.x = a.x * (decltype(a.x))w;
+    r.y = a.y * (decltype(a.y))w;
+    return r;
+}
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
@@ -47,35 +77,43 @@ __device__ constexpr double kSin16[16] = {
     -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
 
 // a * e^{SIGN 2 pi i j / R} for a compile-time j and R | 16.
-template <int R, int J, int SIGN>
-__device__ __forceinline__ double2 twc(double2 a) {
+template <int R, int J, int SIGN, typename C>
+__device__ __forceinline__ C twc(C a) {
+    using T = decltype(a.x);
     constexpr int jj = (J % R) * (16 / R);
+    C r;
     if constexpr (jj == 0) {
         return a;
     } else if constexpr (jj == 4) {
-        return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+        if (SIGN > 0) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+        return r;
     } else if constexpr (jj == 8) {
-        return make_double2(-a.x, -a.y);
+        r.x = -a.x;
+        r.y = -a.y;
+        return r;
     } else if constexpr (jj == 12) {
-        return SIGN > 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+        if (SIGN > 0) { r.x = a.y; r.y = -a.x; } else { r.x = -a.y; r.y = a.x; }
+        return r;
     } else {
-        const double c = kCos16[jj], s = SIGN * kSin16[jj];
-        return make_double2(a.x * c - a.y * s, a.x * s + a.y * c);
+        const T c = (T)kCos16[jj], s = (T)(SIGN * kSin16[jj]);
+        r.x = a.x * c - a.y * s;
+        r.y = a.x * s + a.y * c;
+        return r;
     }
 }
 
 // In-register DFT of R points: X[k] = sum_n x[n] e^{SIGN 2 pi i n k / R}.
-template <int R, int SIGN>
-__device__ __forceinline__ void dft(double2 *v) {
+template <int R, int SIGN, typename C>
+__device__ __forceinline__ void dft(C *v) {
     if constexpr (R == 1) {
         return;
     } else if constexpr (R == 2) {
-        const double2 a = v[0], b = v[1];
+        const C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     } else if constexpr (R == 4) {
-        const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-        const double2 a2 = cadd(v[1], v[3]), a3 = twc<4, 1, SIGN>(csub(v[1], v[3]));
+        const C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const C a2 = cadd(v[1], v[3]), a3 = twc<4, 1, SIGN>(csub(v[1], v[3]));
         v[0] = cadd(a0, a2);
         v[1] = cadd(a1, a3);
         v[2] = csub(a0, a2);
@@ -84,13 +122,13 @@ __device__ __forceinline__ void dft(double2 *v) {
         // R = 4 * Bq: n = Bq n1 + n2, k = k1 + 4 k2; inner DFT-4 over n1,
         // twiddle e^{SIGN 2 pi i n2 k1 / R}, outer DFT-Bq over n2.
         constexpr int A = 4, Bq = R / 4;
-        double2 y[Bq][A];
+        C y[Bq][A];
 #pragma unroll
         for (int n2 = 0; n2 < Bq; ++n2) {
-            double2 a[A];
+            C a[A];
 #pragma unroll
             for (int n1 = 0; n1 < A; ++n1) a[n1] = v[Bq * n1 + n2];
-            dft<A, SIGN>(a);
+            dft<A, SIGN, C>(a);
             y[n2][0] = a[0];
             if (n2 == 0) {
                 y[0][1] = a[1];
@@ -112,10 +150,10 @@ __device__ __forceinline__ void dft(double2 *v) {
         }
 #pragma unroll
         for (int k1 = 0; k1 < A; ++k1) {
-            double2 b[Bq];
+            C b[Bq];
 #pragma unroll
             for (int n2 = 0; n2 < Bq; ++n2) b[n2] = y[n2][k1];
-            dft<Bq, SIGN>(b);
+            dft<Bq, SIGN, C>(b);
 #pragma unroll
             for (int k2 = 0; k2 < Bq; ++k2) v[k1 + A * k2] = b[k2];
         }
@@ -163,8 +201,8 @@ constexpr int ns_of() {  // product of the radices before stage S
 __device__ __forceinline__ int lds_pos(int t, int idx, int RS) { return t * RS + idx + (idx >> 4); }
 
 // Twiddle and butterfly all of a thread's radix-R butterflies of stage S.
-template <int N, int S, int SIGN>
-__device__ __forceinline__ void run_stage(double2 (&v)[Shape<N>::E], int p, const double2 *__restrict__ tw) {
+template <int N, int S, int SIGN, typename C>
+__device__ __forceinline__ void run_stage(C (&v)[Shape<N>::E], int p, const C *__restrict__ tw) {
     constexpr int R = radix_of<N, S>(), NS = ns_of<N, S>();
     constexpr int P = Shape<N>::P, BPT = N / R / P;
 #pragma unroll
@@ -175,13 +213,13 @@ __device__ __forceinline__ void run_stage(double2 (&v)[Shape<N>::E], int p, cons
 #pragma unroll
             for (int r = 1; r < R; ++r) v[k * R + r] = cmul(v[k * R + r], tw[kk * r * (N / (R * NS))]);
         }
-        dft<R, SIGN>(&v[k * R]);
+        dft<R, SIGN, C>(&v[k * R]);
     }
 }
 
 // Stage S outputs -> LDS (row t), element (b/NS)*NS*R + b%NS + r*NS.
-template <int N, int S>
-__device__ __forceinline__ void put_stage(const double2 (&v)[Shape<N>::E], double2 *lds, int t, int p) {
+template <int N, int S, typename C>
+__device__ __forceinline__ void put_stage(const C (&v)[Shape<N>::E], C *lds, int t, int p) {
     constexpr int R = radix_of<N, S>(), NS = ns_of<N, S>();
     constexpr int P = Shape<N>::P, BPT = N / R / P, RS = Shape<N>::RS;
 #pragma unroll
@@ -194,8 +232,8 @@ __device__ __forceinline__ void put_stage(const double2 (&v)[Shape<N>::E], doubl
 }
 
 // Stage S inputs <- LDS (row t), element b + r*N/R.
-template <int N, int S>
-__device__ __forceinline__ void get_stage(double2 (&v)[Shape<N>::E], const double2 *lds, int t, int p) {
+template <int N, int S, typename C>
+__device__ __forceinline__ void get_stage(C (&v)[Shape<N>::E], const C *lds, int t, int p) {
     constexpr int R = radix_of<N, S>();
     constexpr int P = Shape<N>::P, BPT = N / R / P, RS = Shape<N>::RS;
 #pragma unroll
@@ -227,32 +265,60 @@ __device__ __forceinline__ BlockPos block_pos(int ntile, int nline) {
     return {lin % ntile, lin / ntile, (int)blockIdx.z};
 }
 
-// One pass.  Element addresses per kind:
+// Twiddle table of a band for the complex type of the plan.
+template <typename C>
+__device__ __forceinline__ const C *twiddles(const PlanView &p, int sign);
+template <>
+__device__ __forceinline__ const double2 *twiddles<double2>(const PlanView &p, int sign) {
+    return sign > 0 ? p.twp : p.twm;
+}
+template <>
+__device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int sign) {
+    return sign > 0 ? p.twpf : p.twmf;
+}
+
+// One pass over the functions of one band (blockIdx.z = index within the
+// band; t1 holds one N^3 intermediate per such index).  Element addresses:
 //   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out t1[(q*N + j)*N + i]
 //   ALPHA_FWD: block (j-tile, q): in t1[(q*N + j)*N + i],   out S[slot*N + j']
 //   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],         out t1[(q*N + j)*N + i]
 //   GAMMA_INV: block (i-tile, j): in t1[(q*N + j)*N + i],    out grid[(i*N + j)*N + k]
-template <int N, int KIND, int SIGN>
-__global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const double2 *__restrict__ in,
-                                                     double2 *__restrict__ out, int apply_w) {
+template <int N, int KIND, int SIGN, typename C>
+__global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
+                                                     int apply_w) {
     using Sh = Shape<N>;
     constexpr int T = Sh::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
     constexpr int B = N / 2;
     constexpr int LAST = NSTG - 1;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
-    __shared__ double2 lds[Sh::LDS];
-    const double2 *tw = SIGN > 0 ? p.twp : p.twm;
+    __shared__ C lds[Sh::LDS];
+    const C *tw = twiddles<C>(p, SIGN);
 
     // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
     const BlockPos bp = block_pos(N / T, ALPHA ? N - 1 : N);
     const int tile = bp.tile;
     const int line = ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line;
     const size_t N3 = (size_t)N * N * N;
-    const size_t SB = (size_t)p.G * kSlots * N;
+    const FuncInfo fi = p.funcs[p.band_funcs[bp.batch]];
+    const C *src;
+    C *dst;
+    if constexpr (KIND == GAMMA_FWD) {
+        src = in + fi.grid_off;
+        dst = out + bp.batch * N3;
+    } else if constexpr (KIND == ALPHA_FWD) {
+        src = in + bp.batch * N3;
+        dst = out + fi.s_off;
+    } else if constexpr (KIND == ALPHA_INV) {
+        src = in + fi.s_off;
+        dst = out + bp.batch * N3;
+    } else {
+        src = in + bp.batch * N3;
+        dst = out + fi.grid_off;
+    }
     const int tid = threadIdx.x;
     const int mp_line = line < B ? line : line - N;  // m' of an alpha-pass block
 
-    double2 v[E];
+    C v[E];
     // ---- stage 0 inputs from HBM: element b + r*N/R ----
     const int t_in = transposed_in<KIND>() ? tid % T : tid / P;
     const int p_in = transposed_in<KIND>() ? tid / T : tid % P;
@@ -264,45 +330,45 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const double2 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int n = p_in + k * P + r * (N / R);
-                double2 x;
+                C x;
                 if constexpr (KIND == GAMMA_FWD) {
-                    x = in[bp.batch * N3 + ((size_t)row * N + line) * N + n];
+                    x = src[((size_t)row * N + line) * N + n];
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    x = in[bp.batch * N3 + ((size_t)line * N + row) * N + n];
+                    x = src[((size_t)line * N + row) * N + n];
                 } else if constexpr (KIND == ALPHA_INV) {
                     if (n == B) {
-                        x = make_double2(0.0, 0.0);
+                        x = mk<C>(0.0, 0.0);
                     } else {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
-                        x = in[bp.batch * SB + (size_t)(sl >> 1) * N + jj];
+                        x = src[(size_t)(sl >> 1) * N + jj];
                     }
                 } else {
-                    x = n == B ? make_double2(0.0, 0.0) : in[bp.batch * N3 + ((size_t)n * N + line) * N + row];
+                    x = n == B ? mk<C>(0.0, 0.0) : src[((size_t)n * N + line) * N + row];
                 }
                 v[k * R + r] = x;
             }
         }
     }
-    run_stage<N, 0, SIGN>(v, p_in, tw);
+    run_stage<N, 0, SIGN, C>(v, p_in, tw);
 
     // ---- exchanges through LDS (lane order: row index fastest) ----
     int t_out = t_in, p_out = p_in;
     if constexpr (NSTG > 1) {
         const int t = tid / P, pp = tid % P;
-        put_stage<N, 0>(v, lds, t_in, p_in);
+        put_stage<N, 0, C>(v, lds, t_in, p_in);
         __syncthreads();
         if constexpr (NSTG > 2) {
-            get_stage<N, 1>(v, lds, t, pp);
-            run_stage<N, 1, SIGN>(v, pp, tw);
+            get_stage<N, 1, C>(v, lds, t, pp);
+            run_stage<N, 1, SIGN, C>(v, pp, tw);
             __syncthreads();
-            put_stage<N, 1>(v, lds, t, pp);
+            put_stage<N, 1, C>(v, lds, t, pp);
             __syncthreads();
         }
         t_out = transposed_out<KIND>() ? tid % T : t;
         p_out = transposed_out<KIND>() ? tid / T : pp;
-        get_stage<N, LAST>(v, lds, t_out, p_out);
-        run_stage<N, LAST, SIGN>(v, p_out, tw);
+        get_stage<N, LAST, C>(v, lds, t_out, p_out);
+        run_stage<N, LAST, SIGN, C>(v, p_out, tw);
     }
 
     // ---- last stage outputs to HBM: element b + r*N/R ----
@@ -318,71 +384,78 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const double2 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int n = p_out + k * P + r * (N / R);
-                const double2 x = v[k * R + r];
+                const C x = v[k * R + r];
                 if constexpr (KIND == GAMMA_FWD) {
-                    if (n != B) out[bp.batch * N3 + ((size_t)n * N + line) * N + row] = x;
+                    if (n != B) dst[((size_t)n * N + line) * N + row] = x;
                 } else if constexpr (KIND == ALPHA_FWD) {
                     if (n != B) {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
-                        out[bp.batch * SB + (size_t)(sl >> 1) * N + jj] = make_double2(x.x * wj, x.y * wj);
+                        dst[(size_t)(sl >> 1) * N + jj] = cscale(x, wj);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
-                    out[bp.batch * N3 + ((size_t)line * N + row) * N + n] = x;
+                    dst[((size_t)line * N + row) * N + n] = x;
                 } else {
-                    out[bp.batch * N3 + ((size_t)row * N + line) * N + n] = make_double2(x.x * wj, x.y * wj);
+                    dst[((size_t)row * N + line) * N + n] = cscale(x, wj);
                 }
             }
         }
     }
 }
 
-template <int N, int KIND, int SIGN>
-hipError_t launch_kind(const PlanView &p, int batch, const double2 *in, double2 *out, int apply_w, hipStream_t s) {
+template <int N, int KIND, int SIGN, typename C>
+hipError_t launch_kind(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
     using Sh = Shape<N>;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
     const int nline = ALPHA ? N - 1 : N;
-    // Grid (tiles, lines, batch); block_pos() re-deals (tile, line) across XCDs.
-    dim3 g(N / Sh::T, nline, batch);
-    hipLaunchKernelGGL((k_fft<N, KIND, SIGN>), g, dim3(Sh::NT), 0, s, p, in, out, apply_w);
+    // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
+    dim3 g(N / Sh::T, nline, p.nfunc);
+    hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Sh::NT), 0, s, p, in, out, apply_w);
     return hipGetLastError();
 }
 
-template <int KIND, int SIGN>
-hipError_t dispatch(const PlanView &p, int batch, const double2 *in, double2 *out, int apply_w, hipStream_t s) {
+template <int KIND, int SIGN, typename C>
+hipError_t dispatch(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
     switch (p.N) {
-        case 2: return launch_kind<2, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 4: return launch_kind<4, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 8: return launch_kind<8, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 16: return launch_kind<16, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 32: return launch_kind<32, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 64: return launch_kind<64, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 128: return launch_kind<128, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 256: return launch_kind<256, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 512: return launch_kind<512, KIND, SIGN>(p, batch, in, out, apply_w, s);
-        case 1024: return launch_kind<1024, KIND, SIGN>(p, batch, in, out, apply_w, s);
+        case 2: return launch_kind<2, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 4: return launch_kind<4, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 8: return launch_kind<8, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 16: return launch_kind<16, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 32: return launch_kind<32, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 64: return launch_kind<64, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 128: return launch_kind<128, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 256: return launch_kind<256, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 512: return launch_kind<512, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 1024: return launch_kind<1024, KIND, SIGN, C>(p, in, out, apply_w, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_fft_gamma_fwd(const PlanView &p, int batch, const double2 *grid, double2 *t1, hipStream_t s) {
-    return dispatch<GAMMA_FWD, +1>(p, batch, grid, t1, 0, s);
+template <typename C>
+hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s) {
+    return dispatch<GAMMA_FWD, +1, C>(p, grid, t1, 0, s);
+}
+template <typename C>
+hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, C *S, bool apply_w, hipStream_t s) {
+    return dispatch<ALPHA_FWD, +1, C>(p, t1, S, (int)apply_w, s);
+}
+template <typename C>
+hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, hipStream_t s) {
+    return dispatch<ALPHA_INV, -1, C>(p, S, t1, 0, s);
+}
+template <typename C>
+hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, hipStream_t s) {
+    return dispatch<GAMMA_INV, -1, C>(p, t1, grid, (int)apply_w, s);
 }
 
-hipError_t launch_fft_alpha_fwd(const PlanView &p, int batch, const double2 *t1, double2 *S, bool apply_w,
-                                hipStream_t s) {
-    return dispatch<ALPHA_FWD, +1>(p, batch, t1, S, (int)apply_w, s);
-}
-
-hipError_t launch_fft_alpha_inv(const PlanView &p, int batch, const double2 *S, double2 *t1, hipStream_t s) {
-    return dispatch<ALPHA_INV, -1>(p, batch, S, t1, 0, s);
-}
-
-hipError_t launch_fft_gamma_inv(const PlanView &p, int batch, const double2 *t1, double2 *grid, bool apply_w,
-                                hipStream_t s) {
-    return dispatch<GAMMA_INV, -1>(p, batch, t1, grid, (int)apply_w, s);
-}
+#define SOFT_FFT_INSTANTIATE(C)                                                                         \
+    template hipError_t launch_fft_gamma_fwd<C>(const PlanView &, const C *, C *, hipStream_t);          \
+    template hipError_t launch_fft_alpha_fwd<C>(const PlanView &, const C *, C *, bool, hipStream_t);    \
+    template hipError_t launch_fft_alpha_inv<C>(const PlanView &, const C *, C *, hipStream_t);          \
+    template hipError_t launch_fft_gamma_inv<C>(const PlanView &, const C *, C *, bool, hipStream_t);
+SOFT_FFT_INSTANTIATE(double2)
+SOFT_FFT_INSTANTIATE(float2)
 
 }  // namespace soft

@@ -1,31 +1,64 @@
 // soft_api.hip -- plan creation and the C-ABI entry points of include/soft.h.
 //
-// Plan-time tables are computed on the host in x87 long double and rounded
-// once to double (or split into double-double hi/lo pairs where the device
-// sums them):
+// A plan holds n functions; the functions of one bandwidth form a band.  Per
+// band the host computes, in x87 long double rounded once to double (or split
+// into double-double hi/lo pairs where the device sums them):
 //   w_B(j)                 quadrature weights, eq. "weights"
 //   cos(b_j)               recurrence argument, eq. "Wigner_d_recurrence"
 //   log cos(b_j/2), log sin(b_j/2), 0.5 log((2m)!/((m+m')!(m-m')!))
 //                          seed exponents, Sect. 2.2 "initial cases"
-//   e^{+-2 pi i k/2B}      FFT twiddles
-//   group / slot tables    symmetry groups of order pairs (Sect. 3)
+//   e^{+-2 pi i k/2B}      FFT twiddles (FP64 and FP32)
+//   group tables           symmetry groups of order pairs (Sect. 3)
+// and a plan-time kernel fills the rescaled recurrence table of every band.
+// A transform runs the FFT passes band by band, and the DWT as one launch per
+// launch shape over a cost-sorted work list of (function, group) items, so
+// all bands with 2B <= 256 share a single DWT launch.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "soft_internal.h"
 
+namespace {
+
+using soft::FuncInfo;
+using soft::GroupInfo;
+using soft::kSlots;
+using soft::PlanView;
+using soft::WorkItem;
+
+struct Band {
+    int B = 0, N = 0, G = 0;
+    long long Nc = 0, rows = 0, row_base = 0;
+    std::vector<int> funcs;  // plan function indices, increasing
+    size_t tab_off = 0;      // byte offset of the band's tables in the table block
+    PlanView view{};         // host copy holding device pointers
+};
+
+struct LaunchGroup {
+    int nw = 1, nsub = 1, nitems = 0;
+    size_t items_off = 0;  // byte offset of the work items in the table block
+};
+
+}  // namespace
+
 struct soft_plan_s {
-    int B = 0, N = 0, batch = 0, G = 0, device = 0;
-    long long Nc = 0, rows = 0;
-    soft::PlanView view{};
+    int precision = 0, n = 0, device = 0;
+    std::vector<Band> bands;
+    std::vector<FuncInfo> funcs;
+    std::vector<LaunchGroup> groups;
+    size_t grid_total = 0, coeff_total = 0, s_total = 0, t1_elems = 0, csize = 16;
+    long long rows_total = 0;
     // device allocations
-    void *tables = nullptr;
-    double2 *S = nullptr, *t1 = nullptr;
+    unsigned char *tables = nullptr;
+    void *S = nullptr, *t1 = nullptr;
     double2 *rec = nullptr;
     double *rscale = nullptr;
+    const PlanView *d_views = nullptr;
     size_t ws_bytes = 0;
     // stage timing
     struct Pending {
@@ -41,9 +74,6 @@ struct soft_plan_s {
 
 namespace {
 
-using soft::GroupInfo;
-using soft::kSlots;
-
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 void free_plan(soft_plan_s *p) {
@@ -58,48 +88,51 @@ void free_plan(soft_plan_s *p) {
     delete p;
 }
 
-// Byte offsets of the table block, each 256-byte aligned.
-struct TableLayout {
-    size_t w, cosb, lcs, lbin, grp, goff, slot, twp, twm, total;
-};
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-TableLayout layout_tables(int B, int G) {
-    const int N = 2 * B, P = 2 * B - 1;
-    TableLayout t{};
-    size_t o = 0;
-    t.w = o;    o = align256(o + sizeof(double) * N);
-    t.cosb = o; o = align256(o + sizeof(double) * N);
-    t.lcs = o;  o = align256(o + sizeof(double4) * N);
-    t.lbin = o; o = align256(o + sizeof(double2) * G);
-    t.grp = o;  o = align256(o + sizeof(GroupInfo) * G);
-    t.goff = o; o = align256(o + sizeof(long long) * G);
-    t.slot = o; o = align256(o + sizeof(int) * (size_t)P * P);
-    t.twp = o;  o = align256(o + sizeof(double2) * N);
-    t.twm = o;  o = align256(o + sizeof(double2) * N);
-    t.total = o;
-    return t;
-}
 
 void split_dd(long double x, double &hi, double &lo) {
     hi = (double)x;
     lo = (double)(x - (long double)hi);
 }
 
-int build_tables(soft_plan_s *p, std::vector<unsigned char> &host, TableLayout &lay) {
-    const int B = p->B, N = p->N, P = 2 * B - 1, G = p->G;
-    lay = layout_tables(B, G);
-    host.assign(lay.total, 0);
-    double *w = reinterpret_cast<double *>(host.data() + lay.w);
-    double *cosb = reinterpret_cast<double *>(host.data() + lay.cosb);
-    double4 *lcs = reinterpret_cast<double4 *>(host.data() + lay.lcs);
-    double2 *lbin = reinterpret_cast<double2 *>(host.data() + lay.lbin);
-    GroupInfo *grp = reinterpret_cast<GroupInfo *>(host.data() + lay.grp);
-    long long *goff = reinterpret_cast<long long *>(host.data() + lay.goff);
-    int *slot = reinterpret_cast<int *>(host.data() + lay.slot);
-    double2 *twp = reinterpret_cast<double2 *>(host.data() + lay.twp);
-    double2 *twm = reinterpret_cast<double2 *>(host.data() + lay.twm);
+// Byte offsets of one band's tables, each 256-byte aligned.
+struct BandLayout {
+    size_t w, cosb, lcs, lbin, grp, goff, twp, twm, twpf, twmf, bfuncs, total;
+};
+
+BandLayout band_layout(const Band &b) {
+    const size_t N = b.N, G = b.G;
+    BandLayout t{};
+    size_t o = 0;
+    t.w = o;      o = align256(o + sizeof(double) * N);
+    t.cosb = o;   o = align256(o + sizeof(double) * N);
+    t.lcs = o;    o = align256(o + sizeof(double4) * N);
+    t.lbin = o;   o = align256(o + sizeof(double2) * G);
+    t.grp = o;    o = align256(o + sizeof(GroupInfo) * G);
+    t.goff = o;   o = align256(o + sizeof(long long) * G);
+    t.twp = o;    o = align256(o + sizeof(double2) * N);
+    t.twm = o;    o = align256(o + sizeof(double2) * N);
+    t.twpf = o;   o = align256(o + sizeof(float2) * N);
+    t.twmf = o;   o = align256(o + sizeof(float2) * N);
+    t.bfuncs = o; o = align256(o + sizeof(int) * b.funcs.size());
+    t.total = o;
+    return t;
+}
+
+// Fills one band's tables at host address base (laid out by band_layout).
+int fill_band(const Band &b, const BandLayout &lay, unsigned char *base) {
+    const int B = b.B, N = b.N, P = 2 * B - 1;
+    double *w = reinterpret_cast<double *>(base + lay.w);
+    double *cosb = reinterpret_cast<double *>(base + lay.cosb);
+    double4 *lcs = reinterpret_cast<double4 *>(base + lay.lcs);
+    double2 *lbin = reinterpret_cast<double2 *>(base + lay.lbin);
+    GroupInfo *grp = reinterpret_cast<GroupInfo *>(base + lay.grp);
+    long long *goff = reinterpret_cast<long long *>(base + lay.goff);
+    double2 *twp = reinterpret_cast<double2 *>(base + lay.twp);
+    double2 *twm = reinterpret_cast<double2 *>(base + lay.twm);
+    float2 *twpf = reinterpret_cast<float2 *>(base + lay.twpf);
+    float2 *twmf = reinterpret_cast<float2 *>(base + lay.twmf);
+    int *bfuncs = reinterpret_cast<int *>(base + lay.bfuncs);
 
     const long double PI = 3.141592653589793238462643383279502884L;
     for (int j = 0; j < N; ++j) {
@@ -108,19 +141,21 @@ int build_tables(soft_plan_s *p, std::vector<unsigned char> &host, TableLayout &
         for (int i = 0; i < B; ++i) s += sinl((long double)(2 * i + 1) * beta) / (long double)(2 * i + 1);
         w[j] = (double)(2.0L * PI * sinl(beta) / ((long double)B * (long double)B) * s);
         cosb[j] = (double)cosl(beta);
-        double a, b, c, d;
-        split_dd(logl(cosl(beta / 2)), a, b);
-        split_dd(logl(sinl(beta / 2)), c, d);
-        lcs[j] = make_double4(a, b, c, d);
+        double a, c, d, e;
+        split_dd(logl(cosl(beta / 2)), a, c);
+        split_dd(logl(sinl(beta / 2)), d, e);
+        lcs[j] = make_double4(a, c, d, e);
     }
     for (int k = 0; k < N; ++k) {
         const long double ang = 2.0L * PI * (long double)k / (long double)N;
-        const double cr = (double)cosl(ang), si = (double)sinl(ang);
-        twp[k] = make_double2(cr, si);
-        twm[k] = make_double2(cr, -si);
+        const long double cr = cosl(ang), si = sinl(ang);
+        twp[k] = make_double2((double)cr, (double)si);
+        twm[k] = make_double2((double)cr, (double)-si);
+        twpf[k] = make_float2((float)cr, (float)si);
+        twmf[k] = make_float2((float)cr, (float)-si);
     }
-    for (int i = 0; i < P * P; ++i) slot[i] = -1;
-    long long row = 0;
+    std::vector<int> slot((size_t)P * P, -1);
+    long long row = b.row_base;
     int g = 0;
     for (int m = 0; m < B; ++m) {
         for (int mp = 0; mp <= m; ++mp, ++g) {
@@ -141,16 +176,28 @@ int build_tables(soft_plan_s *p, std::vector<unsigned char> &host, TableLayout &
                                    {-m, mp}, {m, -mp}, {-mp, m}, {mp, -m}};
             for (int s = 0; s < kSlots; ++s) {
                 if (!((mask >> s) & 1)) continue;
-                const int idx = (mem[s][0] + B - 1) * P + (mem[s][1] + B - 1);
+                const size_t idx = (size_t)(mem[s][0] + B - 1) * P + (mem[s][1] + B - 1);
                 if (slot[idx] != -1) return SOFT_ERR_INVALID;  // pair claimed twice
                 slot[idx] = (g * kSlots + s) * 2 + (s >= 4 ? 1 : 0);
             }
         }
     }
-    for (int i = 0; i < P * P; ++i)  // every pair covered, and by the kernels' slot_code
-        if (slot[i] < 0 || slot[i] != soft::slot_code(i / P - (B - 1), i % P - (B - 1))) return SOFT_ERR_INVALID;
-    p->rows = row;
+    // Every pair is covered, and exactly as the kernels' slot_code() says.
+    for (size_t i = 0; i < slot.size(); ++i)
+        if (slot[i] < 0 || slot[i] != soft::slot_code((int)(i / P) - (B - 1), (int)(i % P) - (B - 1)))
+            return SOFT_ERR_INVALID;
+    if (row != b.row_base + b.rows) return SOFT_ERR_INVALID;
+    for (size_t f = 0; f < b.funcs.size(); ++f) bfuncs[f] = b.funcs[f];
     return SOFT_OK;
+}
+
+// DWT launch shape (waves per block, beta sub-tiles per lane) of length N.
+std::pair<int, int> shape_for(int N) {
+    if (N <= 64) return {1, 1};
+    if (N == 128) return {2, 1};
+    if (N == 256) return {4, 1};
+    if (N == 512) return {8, 1};
+    return {8, 2};
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SOFT_OK : SOFT_ERR_HIP; }
@@ -164,7 +211,7 @@ int check_call(soft_plan_t plan, const void *a, const void *b) {
 }
 
 // Records one HIP event between consecutive kernels of a call when the plan
-// has timing enabled; stage s spans the events around its kernel.
+// has timing enabled; each lap is charged to the stage of the kernel before it.
 class StageClock {
   public:
     StageClock(soft_plan_s *p, hipStream_t s) : p_(p), s_(s) {}
@@ -197,41 +244,268 @@ class StageClock {
     hipEvent_t prev_ = nullptr;
 };
 
-// Forward-type transform: FFT (gamma, then alpha with optional W), DWT with
-// the reorder (optional V) in its epilogue.  soft_forward uses W and V; soft_adjoint_inverse
-// uses neither.
-int run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bool scaled) {
-    const int rc = check_call(p, grid, coeffs);
-    if (rc != SOFT_OK) return rc;
+const WorkItem *items_of(const soft_plan_s *p, const LaunchGroup &lg) {
+    return reinterpret_cast<const WorkItem *>(p->tables + lg.items_off);
+}
+
+// Forward-type transform: per band the gamma then alpha FFT pass (optional W),
+// then the DWT launches, which write the l-major coefficients (optional V).
+// soft_forward uses W and V; soft_adjoint_inverse uses neither.
+template <int PR>
+hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bool scaled) {
+    using C = typename soft::PrecT<PR>::C;
+    const C *gin = static_cast<const C *>(grid);
+    C *cout_ = static_cast<C *>(coeffs);
+    C *t1 = static_cast<C *>(p->t1);
+    C *S = static_cast<C *>(p->S);
     StageClock clk(p, s);
     hipError_t e = clk.start();
-    if (e == hipSuccess) e = soft::launch_fft_gamma_fwd(p->view, p->batch, static_cast<const double2 *>(grid), p->t1, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_FWD);
-    if (e == hipSuccess) e = soft::launch_fft_alpha_fwd(p->view, p->batch, p->t1, p->S, scaled, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_FWD);
-    if (e == hipSuccess)
-        e = soft::launch_dwt_fwd(p->view, p->batch, p->S, static_cast<double2 *>(coeffs), scaled, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
+    for (const Band &b : p->bands) {
+        if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, s);
+        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_FWD);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, S, scaled, s);
+        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_FWD);
+    }
+    for (const LaunchGroup &lg : p->groups) {
+        if (e == hipSuccess)
+            e = soft::launch_dwt_fwd<PR>(p->d_views, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, p->rec, S, cout_,
+                                         scaled, s);
+        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
+    }
+    return e;
+}
+
+// Inverse-type transform: the iDWT launches (reading the l-major coefficients,
+// optional V), then per band the alpha then gamma FFT pass (optional W).
+// soft_inverse uses neither factor; soft_adjoint uses both.
+template <int PR>
+hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bool scaled) {
+    using C = typename soft::PrecT<PR>::C;
+    const C *cin = static_cast<const C *>(coeffs);
+    C *gout = static_cast<C *>(grid);
+    C *t1 = static_cast<C *>(p->t1);
+    C *S = static_cast<C *>(p->S);
+    StageClock clk(p, s);
+    hipError_t e = clk.start();
+    for (const LaunchGroup &lg : p->groups) {
+        if (e == hipSuccess)
+            e = soft::launch_dwt_inv<PR>(p->d_views, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, p->rec, cin, S,
+                                         scaled, s);
+        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
+    }
+    for (const Band &b : p->bands) {
+        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, s);
+        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_INV);
+        if (e == hipSuccess) e = soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, s);
+        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_INV);
+    }
+    return e;
+}
+
+int dispatch(soft_plan_t p, const void *in, void *out, hipStream_t s, bool forward, bool scaled) {
+    const int rc = check_call(p, in, out);
+    if (rc != SOFT_OK) return rc;
+    hipError_t e;
+    switch (p->precision) {
+        case SOFT_FP64:
+            e = forward ? run_forward<soft::P64>(p, in, out, s, scaled) : run_inverse<soft::P64>(p, in, out, s, scaled);
+            break;
+        case SOFT_FP32:
+            e = forward ? run_forward<soft::P32>(p, in, out, s, scaled) : run_inverse<soft::P32>(p, in, out, s, scaled);
+            break;
+        default:
+            e = forward ? run_forward<soft::P32S>(p, in, out, s, scaled)
+                        : run_inverse<soft::P32S>(p, in, out, s, scaled);
+            break;
+    }
     return hip_status(e);
 }
 
-// Inverse-type transform: iDWT (gathering the l-major coefficients, optional
-// V), FFT (alpha, then gamma with optional W).  soft_inverse uses neither
-// factor; soft_adjoint uses both.
-int run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bool scaled) {
-    const int rc = check_call(p, coeffs, grid);
-    if (rc != SOFT_OK) return rc;
-    StageClock clk(p, s);
-    hipError_t e = clk.start();
-    if (e == hipSuccess)
-        e = soft::launch_dwt_inv(p->view, p->batch, static_cast<const double2 *>(coeffs), p->S, scaled, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
-    if (e == hipSuccess) e = soft::launch_fft_alpha_inv(p->view, p->batch, p->S, p->t1, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_INV);
-    if (e == hipSuccess)
-        e = soft::launch_fft_gamma_inv(p->view, p->batch, p->t1, static_cast<double2 *>(grid), scaled, s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_INV);
-    return hip_status(e);
+bool valid_precision(int precision) {
+    return precision == SOFT_FP64 || precision == SOFT_FP32 || precision == SOFT_FP32_SPLIT;
+}
+
+// Builds bands, the function table and the DWT work lists of a plan for the
+// bandwidths Bs[0..n) (validated by the caller).
+int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
+    soft_plan_s *p = new (std::nothrow) soft_plan_s;
+    if (!p) return SOFT_ERR_OOM;
+    try {
+        p->precision = precision;
+        p->n = n;
+        p->csize = precision == SOFT_FP64 ? sizeof(double2) : sizeof(float2);
+        if (hipGetDevice(&p->device) != hipSuccess) {
+            delete p;
+            return SOFT_ERR_HIP;
+        }
+        // Bands in increasing B; functions keep the caller's order.
+        std::vector<int> distinct(Bs, Bs + n);
+        std::sort(distinct.begin(), distinct.end());
+        distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+        for (int B : distinct) {
+            Band b;
+            b.B = B;
+            b.N = 2 * B;
+            b.G = B * (B + 1) / 2;
+            b.Nc = (long long)B * (4LL * B * B - 1) / 3;
+            for (int m = 0; m < B; ++m) b.rows += (long long)(m + 1) * (B - m);
+            b.row_base = p->rows_total;
+            p->rows_total += b.rows;
+            p->bands.push_back(b);
+        }
+        p->funcs.resize(n);
+        for (int f = 0; f < n; ++f) {
+            const int bi = (int)(std::lower_bound(distinct.begin(), distinct.end(), Bs[f]) - distinct.begin());
+            Band &b = p->bands[bi];
+            FuncInfo &fi = p->funcs[f];
+            fi.band = bi;
+            fi.pad = 0;
+            fi.grid_off = (long long)p->grid_total;
+            fi.coeff_off = (long long)p->coeff_total;
+            fi.s_off = (long long)p->s_total;
+            p->grid_total += (size_t)b.N * b.N * b.N;
+            p->coeff_total += (size_t)b.Nc;
+            p->s_total += (size_t)b.G * kSlots * b.N;
+            b.funcs.push_back(f);
+        }
+        for (const Band &b : p->bands)
+            p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
+
+        // DWT launch groups: in a plan of several bands, all bands with
+        // 2B <= 256 share one launch of 4-wave blocks; otherwise each length
+        // keeps its own shape.
+        const bool merged = p->bands.size() > 1;
+        std::vector<std::pair<int, int>> shapes;
+        std::vector<std::vector<int>> group_bands;
+        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+            std::pair<int, int> sh = shape_for(p->bands[bi].N);
+            if (merged && p->bands[bi].N <= 256) sh = {4, 1};
+            size_t gi = std::find(shapes.begin(), shapes.end(), sh) - shapes.begin();
+            if (gi == shapes.size()) {
+                shapes.push_back(sh);
+                group_bands.emplace_back();
+            }
+            group_bands[gi].push_back((int)bi);
+        }
+        // Work lists: runs of 8 consecutive groups of one function (the XCD
+        // remap hands each run to one XCD), ordered by the cost (B - m) 2B of
+        // their first group, largest first, so the long recurrences start
+        // early and the short ones fill the tail.
+        std::vector<std::vector<WorkItem>> lists(shapes.size());
+        for (size_t gi = 0; gi < shapes.size(); ++gi) {
+            struct Run {
+                long long cost;
+                int band, func, g0, g1;
+            };
+            std::vector<Run> runs;
+            for (int bi : group_bands[gi]) {
+                const Band &b = p->bands[bi];
+                std::vector<int> m_of(b.G);
+                for (int m = 0, g = 0; m < b.B; ++m)
+                    for (int mp = 0; mp <= m; ++mp) m_of[g++] = m;
+                for (int f : b.funcs)
+                    for (int g0 = 0; g0 < b.G; g0 += 8)
+                        runs.push_back({(long long)(b.B - m_of[g0]) * b.N, bi, f, g0, std::min(b.G, g0 + 8)});
+            }
+            std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.cost > c.cost; });
+            for (const Run &r : runs)
+                for (int g = r.g0; g < r.g1; ++g) lists[gi].push_back(WorkItem{r.band, r.func, g, 0});
+            LaunchGroup lg;
+            lg.nw = shapes[gi].first;
+            lg.nsub = shapes[gi].second;
+            lg.nitems = (int)lists[gi].size();
+            p->groups.push_back(lg);
+        }
+
+        // Table block: band tables, function table, band views, work lists.
+        size_t off = 0;
+        std::vector<BandLayout> lays;
+        for (Band &b : p->bands) {
+            b.tab_off = off;
+            lays.push_back(band_layout(b));
+            off = align256(off + lays.back().total);
+        }
+        const size_t funcs_off = off;
+        off = align256(off + sizeof(FuncInfo) * n);
+        const size_t views_off = off;
+        off = align256(off + sizeof(PlanView) * p->bands.size());
+        for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+            p->groups[gi].items_off = off;
+            off = align256(off + sizeof(WorkItem) * lists[gi].size());
+        }
+        const size_t total = off;
+        std::vector<unsigned char> host(total, 0);
+        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+            const int rc = fill_band(p->bands[bi], lays[bi], host.data() + p->bands[bi].tab_off);
+            if (rc != SOFT_OK) {
+                delete p;
+                return rc;
+            }
+        }
+        std::memcpy(host.data() + funcs_off, p->funcs.data(), sizeof(FuncInfo) * n);
+        for (size_t gi = 0; gi < p->groups.size(); ++gi)
+            std::memcpy(host.data() + p->groups[gi].items_off, lists[gi].data(), sizeof(WorkItem) * lists[gi].size());
+
+        const size_t rec_rows = (size_t)p->rows_total + soft::kPadRows;
+        if (hipMalloc(&p->tables, total) != hipSuccess || hipMalloc(&p->S, p->s_total * p->csize) != hipSuccess ||
+            hipMalloc(&p->t1, p->t1_elems * p->csize) != hipSuccess ||
+            hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            free_plan(p);
+            return SOFT_ERR_OOM;
+        }
+        p->ws_bytes = total + (p->s_total + p->t1_elems) * p->csize + rec_rows * (sizeof(double2) + sizeof(double));
+
+        // Band views with device pointers, kept on the host (FFT launches)
+        // and in the table block (DWT work lists).
+        std::vector<PlanView> views;
+        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+            Band &b = p->bands[bi];
+            const BandLayout &lay = lays[bi];
+            const unsigned char *base = p->tables + b.tab_off;
+            PlanView &v = b.view;
+            v.B = b.B;
+            v.N = b.N;
+            v.G = b.G;
+            v.nfunc = (int)b.funcs.size();
+            v.Nc = b.Nc;
+            v.rows = b.rows;
+            v.w = reinterpret_cast<const double *>(base + lay.w);
+            v.cosb = reinterpret_cast<const double *>(base + lay.cosb);
+            v.lcs = reinterpret_cast<const double4 *>(base + lay.lcs);
+            v.lbin = reinterpret_cast<const double2 *>(base + lay.lbin);
+            v.grp = reinterpret_cast<const GroupInfo *>(base + lay.grp);
+            v.goff = reinterpret_cast<const long long *>(base + lay.goff);
+            v.twp = reinterpret_cast<const double2 *>(base + lay.twp);
+            v.twm = reinterpret_cast<const double2 *>(base + lay.twm);
+            v.twpf = reinterpret_cast<const float2 *>(base + lay.twpf);
+            v.twmf = reinterpret_cast<const float2 *>(base + lay.twmf);
+            v.rscale = p->rscale;
+            v.funcs = reinterpret_cast<const FuncInfo *>(p->tables + funcs_off);
+            v.band_funcs = reinterpret_cast<const int *>(base + lay.bfuncs);
+            views.push_back(v);
+        }
+        std::memcpy(host.data() + views_off, views.data(), sizeof(PlanView) * views.size());
+        p->d_views = reinterpret_cast<const PlanView *>(p->tables + views_off);
+
+        hipError_t e = hipMemcpy(p->tables, host.data(), total, hipMemcpyHostToDevice);
+        // Padding rows are read (never used) by prefetches; give them defined values.
+        if (e == hipSuccess) e = hipMemset(p->rec, 0, rec_rows * sizeof(double2));
+        if (e == hipSuccess) e = hipMemset(p->rscale, 0, rec_rows * sizeof(double));
+        for (const Band &b : p->bands)
+            if (e == hipSuccess) e = soft::launch_fill_recurrence(b.view, p->rec, p->rscale, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            free_plan(p);
+            return SOFT_ERR_HIP;
+        }
+    } catch (const std::bad_alloc &) {
+        free_plan(p);
+        return SOFT_ERR_OOM;
+    }
+    *out = p;
+    return SOFT_OK;
 }
 
 }  // namespace
@@ -239,96 +513,59 @@ int run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bo
 extern "C" {
 
 int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out) {
-    if (!out || B < 1 || batch < 1 || flags != 0) return SOFT_ERR_INVALID;
-    if (precision != SOFT_FP64) return SOFT_ERR_INVALID;
+    if (!out || B < 1 || batch < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
     if (!is_pow2(B) || B > 512) return SOFT_ERR_UNSUPPORTED;
-    soft_plan_s *p = new (std::nothrow) soft_plan_s;
-    if (!p) return SOFT_ERR_OOM;
-    p->B = B;
-    p->N = 2 * B;
-    p->batch = batch;
-    p->G = B * (B + 1) / 2;
-    p->Nc = (long long)B * (4LL * B * B - 1) / 3;
-    if (hipGetDevice(&p->device) != hipSuccess) {
-        delete p;
-        return SOFT_ERR_HIP;
-    }
-    std::vector<unsigned char> host;
-    TableLayout lay;
-    int rc = build_tables(p, host, lay);
-    if (rc != SOFT_OK) {
-        delete p;
-        return rc;
-    }
-    const size_t N = p->N;
-    const size_t s_elems = (size_t)batch * p->G * kSlots * N;
-    const size_t t1_elems = (size_t)batch * N * N * N;
-    const size_t rec_rows = (size_t)p->rows + soft::kPadRows;
-    if (hipMalloc(&p->tables, lay.total) != hipSuccess || hipMalloc(&p->S, s_elems * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->t1, t1_elems * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        free_plan(p);
+    std::vector<int> Bs;
+    try {
+        Bs.assign(batch, B);
+    } catch (const std::bad_alloc &) {
         return SOFT_ERR_OOM;
     }
-    p->ws_bytes = lay.total + (s_elems + t1_elems) * sizeof(double2) +
-                  rec_rows * (sizeof(double2) + sizeof(double));
-    if (hipMemcpy(p->tables, host.data(), lay.total, hipMemcpyHostToDevice) != hipSuccess) {
-        free_plan(p);
-        return SOFT_ERR_HIP;
-    }
-    const unsigned char *base = static_cast<const unsigned char *>(p->tables);
-    soft::PlanView &v = p->view;
-    v.B = B;
-    v.N = p->N;
-    v.G = p->G;
-    v.Nc = p->Nc;
-    v.rows = p->rows;
-    v.w = reinterpret_cast<const double *>(base + lay.w);
-    v.cosb = reinterpret_cast<const double *>(base + lay.cosb);
-    v.lcs = reinterpret_cast<const double4 *>(base + lay.lcs);
-    v.lbin = reinterpret_cast<const double2 *>(base + lay.lbin);
-    v.grp = reinterpret_cast<const GroupInfo *>(base + lay.grp);
-    v.goff = reinterpret_cast<const long long *>(base + lay.goff);
-    v.slot = reinterpret_cast<const int *>(base + lay.slot);
-    v.twp = reinterpret_cast<const double2 *>(base + lay.twp);
-    v.twm = reinterpret_cast<const double2 *>(base + lay.twm);
-    v.rec = p->rec;
-    v.rscale = p->rscale;
-    // Padding rows are read (never used) by prefetches; give them defined values.
-    if (hipMemset(p->rec, 0, rec_rows * sizeof(double2)) != hipSuccess ||
-        hipMemset(p->rscale, 0, rec_rows * sizeof(double)) != hipSuccess ||
-        soft::launch_fill_recurrence(v, p->rec, p->rscale, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        free_plan(p);
-        return SOFT_ERR_HIP;
-    }
-    *out = p;
-    return SOFT_OK;
+    return make_plan(Bs.data(), batch, precision, out);
+}
+
+int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, soft_plan_t *out) {
+    if (!out || !B_list || n < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    for (int i = 0; i < n; ++i)
+        if (B_list[i] < 1) return SOFT_ERR_INVALID;
+    for (int i = 0; i < n; ++i)
+        if (!is_pow2(B_list[i]) || B_list[i] > 512) return SOFT_ERR_UNSUPPORTED;
+    return make_plan(B_list, n, precision, out);
 }
 
 int soft_plan_sizes(soft_plan_t p, size_t *grid_elems, size_t *coeff_elems, size_t *workspace_bytes) {
     if (!p) return SOFT_ERR_INVALID;
-    if (grid_elems) *grid_elems = (size_t)p->batch * p->N * p->N * p->N;
-    if (coeff_elems) *coeff_elems = (size_t)p->batch * p->Nc;
+    if (grid_elems) *grid_elems = p->grid_total;
+    if (coeff_elems) *coeff_elems = p->coeff_total;
     if (workspace_bytes) *workspace_bytes = p->ws_bytes;
     return SOFT_OK;
 }
 
+int soft_plan_offsets(soft_plan_t p, size_t *grid_offsets, size_t *coeff_offsets) {
+    if (!p) return SOFT_ERR_INVALID;
+    for (int f = 0; f < p->n; ++f) {
+        if (grid_offsets) grid_offsets[f] = (size_t)p->funcs[f].grid_off;
+        if (coeff_offsets) coeff_offsets[f] = (size_t)p->funcs[f].coeff_off;
+    }
+    if (grid_offsets) grid_offsets[p->n] = p->grid_total;
+    if (coeff_offsets) coeff_offsets[p->n] = p->coeff_total;
+    return SOFT_OK;
+}
+
 int soft_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s) {
-    return run_forward(p, grid, coeffs, s, true);
+    return dispatch(p, grid, coeffs, s, true, true);
 }
 
 int soft_adjoint_inverse(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s) {
-    return run_forward(p, grid, coeffs, s, false);
+    return dispatch(p, grid, coeffs, s, true, false);
 }
 
 int soft_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s) {
-    return run_inverse(p, coeffs, grid, s, false);
+    return dispatch(p, coeffs, grid, s, false, false);
 }
 
 int soft_adjoint(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s) {
-    return run_inverse(p, coeffs, grid, s, true);
+    return dispatch(p, coeffs, grid, s, false, true);
 }
 
 int soft_plan_set_timing(soft_plan_t p, int enable) {

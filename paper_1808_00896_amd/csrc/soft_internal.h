@@ -94,9 +94,40 @@ struct GroupInfo {
     int pad;
 };
 
-// Device-side view of a plan, passed by value to kernels.
+// Arithmetic of a plan.  P64: complex128 data, FP64 throughout.  P32:
+// complex64 data, FP32 FFTs and FP32 MFMA contractions with d rounded to
+// FP32.  P32S: as P32 but d is split into hi + lo FP32 parts (two MFMA
+// products) and partial sums over 16 beta samples or 16 degrees are combined
+// in FP64.  In every mode the seeds, the recurrence, s_l, V_B and w_B(j) stay
+// in FP64.
+enum Prec { P64 = 0, P32 = 1, P32S = 2 };
+template <int PR>
+struct PrecT {
+    using R = float;
+    using C = float2;
+};
+template <>
+struct PrecT<P64> {
+    using R = double;
+    using C = double2;
+};
+
+// One function of a plan: element offsets (complex) of its grid, its
+// coefficients and its beta-sample workspace, and its band.
+struct FuncInfo {
+    long long grid_off, coeff_off, s_off;
+    int band, pad;
+};
+
+// One DWT work item: symmetry group g of function func in band band.
+struct WorkItem {
+    int band, func, g, pad;
+};
+
+// Device-side view of one band (all functions of one bandwidth).
 struct PlanView {
     int B, N, G;
+    int nfunc;             // functions in this band
     long long Nc;          // coefficients per function
     long long rows;        // group rows (one per group and degree) per function
     const double *w;       // [N]   quadrature weights w_B(j)
@@ -104,29 +135,43 @@ struct PlanView {
     const double4 *lcs;    // [N]   (log cos(b_j/2) hi, lo, log sin(b_j/2) hi, lo)
     const double2 *lbin;   // [G]   0.5 log((2m)!/((m+m')!(m-m')!)) as (hi, lo)
     const GroupInfo *grp;  // [G]
-    const long long *goff; // [G]   first row of group g in the per-row tables
-    const int *slot;       // [(2B-1)^2] (g*8 + s)*2 + (s >= 4), indexed (m+B-1)(2B-1) + (m'+B-1)
-    const double2 *rec;    // [rows + kPadRows] rescaled recurrence coefficients (alpha_l, gamma_l)
-    const double *rscale;  // [rows + kPadRows] s_l, with d(l) = s_l e(l)
+    const long long *goff; // [G]   first row of group g in the plan's per-row tables
     const double2 *twp;    // [N]   e^{+2 pi i k/N}
     const double2 *twm;    // [N]   e^{-2 pi i k/N}
+    const float2 *twpf;    // [N]   e^{+2 pi i k/N}, FP32
+    const float2 *twmf;    // [N]   e^{-2 pi i k/N}, FP32
+    const double *rscale;  // plan-wide per-row s_l (d(l) = s_l e(l)), indexed by goff
+    const FuncInfo *funcs; // plan-wide function table
+    const int *band_funcs; // [nfunc] function indices of this band
 };
 
-// FFT stage (separation of variables, Sect. 2.4).
-hipError_t launch_fft_gamma_fwd(const PlanView &p, int batch, const double2 *grid, double2 *t1, hipStream_t s);
-hipError_t launch_fft_alpha_fwd(const PlanView &p, int batch, const double2 *t1, double2 *S, bool apply_w, hipStream_t s);
-hipError_t launch_fft_alpha_inv(const PlanView &p, int batch, const double2 *S, double2 *t1, hipStream_t s);
-hipError_t launch_fft_gamma_inv(const PlanView &p, int batch, const double2 *t1, double2 *grid, bool apply_w, hipStream_t s);
+// FFT stage (separation of variables, Sect. 2.4), one launch per band; t1 is
+// the band's intermediate, [nfunc][N^3].
+template <typename C>
+hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s);
+template <typename C>
+hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, C *S, bool apply_w, hipStream_t s);
+template <typename C>
+hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, hipStream_t s);
+template <typename C>
+hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, hipStream_t s);
 
-// Discrete Wigner transform and its transpose (Sect. 2.4 matrix form).
+// Plan-time fill of the rescaled recurrence table of one band (rows from
+// goff[g]; rec and rscale are the plan-wide tables).
 hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s);
-// Forward DWT with the reorder fused into its epilogue: writes the l-major
-// coefficients directly (symmetry signs, s_l and, when apply_v, V_B applied).
-hipError_t launch_dwt_fwd(const PlanView &p, int batch, const double2 *S, double2 *coeffs, bool apply_v,
-                          hipStream_t s);
-// Inverse DWT reading the l-major coefficients directly (the inverse reorder
-// is fused into its staging: symmetry signs, s_l and, when apply_v, V_B).
-hipError_t launch_dwt_inv(const PlanView &p, int batch, const double2 *coeffs, double2 *S, bool apply_v,
-                          hipStream_t s);
+
+// DWT and iDWT over a work list (one block per item), all items sharing one
+// launch shape: nw waves, nsub subsets of 64 beta samples per wave.  views is
+// the device copy of the plan's band views.  The forward writes the l-major
+// coefficients (symmetry signs, s_l and, when apply_v, V_B applied); the
+// inverse reads them.
+template <int PR>
+hipError_t launch_dwt_fwd(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
+                          const double2 *rec, const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs,
+                          bool apply_v, hipStream_t s);
+template <int PR>
+hipError_t launch_dwt_inv(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
+                          const double2 *rec, const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S,
+                          bool apply_v, hipStream_t s);
 
 }  // namespace soft

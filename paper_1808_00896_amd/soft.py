@@ -1,14 +1,16 @@
 """Thin Python binding of libsoft.so (C-ABI in include/soft.h).
 
 Argument marshalling only: every step of the transforms runs in the HIP
-library.  Tensors are torch complex128 CUDA (HIP) tensors; the binding passes
+library.  Tensors are torch complex CUDA (HIP) tensors (complex128 for
+SOFT_FP64, complex64 for SOFT_FP32 and SOFT_FP32_SPLIT); the binding passes
 their device pointers and the current torch stream.  Loading fails loudly if
 the library has not been built (``python -m paper_1808_00896_amd.build``);
 there is no fallback.
 
 The module-level functions mirror the C entry points one to one
-(``soft_plan``, ``soft_forward``, ...); ``Plan`` wraps a plan handle with
-shape checks and output allocation.
+(``soft_plan``, ``soft_forward``, ...); ``Plan`` (one bandwidth) and
+``UnevenPlan`` (mixed bandwidths) wrap a plan handle with shape checks and
+output allocation.
 """
 import ctypes
 import os
@@ -19,6 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsoft.so")
 
 SOFT_FP64 = 0
+SOFT_FP32 = 1
+SOFT_FP32_SPLIT = 2
+PRECISIONS = {"fp64": SOFT_FP64, "fp32": SOFT_FP32, "fp32_split": SOFT_FP32_SPLIT}
 SOFT_OK = 0
 SOFT_ERR_INVALID = -1
 SOFT_ERR_UNSUPPORTED = -2
@@ -43,7 +48,10 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.soft_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(vp)]
+        L.soft_plan_uneven.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                       ctypes.POINTER(vp)]
         L.soft_plan_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.soft_plan_offsets.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         for name in ("soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse"):
             getattr(L, name).argtypes = [vp, vp, vp, vp]
         L.soft_plan_destroy.argtypes = [vp]
@@ -52,7 +60,7 @@ def lib():
                                             ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
-        for name in ("soft_plan", "soft_plan_sizes", "soft_forward", "soft_inverse", "soft_adjoint",
+        for name in ("soft_plan", "soft_plan_uneven", "soft_plan_sizes", "soft_plan_offsets", "soft_forward", "soft_inverse", "soft_adjoint",
                      "soft_adjoint_inverse", "soft_plan_destroy", "soft_plan_set_timing",
                      "soft_plan_stage_times"):
             getattr(L, name).restype = ctypes.c_int
@@ -84,6 +92,23 @@ def soft_plan(B, batch=1, precision=SOFT_FP64, flags=0):
     h = ctypes.c_void_p()
     _check(lib().soft_plan(int(B), int(batch), int(precision), int(flags), ctypes.byref(h)), "soft_plan")
     return h.value
+
+
+def soft_plan_uneven(B_list, precision=SOFT_FP64, flags=0):
+    """Create a plan over functions of the bandwidths in ``B_list`` (in storage order)."""
+    Bs = [int(b) for b in B_list]
+    arr = (ctypes.c_int * max(1, len(Bs)))(*Bs)
+    h = ctypes.c_void_p()
+    _check(lib().soft_plan_uneven(arr, len(Bs), int(precision), int(flags), ctypes.byref(h)), "soft_plan_uneven")
+    return h.value
+
+
+def soft_plan_offsets(plan, n):
+    """(grid_offsets, coeff_offsets), each a list of n+1 element offsets."""
+    g = (ctypes.c_size_t * (n + 1))()
+    c = (ctypes.c_size_t * (n + 1))()
+    _check(lib().soft_plan_offsets(ctypes.c_void_p(plan), g, c), "soft_plan_offsets")
+    return list(g), list(c)
 
 
 def soft_plan_sizes(plan):
@@ -142,35 +167,28 @@ def num_coeffs(B):
     return B * (4 * B * B - 1) // 3
 
 
-class Plan:
-    """A plan for ``batch`` SO(3) transforms of bandwidth ``B`` on one device.
+def _precision(precision):
+    if isinstance(precision, str):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {precision!r}")
+        return PRECISIONS[precision]
+    return int(precision)
 
-    Grids are complex128 tensors of shape [batch, 2B, 2B, 2B] (or [2B, 2B, 2B]
-    when batch == 1); coefficient vectors are [batch, B(4B^2-1)/3] (or flat).
-    Calls are asynchronous on the current torch stream.
-    """
 
-    def __init__(self, B, batch=1, device=None):
+class _PlanBase:
+    """Shape and dtype checks shared by Plan and UnevenPlan."""
+
+    def _init_device(self, device, precision):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
-        with torch.cuda.device(self.device):
-            self.handle = soft_plan(B, batch, SOFT_FP64, 0)
-        self.B, self.batch, self.N = B, batch, 2 * B
-        self.nc = num_coeffs(B)
-
-    # shapes -------------------------------------------------------------
-    def grid_shape(self):
-        N = self.N
-        return (N, N, N) if self.batch == 1 else (self.batch, N, N, N)
-
-    def coeff_shape(self):
-        return (self.nc,) if self.batch == 1 else (self.batch, self.nc)
+        self.precision = _precision(precision)
+        self.dtype = torch.complex128 if self.precision == SOFT_FP64 else torch.complex64
 
     def _checked(self, t, shape, what):
         if not isinstance(t, torch.Tensor) or t.device != self.device:
             raise ValueError(f"{what} must be a tensor on {self.device}")
-        if t.dtype != torch.complex128:
-            raise ValueError(f"{what} must be complex128, got {t.dtype}")
+        if t.dtype != self.dtype:
+            raise ValueError(f"{what} must be {self.dtype}, got {t.dtype}")
         if t.numel() != int(torch.Size(shape).numel()):
             raise ValueError(f"{what} has {t.numel()} elements, expected shape {shape}")
         if not t.is_contiguous():
@@ -179,7 +197,7 @@ class Plan:
 
     def _out(self, out, shape, what):
         if out is None:
-            return torch.empty(shape, dtype=torch.complex128, device=self.device)
+            return torch.empty(shape, dtype=self.dtype, device=self.device)
         return self._checked(out, shape, what)
 
     # transforms -----------------------------------------------------------
@@ -230,3 +248,58 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Plan(_PlanBase):
+    """A plan for ``batch`` SO(3) transforms of bandwidth ``B`` on one device.
+
+    Grids are tensors of shape [batch, 2B, 2B, 2B] (or [2B, 2B, 2B] when
+    batch == 1); coefficient vectors are [batch, B(4B^2-1)/3] (or flat).
+    ``precision`` is "fp64" (complex128), "fp32" or "fp32_split" (complex64).
+    Calls are asynchronous on the current torch stream.
+    """
+
+    def __init__(self, B, batch=1, device=None, precision="fp64"):
+        self._init_device(device, precision)
+        with torch.cuda.device(self.device):
+            self.handle = soft_plan(B, batch, self.precision, 0)
+        self.B, self.batch, self.N = B, batch, 2 * B
+        self.nc = num_coeffs(B)
+
+    def grid_shape(self):
+        N = self.N
+        return (N, N, N) if self.batch == 1 else (self.batch, N, N, N)
+
+    def coeff_shape(self):
+        return (self.nc,) if self.batch == 1 else (self.batch, self.nc)
+
+
+class UnevenPlan(_PlanBase):
+    """One call over functions of mixed bandwidths ``Bs`` (storage order).
+
+    Grids and coefficient vectors are flat 1-D tensors holding the functions
+    back to back; ``grid_offsets`` / ``coeff_offsets`` (n+1 entries) give
+    where each starts, and ``split_grids`` / ``split_coeffs`` return views.
+    """
+
+    def __init__(self, Bs, device=None, precision="fp64"):
+        self._init_device(device, precision)
+        self.Bs = [int(b) for b in Bs]
+        with torch.cuda.device(self.device):
+            self.handle = soft_plan_uneven(self.Bs, self.precision, 0)
+        self.grid_offsets, self.coeff_offsets = soft_plan_offsets(self.handle, len(self.Bs))
+
+    def grid_shape(self):
+        return (self.grid_offsets[-1],)
+
+    def coeff_shape(self):
+        return (self.coeff_offsets[-1],)
+
+    def split_grids(self, flat):
+        """Views [2B, 2B, 2B] of each function's grid in a flat grid buffer."""
+        return [flat[self.grid_offsets[f]:self.grid_offsets[f + 1]].view(2 * B, 2 * B, 2 * B)
+                for f, B in enumerate(self.Bs)]
+
+    def split_coeffs(self, flat):
+        """Views of each function's coefficient vector in a flat buffer."""
+        return [flat[self.coeff_offsets[f]:self.coeff_offsets[f + 1]] for f in range(len(self.Bs))]

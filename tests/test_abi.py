@@ -57,3 +57,25 @@ def test_argument_errors_need_no_gpu(L):
         assert getattr(L, name)(None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_sizes(None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_destroy(None) == soft.SOFT_OK
+
+
+def test_uneven_argument_errors_need_no_gpu(L):
+    from paper_1808_00896_amd import soft
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int * 3)(8, 16, 4)
+    assert L.soft_plan_uneven(None, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_uneven(arr, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_uneven(arr, 3, 3, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_uneven(arr, 3, 0, 2, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_uneven(arr, 3, 0, 0, None) == soft.SOFT_ERR_INVALID
+    bad = (ctypes.c_int * 3)(8, 0, 4)
+    assert L.soft_plan_uneven(bad, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    odd = (ctypes.c_int * 3)(8, 12, 4)
+    assert L.soft_plan_uneven(odd, 3, 1, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    big = (ctypes.c_int * 2)(8, 1024)
+    assert L.soft_plan_uneven(big, 2, 2, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert h.value is None
+    assert L.soft_plan_offsets(None, None, None) == soft.SOFT_ERR_INVALID
+    for prec in (soft.SOFT_FP32, soft.SOFT_FP32_SPLIT):
+        assert L.soft_plan(8, 0, prec, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+        assert L.soft_plan(12, 1, prec, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
