@@ -1,17 +1,22 @@
 """Benchmark: SO(3) FFT forward + inverse throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--B 128]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--B 128] [--quick]
 
 A step is one inverse (coefficients -> grid) followed by one forward (grid ->
 coefficients) of one function at bandwidth B in FP64: the whole hot path
-(iDWT, two FFT passes, two FFT passes, DWT).  Inputs are
-seeded synthetic band-limited coefficients (i.i.d. normal parts scaled by
-(1+l)^-1) already resident in HBM when the timed region starts.
+(iDWT, two FFT passes, two FFT passes, DWT).  Inputs are seeded synthetic
+band-limited coefficients (i.i.d. normal parts scaled by (1+l)^-1) already
+resident in HBM when the timed region starts.
 
-Printed: one JSON line with the throughput (fwd+inv per second), the
-roofline of the dominant kernel (HIP-event stage timers recorded inside the
-library on the launch stream during the timed region), the round-trip error,
-the oracle timed on the host cores, and a B = 512 leg.
+Printed: one JSON line with the throughput (fwd+inv per second) at B = 128 in
+FP64, the roofline of the dominant kernel (HIP-event stage timers recorded
+inside the library on the launch stream during the timed region), the
+round-trip error, the oracle timed on the host cores, and the legs of the
+metric: plain FP64 at B = 512, batched FP32-split at B = 128 and 512, and 256
+functions of uneven bandwidth in FP64 / FP32 / FP32-split.  Every reduced-
+precision leg reports its error against the FP64 path on the same inputs
+(the FP64 path itself is held to 1e-11 / 1e-9 of the oracle by the parity
+tests).
 """
 import argparse
 import hashlib
@@ -30,34 +35,37 @@ FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 (vector and matrix), published
 METRIC = "SOFT fwd+inv/sec at B=128 & 512: FP64 plain vs batched FP32-split @ ≤1e-6 err"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"fft": "fft.hip", "dwt": "dwt.hip"}
+CSIZE = {"fp64": 16, "fp32": 8, "fp32_split": 8}
 
 
 def num_coeffs(B):
     return B * (4 * B * B - 1) // 3
 
 
-def stage_work(B, batch=1):
-    """Algorithmic bytes (HBM-bound stages) or flops (DWT) per launch.
+def stage_work(Bs, prec="fp64"):
+    """Algorithmic bytes (FFT stages) or flops (DWT stages) of one step over
+    functions of bandwidths Bs.
 
-    FFT passes: every complex128 element read once and written once, with the
-    +-B frequency row absent on the side where it is dropped.  Reorder: the
-    coefficients read and written once.  DWT: 8B flops per coefficient for
-    the contraction (complex x real over 2B beta samples, FMA = 2 flops) plus
-    5 flops per recurrence step per beta sample and symmetry group.
+    FFT passes: every complex element read once and written once, with the
+    +-B frequency row absent on the side where it is dropped.  DWT: 8B flops
+    per coefficient for the contraction (complex x real over 2B beta samples,
+    FMA = 2 flops) plus 5 flops per recurrence step per beta sample and
+    symmetry group.
     """
-    N, P = 2 * B, 2 * B - 1
-    nc = num_coeffs(B)
-    steps = sum((m + 1) * (B - 1 - m) for m in range(B))  # recurrence steps over groups m >= m' >= 0
-    dwt_flops = 8.0 * B * nc + 5.0 * N * steps
-    w = {
-        "fft_gamma_fwd": ("hbm", 16.0 * (N ** 3 + N * N * (N - 1))),
-        "fft_alpha_fwd": ("hbm", 16.0 * (N * N * (N - 1) + N * P * P)),
-        "dwt_fwd": ("flop", dwt_flops),
-        "dwt_inv": ("flop", dwt_flops),
-        "fft_alpha_inv": ("hbm", 16.0 * (N * P * P + N * N * (N - 1))),
-        "fft_gamma_inv": ("hbm", 16.0 * (N * N * (N - 1) + N ** 3)),
-    }
-    return {k: (kind, v * batch) for k, (kind, v) in w.items()}
+    cs = CSIZE[prec]
+    tot = {k: 0.0 for k in ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "dwt_inv", "fft_alpha_inv",
+                            "fft_gamma_inv")}
+    for B in Bs:
+        N, P = 2 * B, 2 * B - 1
+        steps = sum((m + 1) * (B - 1 - m) for m in range(B))  # recurrence steps over groups m >= m' >= 0
+        dwt = 8.0 * B * num_coeffs(B) + 5.0 * N * steps
+        tot["fft_gamma_fwd"] += cs * (N ** 3 + N * N * (N - 1))
+        tot["fft_alpha_fwd"] += cs * (N * N * (N - 1) + N * P * P)
+        tot["dwt_fwd"] += dwt
+        tot["dwt_inv"] += dwt
+        tot["fft_alpha_inv"] += cs * (N * P * P + N * N * (N - 1))
+        tot["fft_gamma_inv"] += cs * (N * N * (N - 1) + N ** 3)
+    return {k: ("flop" if k.startswith("dwt") else "hbm", v) for k, v in tot.items()}
 
 
 def source_digest(kind):
@@ -81,8 +89,10 @@ def measured_traffic(stage, B):
     return rec.get("bytes_per_launch")
 
 
-def roofline(stage_ms, B, batch=1):
-    work = stage_work(B, batch)
+def roofline(stage_ms, B):
+    """Roofline of the slowest kernel of a one-function FP64 plan (one launch
+    per stage per step)."""
+    work = stage_work([B])
     avg = {k: ms / n for k, (ms, n) in stage_ms.items() if n}
     dom = max(avg, key=avg.get)
     kind, amount = work[dom]
@@ -93,7 +103,7 @@ def roofline(stage_ms, B, batch=1):
              "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
     else:
         achieved = amount / t / 1e12
-        r = {"kernel": dom, "bound": "mfma" if dom == "dwt_fwd" else "alu", "achieved": round(achieved, 2),
+        r = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2),
              "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
     r["avg_launch_ms"] = round(avg[dom], 5)
     r["algorithmic_per_launch"] = amount
@@ -101,29 +111,37 @@ def roofline(stage_ms, B, batch=1):
     return r
 
 
-def per_stage(stage_ms, B, batch=1):
-    work = stage_work(B, batch)
+def per_stage(stage_ms, Bs, steps, prec="fp64"):
+    """Per stage: ms per step (all launches of the stage) and the algorithmic rate."""
+    work = stage_work(Bs, prec)
     out = {}
     for k, (ms, n) in stage_ms.items():
         if not n:
             continue
-        a = ms / n
+        a = ms / steps
         kind, amount = work[k]
         rate = amount / (a * 1e-3)
-        out[k] = {"ms": round(a, 5), ("GB/s" if kind == "hbm" else "TFLOP/s"):
-                  round(rate / 1e9, 1) if kind == "hbm" else round(rate / 1e12, 2)}
+        out[k] = {"ms": round(a, 5), "launches_per_step": n // steps}
+        if kind == "hbm":
+            out[k]["GB/s"] = round(rate / 1e9, 1)
+        else:
+            out[k]["TFLOP/s"] = round(rate / 1e12, 2)
     return out
 
 
-def run_gpu(B, steps, warmup, seed, batch=1):
-    import torch
-    from paper_1808_00896_amd import inputs, soft
+def make_plan(Bs, prec, uniform):
+    from paper_1808_00896_amd import soft
+    if uniform:
+        return soft.Plan(Bs[0], batch=len(Bs), precision=prec)
+    return soft.UnevenPlan(Bs, precision=prec)
 
-    plan = soft.Plan(B, batch=batch)
-    c_host = np.stack([inputs.coeffs_decay(B, seed + i) for i in range(batch)]) if batch > 1 else \
-        inputs.coeffs_decay(B, seed)
-    c = torch.from_numpy(c_host).cuda()
-    grid = torch.empty(plan.grid_shape(), dtype=torch.complex128, device="cuda")
+
+def timed_steps(plan, c, steps, warmup):
+    """Run warmup + timed steps of inverse then forward; returns (seconds,
+    stage timers, grid, round-tripped coefficients)."""
+    import torch
+    from paper_1808_00896_amd import soft
+    grid = torch.empty(plan.grid_shape(), dtype=plan.dtype, device="cuda")
     c2 = torch.empty_like(c)
 
     def step():
@@ -143,11 +161,57 @@ def run_gpu(B, steps, warmup, seed, batch=1):
     t1 = time.perf_counter()
     soft.soft_plan_set_timing(plan.handle, False)
     st = soft.soft_plan_stage_times(plan.handle, reset=True)
-    err = float((c2 - c).abs().max() / c.abs().max())
+    return t1 - t0, st, grid, c2
+
+
+def relerr_dev(a, b, chunk=1 << 27):
+    """max |a - b| / max |b| over two device tensors of equal size, in FP64,
+    chunk by chunk (the grids reach tens of GB)."""
+    import torch
+    a, b = a.reshape(-1), b.reshape(-1)
+    num = den = 0.0
+    for s in range(0, b.numel(), chunk):
+        x = a[s:s + chunk].to(torch.complex128)
+        y = b[s:s + chunk].to(torch.complex128)
+        num = max(num, float((x - y).abs().max()))
+        den = max(den, float(y.abs().max()))
+    return num / den
+
+
+def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=False):
+    """Time `steps` fwd+inv of the functions Bs in precision prec.
+
+    ref: dict with the FP64 path's grid and coefficients on the same inputs
+    (flat or batched like this plan), for the error report.  keep_ref returns
+    this leg's own grid for use as such a reference.
+    """
+    import torch
+    plan = make_plan(Bs, prec, uniform)
+    dt = plan.dtype
+    c = torch.from_numpy(c_host).to("cuda").to(dt).reshape(plan.coeff_shape())
+    el, st, grid, c2 = timed_steps(plan, c, steps, warmup)
+    n = len(Bs)
+    res = {"functions": n, "precision": prec, "steps": steps,
+           "value": round(steps * n / el, 3), "unit": "function fwd+inv/s",
+           "ms_per_step": round(el / steps * 1e3, 4),
+           "round_trip_err": relerr_dev(c2, c),
+           "stages": per_stage(st, Bs, steps, prec)}
+    out = None
+    if ref is not None:
+        res["inverse_err_vs_fp64"] = relerr_dev(grid, ref["grid"])
+        # forward of the FP64 path's grid, rounded to this precision
+        g_in = ref["grid"].to(dt).reshape(plan.grid_shape())
+        plan.forward(g_in, out=c2)
+        del g_in
+        res["forward_err_vs_fp64"] = relerr_dev(c2, ref["coeffs"])
+    if keep_ref:
+        # this leg's grid and the forward of it (the last timed step's output)
+        out = {"grid": grid.reshape(-1), "coeffs": c2.reshape(-1)}
     plan.close()
     del c, c2, grid
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    return {"elapsed": t1 - t0, "stages": st, "round_trip_err": err, "c_host": c_host}
+    return res, out
 
 
 def cpu_baseline(B, c_host, budget_s=12.0, max_reps=3):
@@ -176,6 +240,10 @@ def calibrate_copy(gib=1.0):
     return 2 * n * 16
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,8 +251,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--B", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="main B leg only (no B=512, batched or uneven legs)")
     ap.add_argument("--no-b512", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--b512-steps", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=16, help="functions per batched FP32-split call at B=128")
+    ap.add_argument("--uneven-n", type=int, default=256)
+    ap.add_argument("--uneven-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -195,16 +268,19 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1808_00896_amd import inputs
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
 
     B = args.B
-    print(f"[bench] B={B} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    r = run_gpu(B, args.steps, args.warmup, seed=1)
-    ms = r["elapsed"] / args.steps * 1e3
-    value = args.steps / r["elapsed"]
+    log(f"B={B} FP64 steps={args.steps} warmup={args.warmup}")
+    c_host = inputs.coeffs_decay(B, 1)
+    main_leg, ref128 = run_leg([B], "fp64", args.steps, args.warmup, c_host, keep_ref=True)
+    # the roofline needs the per-launch stage times of the one-function plan
+    value = main_leg["value"]
+    st_ms = {k: (v["ms"] * args.steps, args.steps) for k, v in main_leg["stages"].items()}
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -212,7 +288,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -221,27 +297,71 @@ def main():
         "config": {"workload": f"one FP64 inverse + forward SO(3) FFT at B={B} "
                                f"({2 * B}^3 complex128 grid, {num_coeffs(B)} coefficients)",
                    "B": B, "batch": 1, "precision": "fp64"},
-        "roofline": roofline(r["stages"], B),
-        "stages": per_stage(r["stages"], B),
-        "round_trip_err": r["round_trip_err"],
+        "roofline": roofline(st_ms, B),
+        "stages": main_leg["stages"],
+        "round_trip_err": main_leg["round_trip_err"],
     }
-    print(f"[bench] B={B}: {value:.1f} fwd+inv/s, round trip {r['round_trip_err']:.2e}", file=sys.stderr, flush=True)
+    log(f"B={B}: {value:.1f} fwd+inv/s, round trip {main_leg['round_trip_err']:.2e}")
 
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(B, r["c_host"])
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(B, c_host)
     else:
         out["cpu_baseline"] = None
 
-    if not args.no_b512:
-        print("[bench] B=512 leg", file=sys.stderr, flush=True)
-        r5 = run_gpu(512, args.b512_steps, 1, seed=3)
-        out["b512"] = {"value": round(args.b512_steps / r5["elapsed"], 3), "unit": "fwd+inv/s",
-                       "ms_per_step": round(r5["elapsed"] / args.b512_steps * 1e3, 3),
-                       "round_trip_err": r5["round_trip_err"], "roofline": roofline(r5["stages"], 512),
-                       "stages": per_stage(r5["stages"], 512)}
-        print(f"[bench] B=512: {out['b512']['value']} fwd+inv/s", file=sys.stderr, flush=True)
+    legs = {}
+    if not args.quick:
+        # batched FP32-split at B=128: `batch` copies of the main input, so the
+        # FP64 path's grid of the main leg is the reference of every function
+        nb = args.batch
+        cb = np.tile(c_host, nb)
+        refb = {"grid": ref128["grid"].repeat(nb), "coeffs": ref128["coeffs"].repeat(nb)}
+        for prec in ("fp64", "fp32", "fp32_split"):
+            log(f"B={B} batch={nb} {prec}")
+            r, _ = run_leg([B] * nb, prec, max(5, args.steps // 5), 2, cb, ref=None if prec == "fp64" else refb)
+            legs[f"B{B}_batch{nb}_{prec}"] = r
+        del refb
+        legs[f"B{B}_batch{nb}_fp32_split"]["speedup_vs_fp64_single"] = round(
+            legs[f"B{B}_batch{nb}_fp32_split"]["value"] / value, 3)
+    del ref128
+    torch.cuda.empty_cache()
 
+    if not args.quick and not args.no_b512:
+        log("B=512 FP64")
+        c5 = inputs.coeffs_decay(512, 3)
+        r5, ref5 = run_leg([512], "fp64", args.b512_steps, 1, c5, keep_ref=True)
+        st5 = {k: (v["ms"] * args.b512_steps, args.b512_steps) for k, v in r5["stages"].items()}
+        r5["roofline"] = roofline(st5, 512)
+        legs["B512_fp64"] = r5
+        log(f"B=512 FP64: {r5['value']} fwd+inv/s")
+        for prec in ("fp32", "fp32_split"):
+            log(f"B=512 {prec}")
+            r, _ = run_leg([512], prec, args.b512_steps, 1, c5, ref=ref5)
+            legs[f"B512_{prec}"] = r
+        legs["B512_fp32_split"]["speedup_vs_fp64"] = round(legs["B512_fp32_split"]["value"] / r5["value"], 3)
+        del ref5
+        torch.cuda.empty_cache()
+
+    if not args.quick and not args.no_uneven:
+        n = args.uneven_n
+        Bs, cs = inputs.uneven_batch(n, [16, 32, 64, 128], seed=4)
+        cu = np.concatenate(cs)
+        del cs
+        log(f"uneven: {n} functions, B in {{16,32,64,128}}, {cu.size} coefficients")
+        ru, refu = run_leg(Bs, "fp64", args.uneven_steps, 1, cu, uniform=False, keep_ref=True)
+        legs["uneven256_fp64"] = ru
+        for prec in ("fp32", "fp32_split"):
+            log(f"uneven {prec}")
+            r, _ = run_leg(Bs, prec, args.uneven_steps, 1, cu, uniform=False, ref=refu)
+            r["speedup_vs_fp64"] = round(r["value"] / ru["value"], 3)
+            legs[f"uneven256_{prec}"] = r
+        for k in list(legs):
+            if k.startswith("uneven"):
+                legs[k]["bandwidths"] = {str(b): Bs.count(b) for b in sorted(set(Bs))}
+        del refu
+        torch.cuda.empty_cache()
+
+    out["legs"] = legs
     if args.calibrate_copy:
         out["copy_calibration_bytes"] = calibrate_copy()
 

@@ -56,9 +56,7 @@ __device__ __forceinline__ DD two_sum(double a, double b) {
 // Seed d(l0, l0, m'; b_j) = sqrt((2 l0)!/((l0+m')!(l0-m')!)) cos^{l0+m'}(b/2)
 // sin^{l0-m'}(b/2) for the representative (l0 = m >= m' >= 0), Sect. 2.2.
 // The exponent is summed in double-double so only the final exp rounds.
-__device__ __forceinline__ double seed_d(const PlanView &p, int g, int m, int mp, int j) {
-    const double2 lb = p.lbin[g];
-    const double4 t = p.lcs[j];
+__device__ __forceinline__ double seed_d(double2 lb, double4 t, int m, int mp) {
     const double P = (double)(m + mp), Q = (double)(m - mp);
     DD a = two_prod(P, t.x);
     a.lo = fma(P, t.y, a.lo);
@@ -129,7 +127,8 @@ __device__ __forceinline__ void lds_wait_all() {
 // Work item of a block: runs of 64 items are re-dealt so that one XCD gets 8
 // consecutive items (8 neighbouring groups of one function, whose scattered
 // 16-byte coefficient accesses then meet in one L2); the list itself is
-// largest-cost first.
+// largest-cost first.  Everything a block indexes uniformly comes from its
+// item and from the kernel arguments, so it stays in scalar registers.
 __device__ __forceinline__ int item_of_block(int b, int n) {
     if (b >= (n & ~63)) return b;
     return (b & ~63) + ((b & 7) << 3) + ((b >> 3) & 7);
@@ -171,9 +170,8 @@ __device__ __forceinline__ int out_row(int krow, int r) {
 // Four accumulators keep four MFMA chains in flight (in the FP32 modes each
 // covers 16 beta samples; the split mode keeps the lo products apart).
 template <int NW, int NSUB, int PR>
-__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(const PlanView *__restrict__ views,
+__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
-                                                    const double2 *__restrict__ rec,
                                                     const typename PrecT<PR>::C *__restrict__ S,
                                                     typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
     using C = typename PrecT<PR>::C;
@@ -182,21 +180,17 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(const PlanView *__restrict_
     __shared__ double red[2][NW][256];
     __shared__ double srow[kMaxB];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
-    const PlanView p = views[it.band];
-    const FuncInfo fi = p.funcs[it.func];
-    const int g = it.g;
-    const GroupInfo gi = p.grp[g];
-    const int N = p.N;
-    const int m = gi.m, mp = gi.mp;
-    const int L = p.B - m;
+    const int B = it.B, N = 2 * B;
+    const int m = it.m, mp = it.mp, mask = it.mask;
+    const int L = B - m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long goff = p.goff[g];
+    const long long goff = it.goff;
     const double2 *__restrict__ Rr = rec + goff;
 
-    const C *Sg = S + fi.s_off + (size_t)g * kSlots * N;
+    const C *Sg = S + it.s_off;
     // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
     const int col = lane & 15, krow = lane >> 4;
-    const bool col_present = (gi.mask >> (col >> 1)) & 1;
+    const bool col_present = (mask >> (col >> 1)) & 1;
     R xb[NSUB][16];
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
@@ -211,8 +205,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(const PlanView *__restrict_
         }
         const int j = jbase + lane;
         if (j < N) {
-            x[h] = p.cosb[j];
-            ecur[h] = seed_d(p, g, m, mp, j);
+            x[h] = tab.cosb[it.jbase + j];
+            ecur[h] = seed_d(tab.lbin[it.lbin], tab.lcs[it.jbase + j], m, mp);
         } else {
             x[h] = 0.0;
             ecur[h] = 0.0;
@@ -226,10 +220,10 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(const PlanView *__restrict_
 
     // s_l of the group's rows, read in the panel epilogues (visible after the
     // first panel's barrier).
-    for (int t = threadIdx.x; t < L; t += NW * 64) srow[t] = p.rscale[goff + t];
+    for (int t = threadIdx.x; t < L; t += NW * 64) srow[t] = tab.rscale[goff + t];
     double *pan = panel[wave];
-    R *out = reinterpret_cast<R *>(coeffs + fi.coeff_off);
-    const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
+    R *out = reinterpret_cast<R *>(coeffs + it.coeff_off);
+    const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
     int buf = 0;
     for (int lp = 0; lp < L; lp += 16, buf ^= 1) {
         double tot[4];
@@ -311,7 +305,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(const PlanView *__restrict_
 #pragma unroll
             for (int w = 0; w < NW; ++w) sum += red[buf][w][t];
             const int li = lp + (t >> 4), slot = (t & 15) >> 1;
-            if (li < L && ((gi.mask >> slot) & 1)) {
+            if (li < L && ((mask >> slot) & 1)) {
                 const int l = m + li;
                 int mm, mmp;
                 double sign;
@@ -347,20 +341,21 @@ struct InvGather {
 
 // Gather chunk c (degrees c*32 .. c*32+31) of group g: element e = row*16 + col.
 template <int NT, typename R, typename C>
-__device__ __forceinline__ void inv_gather(InvGather<NT, R> &st, const PlanView &p, const R *__restrict__ cin,
-                                           const GroupInfo &gi, long long goff, int L, int c, double v0) {
+__device__ __forceinline__ void inv_gather(InvGather<NT, R> &st, const double *__restrict__ rscale,
+                                           const R *__restrict__ cin, const WorkItem &it, int L, int c,
+                                           double v0) {
 #pragma unroll
     for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
         const int row = e >> 4, col = e & 15, slot = col >> 1;
         const int li = c * kChunk + row;
         double val = 0.0;
-        if (e < kChunk * 16 && li < L && ((gi.mask >> slot) & 1)) {
-            const int l = gi.m + li;
+        if (e < kChunk * 16 && li < L && ((it.mask >> slot) & 1)) {
+            const int l = it.m + li;
             int mm, mmp;
             double sign;
-            group_member(slot, gi.m, gi.mp, l, mm, mmp, sign);
-            const double f = sign * p.rscale[goff + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
+            group_member(slot, it.m, it.mp, l, mm, mmp, sign);
+            const double f = sign * rscale[it.goff + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
             val = (double)cin[2 * coeff_index(l, mm, mmp) + (col & 1)] * f;
         }
         st.v[k] = (R)val;
@@ -377,9 +372,8 @@ __device__ __forceinline__ void inv_put(const InvGather<NT, R> &st, R *buf) {
 }
 
 template <int NW, int NSUB, int PR>
-__global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict__ views,
+__global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
-                                                    const double2 *__restrict__ rec,
                                                     const typename PrecT<PR>::C *__restrict__ coeffs,
                                                     typename PrecT<PR>::C *__restrict__ S, int apply_v) {
     using C = typename PrecT<PR>::C;
@@ -388,30 +382,25 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict_
     __shared__ double panel[NW][64 * 16];
     __shared__ R stage[2][kChunk * 16];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
-    const PlanView p = views[it.band];
-    const FuncInfo fi = p.funcs[it.func];
-    const int g = it.g;
-    const GroupInfo gi = p.grp[g];
-    const int N = p.N;
-    const int m = gi.m, mp = gi.mp;
-    const int L = p.B - m;
+    const int B = it.B, N = 2 * B;
+    const int m = it.m, mp = it.mp;
+    const int L = B - m;
     const int nchunk = (L + kChunk - 1) / kChunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
-    const long long goff = p.goff[g];
-    const double2 *__restrict__ Rr = rec + goff;
-    const R *__restrict__ cin = reinterpret_cast<const R *>(coeffs + fi.coeff_off);
-    const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)p.B) : 0.0;
+    const double2 *__restrict__ Rr = rec + it.goff;
+    const R *__restrict__ cin = reinterpret_cast<const R *>(coeffs + it.coeff_off);
+    const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
 
     InvGather<NT, R> st;
-    inv_gather<NT, R, C>(st, p, cin, gi, goff, L, 0, v0);
+    inv_gather<NT, R, C>(st, tab.rscale, cin, it, L, 0, v0);
 
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int j = (wave * NSUB + h) * 64 + lane;
-        x[h] = j < N ? p.cosb[j] : 0.0;
-        ecur[h] = j < N ? seed_d(p, g, m, mp, j) : 0.0;
+        x[h] = j < N ? tab.cosb[it.jbase + j] : 0.0;
+        ecur[h] = j < N ? seed_d(tab.lbin[it.lbin], tab.lcs[it.jbase + j], m, mp) : 0.0;
         eprev[h] = 0.0;
     }
     v4d acc[NSUB][4];
@@ -425,7 +414,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict_
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
 
     inv_put<NT, R>(st, stage[0]);
-    if (nchunk > 1) inv_gather<NT, R, C>(st, p, cin, gi, goff, L, 1, v0);
+    if (nchunk > 1) inv_gather<NT, R, C>(st, tab.rscale, cin, it, L, 1, v0);
     __syncthreads();
 
     double *pan = panel[wave];
@@ -493,7 +482,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict_
         if (lp + 16 - ch * kChunk == kChunk || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
                 inv_put<NT, R>(st, stage[(ch + 1) & 1]);
-                if (ch + 2 < nchunk) inv_gather<NT, R, C>(st, p, cin, gi, goff, L, ch + 2, v0);
+                if (ch + 2 < nchunk) inv_gather<NT, R, C>(st, tab.rscale, cin, it, L, ch + 2, v0);
             }
             __syncthreads();
         }
@@ -502,7 +491,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict_
     // Register r of lane holds Y[j = 16 t + out_row(krow, r)][c = col] of tile t.
     // Transpose through the wave's panel (pairs (re, im) swizzled by j) and
     // store each slot's beta samples contiguously.
-    C *Sg = S + fi.s_off + (size_t)g * kSlots * N;
+    C *Sg = S + it.s_off;
     const int slot = col >> 1, part = col & 1;
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
@@ -520,7 +509,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(const PlanView *__restrict_
             C o;
             o.x = (R)v.x;
             o.y = (R)v.y;
-            if (j < N && ((gi.mask >> s2) & 1)) Sg[(size_t)s2 * N + j] = o;
+            if (j < N && ((it.mask >> s2) & 1)) Sg[(size_t)s2 * N + j] = o;
         }
     }
 }
@@ -535,15 +524,15 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
 // Launch shapes (waves x subsets of 64 beta samples): 1x1, 2x1, 4x1, 8x1, 8x2
 // for 2B <= 64, 128, 256, 512, 1024.
 template <int PR>
-hipError_t launch_dwt_fwd(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
-                          const double2 *rec, const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs,
-                          bool apply_v, hipStream_t s) {
+hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
+                          const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
+                          hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int av = apply_v;
     const dim3 grid(nitems);
 #define SOFT_DWT_FWD(NW_, NS_)                                                                               \
     if (nw == NW_ && nsub == NS_) {                                                                          \
-        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, views, items, nitems, rec, \
+        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items, nitems, \
                            S, coeffs, av);                                                                   \
         return hipGetLastError();                                                                            \
     }
@@ -557,15 +546,15 @@ hipError_t launch_dwt_fwd(const PlanView *views, const WorkItem *items, int nite
 }
 
 template <int PR>
-hipError_t launch_dwt_inv(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
-                          const double2 *rec, const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S,
-                          bool apply_v, hipStream_t s) {
+hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
+                          const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
+                          hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int av = apply_v;
     const dim3 grid(nitems);
 #define SOFT_DWT_INV(NW_, NS_)                                                                               \
     if (nw == NW_ && nsub == NS_) {                                                                          \
-        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, views, items, nitems, rec, \
+        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items, nitems, \
                            coeffs, S, av);                                                                   \
         return hipGetLastError();                                                                            \
     }
@@ -578,10 +567,10 @@ hipError_t launch_dwt_inv(const PlanView *views, const WorkItem *items, int nite
     return hipErrorInvalidValue;
 }
 
-#define SOFT_DWT_INSTANTIATE(PR)                                                                              \
-    template hipError_t launch_dwt_fwd<PR>(const PlanView *, const WorkItem *, int, int, int, const double2 *, \
-                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);           \
-    template hipError_t launch_dwt_inv<PR>(const PlanView *, const WorkItem *, int, int, int, const double2 *, \
+#define SOFT_DWT_INSTANTIATE(PR)                                                                          \
+    template hipError_t launch_dwt_fwd<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
+                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);       \
+    template hipError_t launch_dwt_inv<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
                                            const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);
 SOFT_DWT_INSTANTIATE(P64)
 SOFT_DWT_INSTANTIATE(P32)

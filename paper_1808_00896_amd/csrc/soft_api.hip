@@ -33,6 +33,7 @@ using soft::WorkItem;
 
 struct Band {
     int B = 0, N = 0, G = 0;
+    int jbase = 0, gbase = 0;  // first entry in the plan-wide beta and group tables
     long long Nc = 0, rows = 0, row_base = 0;
     std::vector<int> funcs;  // plan function indices, increasing
     size_t tab_off = 0;      // byte offset of the band's tables in the table block
@@ -58,7 +59,7 @@ struct soft_plan_s {
     void *S = nullptr, *t1 = nullptr;
     double2 *rec = nullptr;
     double *rscale = nullptr;
-    const PlanView *d_views = nullptr;
+    soft::DwtTables dtab{};
     size_t ws_bytes = 0;
     // stage timing
     struct Pending {
@@ -95,9 +96,10 @@ void split_dd(long double x, double &hi, double &lo) {
     lo = (double)(x - (long double)hi);
 }
 
-// Byte offsets of one band's tables, each 256-byte aligned.
+// Byte offsets of one band's own tables, each 256-byte aligned (its beta
+// and log-binomial tables are slices of plan-wide arrays).
 struct BandLayout {
-    size_t w, cosb, lcs, lbin, grp, goff, twp, twm, twpf, twmf, bfuncs, total;
+    size_t w, grp, goff, twp, twm, twpf, twmf, bfuncs, total;
 };
 
 BandLayout band_layout(const Band &b) {
@@ -105,9 +107,6 @@ BandLayout band_layout(const Band &b) {
     BandLayout t{};
     size_t o = 0;
     t.w = o;      o = align256(o + sizeof(double) * N);
-    t.cosb = o;   o = align256(o + sizeof(double) * N);
-    t.lcs = o;    o = align256(o + sizeof(double4) * N);
-    t.lbin = o;   o = align256(o + sizeof(double2) * G);
     t.grp = o;    o = align256(o + sizeof(GroupInfo) * G);
     t.goff = o;   o = align256(o + sizeof(long long) * G);
     t.twp = o;    o = align256(o + sizeof(double2) * N);
@@ -119,13 +118,22 @@ BandLayout band_layout(const Band &b) {
     return t;
 }
 
-// Fills one band's tables at host address base (laid out by band_layout).
-int fill_band(const Band &b, const BandLayout &lay, unsigned char *base) {
+// Symmetry-group mask of representative (m, m'): slots (m,m'), (-m,-m'),
+// (m',m), (-m',-m) at beta and (-m,m'), (m,-m'), (-m',m), (m',-m) at pi - beta,
+// keeping one slot per distinct pair.
+int group_mask(int m, int mp) {
+    if (m == 0) return 0x01;
+    if (mp == 0) return 0x0f;
+    if (mp == m) return 0x33;
+    return 0xff;
+}
+
+// Fills one band's tables at host address base (laid out by band_layout) and
+// its slices cosb[N], lcs[N], lbin[G] of the plan-wide arrays.
+int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double *cosb, double4 *lcs,
+              double2 *lbin) {
     const int B = b.B, N = b.N, P = 2 * B - 1;
     double *w = reinterpret_cast<double *>(base + lay.w);
-    double *cosb = reinterpret_cast<double *>(base + lay.cosb);
-    double4 *lcs = reinterpret_cast<double4 *>(base + lay.lcs);
-    double2 *lbin = reinterpret_cast<double2 *>(base + lay.lbin);
     GroupInfo *grp = reinterpret_cast<GroupInfo *>(base + lay.grp);
     long long *goff = reinterpret_cast<long long *>(base + lay.goff);
     double2 *twp = reinterpret_cast<double2 *>(base + lay.twp);
@@ -159,11 +167,7 @@ int fill_band(const Band &b, const BandLayout &lay, unsigned char *base) {
     int g = 0;
     for (int m = 0; m < B; ++m) {
         for (int mp = 0; mp <= m; ++mp, ++g) {
-            int mask;
-            if (m == 0) mask = 0x01;
-            else if (mp == 0) mask = 0x0f;
-            else if (mp == m) mask = 0x33;
-            else mask = 0xff;
+            const int mask = group_mask(m, mp);
             grp[g] = GroupInfo{m, mp, mask, 0};
             goff[g] = row;
             row += B - m;
@@ -268,8 +272,7 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     }
     for (const LaunchGroup &lg : p->groups) {
         if (e == hipSuccess)
-            e = soft::launch_dwt_fwd<PR>(p->d_views, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, p->rec, S, cout_,
-                                         scaled, s);
+            e = soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, S, cout_, scaled, s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
     }
     return e;
@@ -289,8 +292,7 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     hipError_t e = clk.start();
     for (const LaunchGroup &lg : p->groups) {
         if (e == hipSuccess)
-            e = soft::launch_dwt_inv<PR>(p->d_views, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, p->rec, cin, S,
-                                         scaled, s);
+            e = soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, cin, S, scaled, s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
     }
     for (const Band &b : p->bands) {
@@ -342,11 +344,16 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
         std::vector<int> distinct(Bs, Bs + n);
         std::sort(distinct.begin(), distinct.end());
         distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+        int jtot = 0, gtot = 0;
         for (int B : distinct) {
             Band b;
             b.B = B;
             b.N = 2 * B;
             b.G = B * (B + 1) / 2;
+            b.jbase = jtot;
+            b.gbase = gtot;
+            jtot += b.N;
+            gtot += b.G;
             b.Nc = (long long)B * (4LL * B * B - 1) / 3;
             for (int m = 0; m < B; ++m) b.rows += (long long)(m + 1) * (B - m);
             b.row_base = p->rows_total;
@@ -387,6 +394,19 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
             }
             group_bands[gi].push_back((int)bi);
         }
+        // Per band and group g (ordered by m, then m'): m and the first row.
+        std::vector<std::vector<int>> gm(p->bands.size());
+        std::vector<std::vector<long long>> grow(p->bands.size());
+        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+            const Band &b = p->bands[bi];
+            long long row = b.row_base;
+            for (int m = 0; m < b.B; ++m)
+                for (int mp = 0; mp <= m; ++mp) {
+                    gm[bi].push_back(m);
+                    grow[bi].push_back(row);
+                    row += b.B - m;
+                }
+        }
         // Work lists: runs of 8 consecutive groups of one function (the XCD
         // remap hands each run to one XCD), ordered by the cost (B - m) 2B of
         // their first group, largest first, so the long recurrences start
@@ -400,16 +420,29 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
             std::vector<Run> runs;
             for (int bi : group_bands[gi]) {
                 const Band &b = p->bands[bi];
-                std::vector<int> m_of(b.G);
-                for (int m = 0, g = 0; m < b.B; ++m)
-                    for (int mp = 0; mp <= m; ++mp) m_of[g++] = m;
                 for (int f : b.funcs)
                     for (int g0 = 0; g0 < b.G; g0 += 8)
-                        runs.push_back({(long long)(b.B - m_of[g0]) * b.N, bi, f, g0, std::min(b.G, g0 + 8)});
+                        runs.push_back({(long long)(b.B - gm[bi][g0]) * b.N, bi, f, g0, std::min(b.G, g0 + 8)});
             }
             std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.cost > c.cost; });
-            for (const Run &r : runs)
-                for (int g = r.g0; g < r.g1; ++g) lists[gi].push_back(WorkItem{r.band, r.func, g, 0});
+            for (const Run &r : runs) {
+                const Band &b = p->bands[r.band];
+                const FuncInfo &fi = p->funcs[r.func];
+                for (int g = r.g0; g < r.g1; ++g) {
+                    const int m = gm[r.band][g], mp = g - m * (m + 1) / 2;
+                    WorkItem w{};
+                    w.goff = grow[r.band][g];
+                    w.s_off = fi.s_off + (long long)g * kSlots * b.N;
+                    w.coeff_off = fi.coeff_off;
+                    w.B = b.B;
+                    w.jbase = b.jbase;
+                    w.lbin = b.gbase + g;
+                    w.m = m;
+                    w.mp = mp;
+                    w.mask = group_mask(m, mp);
+                    lists[gi].push_back(w);
+                }
+            }
             LaunchGroup lg;
             lg.nw = shapes[gi].first;
             lg.nsub = shapes[gi].second;
@@ -427,16 +460,25 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
         }
         const size_t funcs_off = off;
         off = align256(off + sizeof(FuncInfo) * n);
-        const size_t views_off = off;
-        off = align256(off + sizeof(PlanView) * p->bands.size());
+        const size_t cosb_off = off;
+        off = align256(off + sizeof(double) * jtot);
+        const size_t lcs_off = off;
+        off = align256(off + sizeof(double4) * jtot);
+        const size_t lbin_off = off;
+        off = align256(off + sizeof(double2) * gtot);
         for (size_t gi = 0; gi < p->groups.size(); ++gi) {
             p->groups[gi].items_off = off;
             off = align256(off + sizeof(WorkItem) * lists[gi].size());
         }
         const size_t total = off;
         std::vector<unsigned char> host(total, 0);
+        double *cosb_h = reinterpret_cast<double *>(host.data() + cosb_off);
+        double4 *lcs_h = reinterpret_cast<double4 *>(host.data() + lcs_off);
+        double2 *lbin_h = reinterpret_cast<double2 *>(host.data() + lbin_off);
         for (size_t bi = 0; bi < p->bands.size(); ++bi) {
-            const int rc = fill_band(p->bands[bi], lays[bi], host.data() + p->bands[bi].tab_off);
+            const Band &b = p->bands[bi];
+            const int rc = fill_band(b, lays[bi], host.data() + b.tab_off, cosb_h + b.jbase, lcs_h + b.jbase,
+                                     lbin_h + b.gbase);
             if (rc != SOFT_OK) {
                 delete p;
                 return rc;
@@ -457,9 +499,12 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
         }
         p->ws_bytes = total + (p->s_total + p->t1_elems) * p->csize + rec_rows * (sizeof(double2) + sizeof(double));
 
-        // Band views with device pointers, kept on the host (FFT launches)
-        // and in the table block (DWT work lists).
-        std::vector<PlanView> views;
+        // Band views with device pointers (kernel arguments of the FFT passes
+        // and of the recurrence fill), and the DWT kernels' plan-wide tables.
+        const double *cosb_d = reinterpret_cast<const double *>(p->tables + cosb_off);
+        const double4 *lcs_d = reinterpret_cast<const double4 *>(p->tables + lcs_off);
+        const double2 *lbin_d = reinterpret_cast<const double2 *>(p->tables + lbin_off);
+        p->dtab = soft::DwtTables{cosb_d, lcs_d, lbin_d, p->rscale, p->rec};
         for (size_t bi = 0; bi < p->bands.size(); ++bi) {
             Band &b = p->bands[bi];
             const BandLayout &lay = lays[bi];
@@ -472,9 +517,9 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
             v.Nc = b.Nc;
             v.rows = b.rows;
             v.w = reinterpret_cast<const double *>(base + lay.w);
-            v.cosb = reinterpret_cast<const double *>(base + lay.cosb);
-            v.lcs = reinterpret_cast<const double4 *>(base + lay.lcs);
-            v.lbin = reinterpret_cast<const double2 *>(base + lay.lbin);
+            v.cosb = cosb_d + b.jbase;
+            v.lcs = lcs_d + b.jbase;
+            v.lbin = lbin_d + b.gbase;
             v.grp = reinterpret_cast<const GroupInfo *>(base + lay.grp);
             v.goff = reinterpret_cast<const long long *>(base + lay.goff);
             v.twp = reinterpret_cast<const double2 *>(base + lay.twp);
@@ -484,10 +529,7 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
             v.rscale = p->rscale;
             v.funcs = reinterpret_cast<const FuncInfo *>(p->tables + funcs_off);
             v.band_funcs = reinterpret_cast<const int *>(base + lay.bfuncs);
-            views.push_back(v);
         }
-        std::memcpy(host.data() + views_off, views.data(), sizeof(PlanView) * views.size());
-        p->d_views = reinterpret_cast<const PlanView *>(p->tables + views_off);
 
         hipError_t e = hipMemcpy(p->tables, host.data(), total, hipMemcpyHostToDevice);
         // Padding rows are read (never used) by prefetches; give them defined values.

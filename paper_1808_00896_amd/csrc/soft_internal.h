@@ -97,8 +97,8 @@ struct GroupInfo {
 // Arithmetic of a plan.  P64: complex128 data, FP64 throughout.  P32:
 // complex64 data, FP32 FFTs and FP32 MFMA contractions with d rounded to
 // FP32.  P32S: as P32 but d is split into hi + lo FP32 parts (two MFMA
-// products) and partial sums over 16 beta samples or 16 degrees are combined
-// in FP64.  In every mode the seeds, the recurrence, s_l, V_B and w_B(j) stay
+// products).  In both FP32 modes the partial sums (at most 32 beta samples
+// or 16 degrees) are combined in FP64.  In every mode the seeds, the recurrence, s_l, V_B and w_B(j) stay
 // in FP64.
 enum Prec { P64 = 0, P32 = 1, P32S = 2 };
 template <int PR>
@@ -119,9 +119,28 @@ struct FuncInfo {
     int band, pad;
 };
 
-// One DWT work item: symmetry group g of function func in band band.
+// One DWT work item: one symmetry group of one function, carrying every
+// value a block indexes uniformly (so none of them comes through a pointer
+// loaded from memory, which the compiler would treat as divergent).
 struct WorkItem {
-    int band, func, g, pad;
+    long long goff;       // first row of the group in the plan-wide recurrence tables
+    long long s_off;      // the group's beta-sample block in S (complex elements)
+    long long coeff_off;  // the function's coefficient vector (complex elements)
+    int B;                // bandwidth of the function
+    int jbase;            // the band's first entry in the plan-wide beta tables
+    int lbin;             // the group's entry in the plan-wide log-binomial table
+    int m, mp;            // representative, m >= mp >= 0
+    int mask;             // bit s set when slot s is present
+};
+
+// Plan-wide tables of the DWT kernels (kernel arguments).
+struct DwtTables {
+    const double *cosb;   // cos(beta_j), band by band
+    const double4 *lcs;   // (log cos(b_j/2) hi, lo, log sin(b_j/2) hi, lo), band by band
+    const double2 *lbin;  // 0.5 log((2m)!/((m+m')!(m-m')!)) as (hi, lo), group by group
+    const double *rscale; // s_l per row (d(l) = s_l e(l))
+    const double2 *rec;   // (alpha_l, gamma_l) per row (the kernels take it as a separate
+                          // restrict argument, so its loads can use the scalar cache)
 };
 
 // Device-side view of one band (all functions of one bandwidth).
@@ -131,9 +150,9 @@ struct PlanView {
     long long Nc;          // coefficients per function
     long long rows;        // group rows (one per group and degree) per function
     const double *w;       // [N]   quadrature weights w_B(j)
-    const double *cosb;    // [N]   cos(beta_j)
-    const double4 *lcs;    // [N]   (log cos(b_j/2) hi, lo, log sin(b_j/2) hi, lo)
-    const double2 *lbin;   // [G]   0.5 log((2m)!/((m+m')!(m-m')!)) as (hi, lo)
+    const double *cosb;    // [N]   cos(beta_j) (slice of the plan-wide table)
+    const double4 *lcs;    // [N]   (log cos(b_j/2) hi, lo, log sin(b_j/2) hi, lo) (slice)
+    const double2 *lbin;   // [G]   0.5 log((2m)!/((m+m')!(m-m')!)) as (hi, lo) (slice)
     const GroupInfo *grp;  // [G]
     const long long *goff; // [G]   first row of group g in the plan's per-row tables
     const double2 *twp;    // [N]   e^{+2 pi i k/N}
@@ -160,18 +179,18 @@ hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool ap
 // goff[g]; rec and rscale are the plan-wide tables).
 hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s);
 
-// DWT and iDWT over a work list (one block per item), all items sharing one
-// launch shape: nw waves, nsub subsets of 64 beta samples per wave.  views is
-// the device copy of the plan's band views.  The forward writes the l-major
+// DWT and iDWT over a device work list (one block per item), all items
+// sharing one launch shape: nw waves, nsub subsets of 64 beta samples per
+// wave (nw * nsub * 64 >= 2B of every item).  The forward writes the l-major
 // coefficients (symmetry signs, s_l and, when apply_v, V_B applied); the
 // inverse reads them.
 template <int PR>
-hipError_t launch_dwt_fwd(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
-                          const double2 *rec, const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs,
-                          bool apply_v, hipStream_t s);
+hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
+                          const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
+                          hipStream_t s);
 template <int PR>
-hipError_t launch_dwt_inv(const PlanView *views, const WorkItem *items, int nitems, int nw, int nsub,
-                          const double2 *rec, const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S,
-                          bool apply_v, hipStream_t s);
+hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
+                          const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
+                          hipStream_t s);
 
 }  // namespace soft
