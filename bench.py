@@ -69,8 +69,11 @@ def stage_work(Bs, prec="fp64"):
 
 
 def source_digest(kind):
-    path = os.path.join(ROOT, "paper_1808_00896_amd", "csrc", KERNEL_SOURCES[kind])
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of a kernel's source file and the shared header it includes."""
+    h = hashlib.sha256()
+    for name in (KERNEL_SOURCES[kind], "soft_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1808_00896_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(stage, B):
