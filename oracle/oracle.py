@@ -197,3 +197,54 @@ def forward_pairs(B, grid, pairs, prec="f64"):
                                            p.ctypes.data_as(_ip), _ptr(out.view(np.float64))),
            "forward_pairs")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Rotational-matching head (correlation of two functions on the sphere,
+# the application motivated in Sect. 1): plain definitions in numpy.
+# ---------------------------------------------------------------------------
+
+def sh_index(l, m):
+    """Position of the spherical-harmonic coefficient (l, m) in a vector of
+    B^2 entries ordered by degree, then order m = -l..l."""
+    return l * l + m + l
+
+
+def correlation_coeffs(B, a, b):
+    """SO(3) coefficients of the correlation of two functions on the sphere:
+    f°(l, M, M') = a(l, M) * conj(b(l, M')), for 0 <= l < B, |M|, |M'| <= l,
+    in the layout of ``coeff_index``.  a, b: B^2 complex coefficients each."""
+    a = _c128(a).reshape(-1)
+    b = _c128(b).reshape(-1)
+    assert a.size == b.size == B * B
+    out = np.empty(num_coeffs(B), np.complex128)
+    for l in range(B):
+        al = a[l * l:(l + 1) * (l + 1)]
+        bl = b[l * l:(l + 1) * (l + 1)]
+        o = coeff_index(l, -l, -l)
+        # row M, column M': a(l, M) conj(b(l, M'))
+        out[o:o + (2 * l + 1) ** 2] = np.outer(al, np.conj(bl)).reshape(-1)
+    return out
+
+
+def correlation_coeffs_vjp(B, a, b, g):
+    """Vector-Jacobian product of ``correlation_coeffs`` in the convention of
+    complex autograd (gradients are conjugate Wirtinger derivatives):
+    ga(l, M) = sum_M' g(l, M, M') b(l, M'),  gb(l, M') = sum_M conj(g(l, M, M')) a(l, M)."""
+    a = _c128(a).reshape(-1)
+    b = _c128(b).reshape(-1)
+    g = _c128(g).reshape(-1)
+    ga = np.empty(B * B, np.complex128)
+    gb = np.empty(B * B, np.complex128)
+    for l in range(B):
+        n = 2 * l + 1
+        o = coeff_index(l, -l, -l)
+        G = g[o:o + n * n].reshape(n, n)
+        ga[l * l:l * l + n] = G @ b[l * l:l * l + n]
+        gb[l * l:l * l + n] = np.conj(G).T @ a[l * l:l * l + n]
+    return ga, gb
+
+
+def argmax_real(grid):
+    """Flat index of the largest real part (the first one on exact ties)."""
+    return int(np.argmax(np.asarray(grid).real.reshape(-1)))

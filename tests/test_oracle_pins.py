@@ -307,3 +307,77 @@ def test_slice_and_pairs_agree_with_full(oracle):
         for l in range(B):
             want = full[oracle.coeff_index(l, m, mp)] if l >= max(abs(m), abs(mp)) else 0
             assert abs(got[p, l] - want) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Rotational-matching head
+# --------------------------------------------------------------------------
+
+def test_correlation_coeffs_single_term_peaks(oracle):
+    """One nonzero product picks one Wigner-D function, whose real part has a
+    maximum fixed by the closed form of d(1, 1, 0) = sin(b)/sqrt(2) and
+    D = e^{-i m a} d e^{-i m' g}: with a(1, 1) = i and b(1, 0) = 1 the grid is
+    i e^{-i a} sin(b)/sqrt 2, largest at a = pi/2, b nearest pi/2, g = 0.
+    Putting the conjugate on a, or swapping M and M', moves the peak."""
+    B = 4
+    N = 2 * B
+    a = np.zeros(B * B, complex)
+    b = np.zeros(B * B, complex)
+    a[oracle.sh_index(1, 1)] = 1j
+    b[oracle.sh_index(1, 0)] = 1.0
+    c = oracle.correlation_coeffs(B, a, b)
+    nz = np.flatnonzero(c)
+    assert list(nz) == [oracle.coeff_index(1, 1, 0)] and c[nz[0]] == 1j
+    g = oracle.inverse(B, c).reshape(N, N, N)
+    i, j, k = np.unravel_index(oracle.argmax_real(g), g.shape)
+    assert (i, k) == (B // 2, 0)                      # alpha = pi/2, gamma = 0
+    assert j in (B - 1, B)                            # beta_j closest to pi/2 (tie: the first)
+    assert j == B - 1
+    beta = (2 * np.arange(N) + 1) * np.pi / (4 * B)
+    want = np.sin(np.pi / 2) * np.sin(beta[j]) / np.sqrt(2)
+    assert abs(g[i, j, k].real - want) < 1e-14
+
+
+def test_correlation_coeffs_against_loops(oracle):
+    """Element by element against the definition written as nested loops."""
+    B = 5
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)
+    b = rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)
+    c = oracle.correlation_coeffs(B, a, b)
+    for l in range(B):
+        for M in range(-l, l + 1):
+            for Mp in range(-l, l + 1):
+                want = a[l * l + M + l] * np.conj(b[l * l + Mp + l])
+                # one complex product: equal up to its rounding order
+                assert abs(c[oracle.coeff_index(l, M, Mp)] - want) <= 4e-16 * abs(want)
+
+
+def test_correlation_vjp_matches_finite_differences(oracle):
+    """The vector-Jacobian product against central differences of the real
+    functional L = Re <g, f°(a, b)> in the real and imaginary directions."""
+    B = 3
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)
+    b = rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)
+    g = rng.standard_normal(oracle.num_coeffs(B)) + 1j * rng.standard_normal(oracle.num_coeffs(B))
+    ga, gb = oracle.correlation_coeffs_vjp(B, a, b, g)
+
+    def L(a_, b_):
+        return float(np.real(np.vdot(g, oracle.correlation_coeffs(B, a_, b_))))
+
+    h = 1e-6
+    for idx in range(B * B):
+        for unit in (1.0, 1j):
+            e = np.zeros(B * B, complex)
+            e[idx] = unit
+            da = (L(a + h * e, b) - L(a - h * e, b)) / (2 * h)
+            db = (L(a, b + h * e) - L(a, b - h * e)) / (2 * h)
+            # gradient convention: dL = Re(conj(grad) * dz)
+            assert abs(da - np.real(np.conj(ga[idx]) * unit)) < 1e-8
+            assert abs(db - np.real(np.conj(gb[idx]) * unit)) < 1e-8
+
+
+def test_argmax_real_first_on_ties(oracle):
+    x = np.array([1.0, 3.0 + 5j, 3.0, -2.0, 3.0 - 1j])
+    assert oracle.argmax_real(x) == 1
