@@ -54,7 +54,7 @@ def stage_work(Bs, prec="fp64"):
     """
     cs = CSIZE[prec]
     tot = {k: 0.0 for k in ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "dwt_inv", "fft_alpha_inv",
-                            "fft_gamma_inv")}
+                            "fft_gamma_inv", "match_coeffs", "argmax")}
     for B in Bs:
         N, P = 2 * B, 2 * B - 1
         steps = sum((m + 1) * (B - 1 - m) for m in range(B))  # recurrence steps over groups m >= m' >= 0
@@ -65,6 +65,8 @@ def stage_work(Bs, prec="fp64"):
         tot["dwt_inv"] += dwt
         tot["fft_alpha_inv"] += cs * (N * P * P + N * N * (N - 1))
         tot["fft_gamma_inv"] += cs * (N * N * (N - 1) + N ** 3)
+        tot["match_coeffs"] += cs * (num_coeffs(B) + 2 * B * B)  # write f°, read a and b
+        tot["argmax"] += cs * N ** 3                              # read the grid
     return {k: ("flop" if k.startswith("dwt") else "hbm", v) for k, v in tot.items()}
 
 
@@ -217,6 +219,61 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=Fa
     return res, out
 
 
+def match_leg(steps, B=128, n=64):
+    """Rotational matching of 64 pairs at B = 128: correlation coefficients,
+    inverse transform to 64 grids of 256^3, argmax of each.  FP32-split timed;
+    the FP64 path run once for the argmax agreement and the grid error."""
+    import torch
+    from paper_1808_00896_amd import inputs, soft
+    a_h, b_h = inputs.sh_pair_batch(n, B, seed=6)
+    legs = {}
+    ref = None
+    for prec in ("fp64", "fp32_split"):
+        log(f"match {n} pairs B={B} {prec}")
+        m = soft.MatchPlan(B, n, precision=prec)
+        a = torch.from_numpy(a_h).cuda().to(m.dtype)
+        b = torch.from_numpy(b_h).cuda().to(m.dtype)
+        grid = torch.empty(m.plan.grid_shape(), dtype=m.dtype, device="cuda")
+        idx = torch.empty(n, dtype=torch.int64, device="cuda")
+        k = steps if prec == "fp32_split" else 2
+        for _ in range(2):
+            m.match(a, b, grid, idx)
+        torch.cuda.synchronize()
+        h = m.plan.handle
+        soft.soft_plan_stage_times(h, reset=True)
+        soft.soft_plan_set_timing(h, True)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            m.match(a, b, grid, idx)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        soft.soft_plan_set_timing(h, False)
+        st = soft.soft_plan_stage_times(h, reset=True)
+        r = {"pairs": n, "B": B, "precision": prec, "steps": k, "value": round(n * k / el, 2),
+             "unit": "pairs/s (coefficients + inverse + argmax)", "ms_per_step": round(el / k * 1e3, 3),
+             "stages": per_stage(st, [B] * n, k, prec)}
+        if ref is None:
+            ref = {"grid": grid, "idx": idx.cpu().numpy()}
+        else:
+            ix = idx.cpu().numpy()
+            r["argmax_agree_with_fp64"] = int((ix == ref["idx"]).sum())
+            near = 0
+            g64 = ref["grid"].reshape(n, -1)
+            for f in np.flatnonzero(ix != ref["idx"]):
+                g = g64[f]
+                gap = float(g[int(ref["idx"][f])].real - g[int(ix[f])].real)
+                near += gap <= 2e-6 * float(g.abs().max())
+            r["argmax_near_ties"] = int(near)
+            r["grid_err_vs_fp64"] = relerr_dev(grid, ref["grid"])
+            r["speedup_vs_fp64"] = round(r["value"] / legs[f"match{n}_B{B}_fp64"]["value"], 3)
+            del ref
+        legs[f"match{n}_B{B}_{prec}"] = r
+        m.close()
+        del a, b, grid
+        torch.cuda.empty_cache()
+    return legs
+
+
 def cpu_baseline(B, c_host, budget_s=12.0, max_reps=3):
     from oracle import oracle as O
     reps, t = 0, 0.0
@@ -261,6 +318,8 @@ def main():
     ap.add_argument("--batch", type=int, default=16, help="functions per batched FP32-split call at B=128")
     ap.add_argument("--uneven-n", type=int, default=256)
     ap.add_argument("--uneven-steps", type=int, default=5)
+    ap.add_argument("--no-match", action="store_true")
+    ap.add_argument("--match-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -363,6 +422,9 @@ def main():
                 legs[k]["bandwidths"] = {str(b): Bs.count(b) for b in sorted(set(Bs))}
         del refu
         torch.cuda.empty_cache()
+
+    if not args.quick and not args.no_match:
+        legs.update(match_leg(args.match_steps))
 
     out["legs"] = legs
     if args.calibrate_copy:

@@ -186,6 +186,8 @@ int soft_adjoint_inverse(soft_plan_t plan, const void *grid, void *coeffs, hipSt
  *   0 gamma FFT (forward)      1 alpha FFT + weights (forward)
  *   2 DWT, writing f° (fwd)    3 iDWT, reading f° (inverse)
  *   4 alpha FFT (inverse)      5 gamma FFT (inverse)
+ *   6 correlation coefficients and 7 argmax, recorded by soft_match on the
+ *     plan returned by soft_match_plan_soft.
  */
 enum {
     SOFT_STAGE_FFT_GAMMA_FWD = 0,
@@ -194,7 +196,9 @@ enum {
     SOFT_STAGE_DWT_INV = 3,
     SOFT_STAGE_FFT_ALPHA_INV = 4,
     SOFT_STAGE_FFT_GAMMA_INV = 5,
-    SOFT_NUM_STAGES = 6
+    SOFT_STAGE_MATCH_COEFFS = 6,
+    SOFT_STAGE_ARGMAX = 7,
+    SOFT_NUM_STAGES = 8
 };
 
 /*
@@ -219,6 +223,84 @@ int soft_plan_stage_times(soft_plan_t plan, double *ms, long long *launches, int
  * accepted and ignored.  Returns SOFT_OK or SOFT_ERR_HIP.
  */
 int soft_plan_destroy(soft_plan_t plan);
+
+/*
+ * Rotational-matching head.  Matching two functions on the sphere over
+ * rotations (the application of Sect. 1) correlates them: with a(l, m) and
+ * b(l, m) their spherical-harmonic coefficients, the SO(3) coefficients
+ *   f°(l, M, M') = a(l, M) conj(b(l, M'))
+ * define a function on SO(3) whose inverse transform (soft_inverse) is the
+ * correlation grid, and the grid point of largest real part is the best
+ * rotation on the grid.
+ *
+ * Layouts: a function on the sphere is B^2 complex coefficients, (l, m) at
+ * l^2 + m + l (0 <= l < B, -l <= m <= l); n of them back to back.  SO(3)
+ * coefficients and grids as above, n of each back to back.  Complex type as
+ * the precision says (complex128 for SOFT_FP64, complex64 otherwise).
+ */
+typedef struct soft_match_s *soft_match_t;
+
+/*
+ * soft_match_plan -- plan the head for n pairs at bandwidth B.
+ *   B, precision, flags as for soft_plan; n >= 1 pairs.
+ *   out  receives the handle; unchanged on error.
+ * Owns a soft_plan of n functions of bandwidth B, one set of n coefficient
+ * vectors, and the argmax partial results (16 bytes per pair and scanned
+ * block).  Synchronous.  Returns as soft_plan.
+ */
+int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out);
+
+/*
+ * soft_match_sizes -- per-call element counts: sh_elems of each of a and b
+ * (n B^2), coeff_elems of the coefficients (n B(4B^2-1)/3) and grid_elems of
+ * the grids (n (2B)^3).  Any pointer may be NULL.
+ */
+int soft_match_sizes(soft_match_t match, size_t *sh_elems, size_t *coeff_elems, size_t *grid_elems);
+
+/*
+ * soft_match_plan_soft -- the soft_plan the head owns (for soft_adjoint_inverse
+ * in a backward pass, or stage timing).  Valid until soft_match_destroy; do
+ * not destroy it.
+ */
+int soft_match_plan_soft(soft_match_t match, soft_plan_t *plan);
+
+/*
+ * soft_match_coeffs -- coeffs = f°(l, M, M') = a(l, M) conj(b(l, M')) for
+ * every pair.  a, b: device, n B^2 each (read only); coeffs: device, written.
+ */
+int soft_match_coeffs(soft_match_t match, const void *a, const void *b, void *coeffs, hipStream_t stream);
+
+/*
+ * soft_match_coeffs_vjp -- vector-Jacobian product of soft_match_coeffs
+ * (gradients as conjugate Wirtinger derivatives, the convention of complex
+ * automatic differentiation): given g = dL/d conj(f°),
+ *   ga(l, M)  = sum_M' g(l, M, M') b(l, M'),
+ *   gb(l, M') = sum_M conj(g(l, M, M')) a(l, M).
+ * a, b, g: device (read only); ga, gb: device, n B^2 each (written).  Sums
+ * run in FP64 in every precision.
+ */
+int soft_match_coeffs_vjp(soft_match_t match, const void *a, const void *b, const void *g, void *ga, void *gb,
+                          hipStream_t stream);
+
+/*
+ * soft_match_argmax -- for each of the n grids, the flat index
+ * (i*2B + j)*2B + k of the largest real part, the smallest such index on
+ * exact ties; NaN entries never win (-1 when every entry is NaN).
+ *   grid   device, n grids (read only).
+ *   index  device, n int64 (written).
+ */
+int soft_match_argmax(soft_match_t match, const void *grid, long long *index, hipStream_t stream);
+
+/*
+ * soft_match -- the whole head: correlation coefficients of every pair (in
+ * the head's own buffer), soft_inverse of them into grid, argmax of each
+ * grid into index.  a, b: device (read only); grid: device, n grids
+ * (written); index: device, n int64 (written).
+ */
+int soft_match(soft_match_t match, const void *a, const void *b, void *grid, long long *index, hipStream_t stream);
+
+/* soft_match_destroy -- release the head and its soft_plan (synchronises the device; NULL ignored). */
+int soft_match_destroy(soft_match_t match);
 
 /* soft_status_string -- static text for a status code (never NULL). */
 const char *soft_status_string(int status);

@@ -6,6 +6,10 @@ convention the backward of y = A x is grad_x = A^H grad_y:
   SoftInverse  (I, eq. "fourier_representation"):        backward = I^H = V^-1 F W^-1
 Both adjoints are entry points of the library (soft_adjoint,
 soft_adjoint_inverse); nothing here computes on the host.
+
+SoftCorrelation forms the correlation coefficients a(l,M) conj(b(l,M')) of
+the rotational-matching head; its backward is the library's vector-Jacobian
+product (soft_match_coeffs_vjp).
 """
 import torch
 
@@ -42,3 +46,29 @@ def soft_forward(grid, plan):
 def soft_inverse(coeffs, plan):
     """Differentiable iFSOFT of `coeffs` with `plan` (a soft.Plan)."""
     return SoftInverse.apply(coeffs, plan)
+
+
+class SoftCorrelation(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a, b, match):
+        a, b = a.contiguous(), b.contiguous()
+        ctx.match = match
+        ctx.save_for_backward(a, b)
+        return match.coeffs(a, b)
+
+    @staticmethod
+    def backward(ctx, grad_coeffs):
+        a, b = ctx.saved_tensors
+        ga, gb = ctx.match.coeffs_vjp(a, b, grad_coeffs.contiguous())
+        return ga, gb, None
+
+
+def correlation_coeffs(a, b, match):
+    """Differentiable correlation coefficients of the pairs (a, b) (a soft.MatchPlan)."""
+    return SoftCorrelation.apply(a, b, match)
+
+
+def correlation_grid(a, b, match):
+    """Differentiable correlation grids: inverse transform of the correlation
+    coefficients with the match plan's own soft.Plan."""
+    return soft_inverse(correlation_coeffs(a, b, match), match.plan)

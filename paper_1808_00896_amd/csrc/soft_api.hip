@@ -73,6 +73,16 @@ struct soft_plan_s {
     long long stage_n[SOFT_NUM_STAGES] = {};
 };
 
+// Rotational-matching head: n pairs of functions on the sphere at bandwidth
+// B, their correlation coefficients, the inverse transform of those (a plan
+// of n functions) and the argmax of each correlation grid.
+struct soft_match_s {
+    int B = 0, n = 0;
+    soft_plan_t plan = nullptr;  // owned
+    void *coeffs = nullptr;      // n coefficient vectors
+    void *part = nullptr;        // argmax partial results
+};
+
 namespace {
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
@@ -87,6 +97,14 @@ void free_plan(soft_plan_s *p) {
     if (p->rec) (void)hipFree(p->rec);
     if (p->rscale) (void)hipFree(p->rscale);
     delete p;
+}
+
+void free_match(soft_match_s *m) {
+    if (!m) return;
+    if (m->coeffs) (void)hipFree(m->coeffs);
+    if (m->part) (void)hipFree(m->part);
+    free_plan(m->plan);
+    delete m;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -220,6 +238,10 @@ class StageClock {
   public:
     StageClock(soft_plan_s *p, hipStream_t s) : p_(p), s_(s) {}
     hipError_t start() { return p_->timing ? record(&prev_) : hipSuccess; }
+    // Continue from the last event another clock on the same plan recorded.
+    void restart_after(soft_plan_s *p) {
+        if (p_->timing && !p->pending.empty()) prev_ = p->pending.back().end;
+    }
     hipError_t lap(int stage) {
         if (!p_->timing) return hipSuccess;
         hipEvent_t e;
@@ -321,6 +343,25 @@ int dispatch(soft_plan_t p, const void *in, void *out, hipStream_t s, bool forwa
             break;
     }
     return hip_status(e);
+}
+
+template <int PR>
+hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, long long *index, hipStream_t s) {
+    using C = typename soft::PrecT<PR>::C;
+    soft_plan_s *p = m->plan;
+    StageClock clk(p, s);
+    hipError_t e = clk.start();
+    if (e == hipSuccess)
+        e = soft::launch_corr_coeffs<C>(m->B, m->n, static_cast<const C *>(a), static_cast<const C *>(b),
+                                        static_cast<C *>(m->coeffs), s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_MATCH_COEFFS);
+    if (e == hipSuccess) e = run_inverse<PR>(p, m->coeffs, grid, s, false);
+    clk.restart_after(p);
+    if (e == hipSuccess)
+        e = soft::launch_argmax_real<C>(static_cast<const C *>(grid), 8LL * m->B * m->B * m->B, m->n, m->part, index,
+                                        s);
+    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_ARGMAX);
+    return e;
 }
 
 bool valid_precision(int precision) {
@@ -648,6 +689,105 @@ int soft_plan_destroy(soft_plan_t p) {
     if (!p) return SOFT_OK;
     const hipError_t e = hipDeviceSynchronize();
     free_plan(p);
+    return hip_status(e);
+}
+
+int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out) {
+    if (!out || B < 1 || n < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!is_pow2(B) || B > 512) return SOFT_ERR_UNSUPPORTED;
+    soft_match_s *m = new (std::nothrow) soft_match_s;
+    if (!m) return SOFT_ERR_OOM;
+    m->B = B;
+    m->n = n;
+    int rc = soft_plan(B, n, precision, 0, &m->plan);
+    if (rc != SOFT_OK) {
+        delete m;
+        return rc;
+    }
+    const long long N3 = 8LL * B * B * B;
+    if (hipMalloc(&m->coeffs, m->plan->coeff_total * m->plan->csize) != hipSuccess ||
+        hipMalloc(&m->part, soft::argmax_workspace_bytes(N3, n)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_match(m);
+        return SOFT_ERR_OOM;
+    }
+    *out = m;
+    return SOFT_OK;
+}
+
+int soft_match_sizes(soft_match_t m, size_t *sh_elems, size_t *coeff_elems, size_t *grid_elems) {
+    if (!m) return SOFT_ERR_INVALID;
+    if (sh_elems) *sh_elems = (size_t)m->n * m->B * m->B;
+    return soft_plan_sizes(m->plan, grid_elems, coeff_elems, nullptr);
+}
+
+int soft_match_plan_soft(soft_match_t m, soft_plan_t *plan) {
+    if (!m || !plan) return SOFT_ERR_INVALID;
+    *plan = m->plan;
+    return SOFT_OK;
+}
+
+int soft_match_coeffs(soft_match_t m, const void *a, const void *b, void *coeffs, hipStream_t s) {
+    if (!m || !b) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, a, coeffs);
+    if (rc != SOFT_OK) return rc;
+    hipError_t e;
+    if (m->plan->precision == SOFT_FP64)
+        e = soft::launch_corr_coeffs<double2>(m->B, m->n, static_cast<const double2 *>(a),
+                                              static_cast<const double2 *>(b), static_cast<double2 *>(coeffs), s);
+    else
+        e = soft::launch_corr_coeffs<float2>(m->B, m->n, static_cast<const float2 *>(a),
+                                             static_cast<const float2 *>(b), static_cast<float2 *>(coeffs), s);
+    return hip_status(e);
+}
+
+int soft_match_coeffs_vjp(soft_match_t m, const void *a, const void *b, const void *gcoeffs, void *ga, void *gb,
+                          hipStream_t s) {
+    if (!m || !b || !gcoeffs || !gb) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, a, ga);
+    if (rc != SOFT_OK) return rc;
+    hipError_t e;
+    if (m->plan->precision == SOFT_FP64)
+        e = soft::launch_corr_vjp<double2>(m->B, m->n, static_cast<const double2 *>(a),
+                                           static_cast<const double2 *>(b), static_cast<const double2 *>(gcoeffs),
+                                           static_cast<double2 *>(ga), static_cast<double2 *>(gb), s);
+    else
+        e = soft::launch_corr_vjp<float2>(m->B, m->n, static_cast<const float2 *>(a), static_cast<const float2 *>(b),
+                                          static_cast<const float2 *>(gcoeffs), static_cast<float2 *>(ga),
+                                          static_cast<float2 *>(gb), s);
+    return hip_status(e);
+}
+
+int soft_match_argmax(soft_match_t m, const void *grid, long long *index, hipStream_t s) {
+    if (!m) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, grid, index);
+    if (rc != SOFT_OK) return rc;
+    const long long N3 = 8LL * m->B * m->B * m->B;
+    hipError_t e;
+    if (m->plan->precision == SOFT_FP64)
+        e = soft::launch_argmax_real<double2>(static_cast<const double2 *>(grid), N3, m->n, m->part, index, s);
+    else
+        e = soft::launch_argmax_real<float2>(static_cast<const float2 *>(grid), N3, m->n, m->part, index, s);
+    return hip_status(e);
+}
+
+int soft_match(soft_match_t m, const void *a, const void *b, void *grid, long long *index, hipStream_t s) {
+    if (!m || !a || !b) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, grid, index);
+    if (rc != SOFT_OK) return rc;
+    hipError_t e;
+    switch (m->plan->precision) {
+        case SOFT_FP64: e = run_match<soft::P64>(m, a, b, grid, index, s); break;
+        case SOFT_FP32: e = run_match<soft::P32>(m, a, b, grid, index, s); break;
+        default: e = run_match<soft::P32S>(m, a, b, grid, index, s); break;
+    }
+    return hip_status(e);
+}
+
+int soft_match_destroy(soft_match_t m) {
+    if (!m) return SOFT_OK;
+    const hipError_t e = hipDeviceSynchronize();
+    free_match(m);
     return hip_status(e);
 }
 

@@ -193,4 +193,16 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
                           hipStream_t s);
 
+// Rotational-matching head (match.hip).  n pairs of functions on the sphere
+// (B^2 coefficients each): correlation coefficients a(l,M) conj(b(l,M')), the
+// vector-Jacobian product of that map, and the per-grid argmax of Re over n
+// grids of count elements (workspace of argmax_workspace_bytes(count, n)).
+template <typename C>
+hipError_t launch_corr_coeffs(int B, int n, const C *a, const C *b, C *coeffs, hipStream_t s);
+template <typename C>
+hipError_t launch_corr_vjp(int B, int n, const C *a, const C *b, const C *g, C *ga, C *gb, hipStream_t s);
+size_t argmax_workspace_bytes(long long count, int n);
+template <typename C>
+hipError_t launch_argmax_real(const C *x, long long count, int n, void *workspace, long long *index, hipStream_t s);
+
 }  // namespace soft

@@ -58,6 +58,17 @@ def lib():
         L.soft_plan_set_timing.argtypes = [vp, ctypes.c_int]
         L.soft_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
+        L.soft_match_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(vp)]
+        L.soft_match_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.soft_match_plan_soft.argtypes = [vp, ctypes.POINTER(vp)]
+        L.soft_match_coeffs.argtypes = [vp, vp, vp, vp, vp]
+        L.soft_match_coeffs_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.soft_match_argmax.argtypes = [vp, vp, vp, vp]
+        L.soft_match.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.soft_match_destroy.argtypes = [vp]
+        for name in ("soft_match_plan", "soft_match_sizes", "soft_match_plan_soft", "soft_match_coeffs",
+                     "soft_match_coeffs_vjp", "soft_match_argmax", "soft_match", "soft_match_destroy"):
+            getattr(L, name).restype = ctypes.c_int
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
         for name in ("soft_plan", "soft_plan_uneven", "soft_plan_sizes", "soft_plan_offsets", "soft_forward", "soft_inverse", "soft_adjoint",
@@ -140,7 +151,8 @@ def soft_adjoint_inverse(plan, grid, coeffs, stream=None):
            "soft_adjoint_inverse")
 
 
-STAGES = ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "dwt_inv", "fft_alpha_inv", "fft_gamma_inv")
+STAGES = ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "dwt_inv", "fft_alpha_inv", "fft_gamma_inv",
+          "match_coeffs", "argmax")
 
 
 def soft_plan_set_timing(plan, enable):
@@ -157,6 +169,50 @@ def soft_plan_stage_times(plan, reset=False):
 
 def soft_plan_destroy(plan):
     _check(lib().soft_plan_destroy(ctypes.c_void_p(plan)), "soft_plan_destroy")
+
+
+def soft_match_plan(B, n, precision=SOFT_FP64, flags=0):
+    h = ctypes.c_void_p()
+    _check(lib().soft_match_plan(int(B), int(n), int(precision), int(flags), ctypes.byref(h)), "soft_match_plan")
+    return h.value
+
+
+def soft_match_sizes(match):
+    """(sh_elems, coeff_elems, grid_elems) of one call."""
+    a, c, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().soft_match_sizes(ctypes.c_void_p(match), ctypes.byref(a), ctypes.byref(c), ctypes.byref(g)),
+           "soft_match_sizes")
+    return a.value, c.value, g.value
+
+
+def soft_match_plan_soft(match):
+    h = ctypes.c_void_p()
+    _check(lib().soft_match_plan_soft(ctypes.c_void_p(match), ctypes.byref(h)), "soft_match_plan_soft")
+    return h.value
+
+
+def soft_match_coeffs(match, a, b, coeffs, stream=None):
+    _check(lib().soft_match_coeffs(ctypes.c_void_p(match), _ptr(a), _ptr(b), _ptr(coeffs), _stream(stream)),
+           "soft_match_coeffs")
+
+
+def soft_match_coeffs_vjp(match, a, b, g, ga, gb, stream=None):
+    _check(lib().soft_match_coeffs_vjp(ctypes.c_void_p(match), _ptr(a), _ptr(b), _ptr(g), _ptr(ga), _ptr(gb),
+                                       _stream(stream)), "soft_match_coeffs_vjp")
+
+
+def soft_match_argmax(match, grid, index, stream=None):
+    _check(lib().soft_match_argmax(ctypes.c_void_p(match), _ptr(grid), _ptr(index), _stream(stream)),
+           "soft_match_argmax")
+
+
+def soft_match(match, a, b, grid, index, stream=None):
+    _check(lib().soft_match(ctypes.c_void_p(match), _ptr(a), _ptr(b), _ptr(grid), _ptr(index), _stream(stream)),
+           "soft_match")
+
+
+def soft_match_destroy(match):
+    _check(lib().soft_match_destroy(ctypes.c_void_p(match)), "soft_match_destroy")
 
 
 # ---------------------------------------------------------------------------
@@ -251,6 +307,23 @@ class _PlanBase:
 
 
 class Plan(_PlanBase):
+    @classmethod
+    def _borrow(cls, handle, B, batch, device, precision):
+        """A Plan over a handle owned elsewhere (closing it does nothing)."""
+        self = cls.__new__(cls)
+        self._init_device(device, precision)
+        self.handle = handle
+        self._owned = False
+        self.B, self.batch, self.N = B, batch, 2 * B
+        self.nc = num_coeffs(B)
+        return self
+
+    def close(self):
+        if getattr(self, "_owned", True):
+            super().close()
+        else:
+            self.handle = None
+
     """A plan for ``batch`` SO(3) transforms of bandwidth ``B`` on one device.
 
     Grids are tensors of shape [batch, 2B, 2B, 2B] (or [2B, 2B, 2B] when
@@ -303,3 +376,77 @@ class UnevenPlan(_PlanBase):
     def split_coeffs(self, flat):
         """Views of each function's coefficient vector in a flat buffer."""
         return [flat[self.coeff_offsets[f]:self.coeff_offsets[f + 1]] for f in range(len(self.Bs))]
+
+
+class MatchPlan:
+    """Rotational-matching head for ``n`` pairs of functions on the sphere at
+    bandwidth ``B``: a, b are [n, B^2] (or [B^2] when n == 1) complex
+    tensors, coefficient (l, m) at l^2 + m + l.  ``plan`` is the owned
+    soft.Plan of the n correlation functions (for backward passes)."""
+
+    def __init__(self, B, n=1, device=None, precision="fp64"):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.precision = _precision(precision)
+        self.dtype = torch.complex128 if self.precision == SOFT_FP64 else torch.complex64
+        with torch.cuda.device(self.device):
+            self.handle = soft_match_plan(B, n, self.precision, 0)
+        self.B, self.n = B, n
+        self.plan = Plan._borrow(soft_match_plan_soft(self.handle), B, n, self.device, self.precision)
+
+    def sh_shape(self):
+        return (self.B * self.B,) if self.n == 1 else (self.n, self.B * self.B)
+
+    def _chk(self, t, shape, what):
+        return self.plan._checked(t, shape, what)
+
+    def coeffs(self, a, b, out=None):
+        """f°(l, M, M') = a(l, M) conj(b(l, M')) for every pair."""
+        a = self._chk(a, self.sh_shape(), "a")
+        b = self._chk(b, self.sh_shape(), "b")
+        c = self.plan._out(out, self.plan.coeff_shape(), "out")
+        soft_match_coeffs(self.handle, a, b, c)
+        return c
+
+    def coeffs_vjp(self, a, b, g):
+        """(ga, gb): vector-Jacobian product of ``coeffs`` for g = dL/d conj(f°)."""
+        a = self._chk(a, self.sh_shape(), "a")
+        b = self._chk(b, self.sh_shape(), "b")
+        g = self._chk(g, self.plan.coeff_shape(), "g")
+        ga, gb = torch.empty_like(a), torch.empty_like(b)
+        soft_match_coeffs_vjp(self.handle, a, b, g, ga, gb)
+        return ga, gb
+
+    def argmax(self, grid, out=None):
+        """Flat index of the largest real part of each correlation grid (int64)."""
+        g = self._chk(grid, self.plan.grid_shape(), "grid")
+        idx = out if out is not None else torch.empty(self.n, dtype=torch.int64, device=self.device)
+        soft_match_argmax(self.handle, g, idx)
+        return idx
+
+    def match(self, a, b, grid=None, index=None):
+        """Correlation grids of every pair and the argmax of each: (grid, index)."""
+        a = self._chk(a, self.sh_shape(), "a")
+        b = self._chk(b, self.sh_shape(), "b")
+        g = self.plan._out(grid, self.plan.grid_shape(), "grid")
+        idx = index if index is not None else torch.empty(self.n, dtype=torch.int64, device=self.device)
+        soft_match(self.handle, a, b, g, idx)
+        return g, idx
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.plan.close()
+            soft_match_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

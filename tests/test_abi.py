@@ -79,3 +79,22 @@ def test_uneven_argument_errors_need_no_gpu(L):
     for prec in (soft.SOFT_FP32, soft.SOFT_FP32_SPLIT):
         assert L.soft_plan(8, 0, prec, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
         assert L.soft_plan(12, 1, prec, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+
+
+def test_match_argument_errors_need_no_gpu(L):
+    from paper_1808_00896_amd import soft
+    h = ctypes.c_void_p()
+    assert L.soft_match_plan(0, 4, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(8, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(8, 4, 5, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(8, 4, 0, 1, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(8, 4, 0, 0, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(24, 4, 2, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert h.value is None
+    assert L.soft_match(None, None, None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_coeffs(None, None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_coeffs_vjp(None, None, None, None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_argmax(None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_sizes(None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan_soft(None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_destroy(None) == soft.SOFT_OK
