@@ -81,7 +81,8 @@ typedef enum {
 typedef enum {
     SOFT_OK = 0,
     SOFT_ERR_INVALID = -1,     /* null pointer, B < 1, batch < 1, unknown precision or flag, wrong device */
-    SOFT_ERR_UNSUPPORTED = -2, /* valid for the paper but not built here: B not a power of two or B > 512 */
+    SOFT_ERR_UNSUPPORTED = -2, /* valid for the paper but not built here: B not a power of two or B > 512,
+                                  more than 65535 functions in one plan */
     SOFT_ERR_OOM = -3,         /* device or host allocation failed at plan time */
     SOFT_ERR_HIP = -4          /* a HIP runtime call or kernel launch failed */
 } soft_status;
@@ -90,7 +91,7 @@ typedef enum {
  * soft_plan -- plan `batch` transforms of bandwidth B (Sect. 2.3: a function
  * of bandwidth B lives in H_B, degrees l < B).
  *   B          bandwidth, a power of two with 1 <= B <= 512.
- *   batch      number of functions per call (>= 1).
+ *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
  *   flags      must be 0.
  *   out        receives the plan handle; unchanged on error.
@@ -111,7 +112,7 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
  * B, grid and coefficient count).
  *   B_list     host array of n bandwidths, each a power of two <= 512, in
  *              the order the functions are stored; read during the call only.
- *   n          number of functions (>= 1).
+ *   n          number of functions, 1 <= n <= 65535.
  *   precision, flags, out   as for soft_plan.
  * Functions of equal B share one set of tables.  The FFT passes run once
  * per distinct B; the DWT runs as one launch over all functions with

@@ -31,28 +31,26 @@ __device__ __forceinline__ int sh_degree(int q) {
     return l;
 }
 
-// Degree of SO(3) coefficient e: the l with deg_offset(l) <= e < deg_offset(l+1).
-__device__ __forceinline__ int degree_of(long long e) {
-    int l = (int)cbrt(0.75 * (double)e);
-    while (deg_offset(l + 1) <= e) ++l;
-    while (l > 0 && deg_offset(l) > e) --l;
-    return l;
-}
-
-// f°(l, M, M') = a(l, M) conj(b(l, M')) for n pairs; one thread per output.
+// f°(l, M, M') = a(l, M) conj(b(l, M')); block (l', f) writes the
+// (2l+1)^2 contiguous coefficients of degree l = B-1-l' of pair f (largest
+// degrees first), 256 at a time.  Row and column come from a float
+// reciprocal of 2l+1 with one exact integer correction.
 template <typename C>
-__global__ __launch_bounds__(256) void k_corr_coeffs(int B, int n, const C *__restrict__ a, const C *__restrict__ b,
+__global__ __launch_bounds__(256) void k_corr_coeffs(int B, const C *__restrict__ a, const C *__restrict__ b,
                                                      C *__restrict__ out) {
-    const long long Nc = deg_offset(B), total = Nc * n;
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= total) return;
-    const long long f = e / Nc, r = e - f * Nc;
-    const int l = degree_of(r);
-    const int w = 2 * l + 1;
-    const int q = (int)(r - deg_offset(l));
-    const int row = q / w, col = q - row * w;  // M + l, M' + l
-    const long long base = f * (long long)B * B + (long long)l * l;
-    out[e] = cmul_conj(a[base + row], b[base + col]);
+    const int l = B - 1 - (int)blockIdx.x, f = blockIdx.y;
+    const int w = 2 * l + 1, cnt = w * w;
+    const float rw = 1.0f / (float)w;
+    const C *al = a + (long long)f * B * B + (long long)l * l;
+    const C *bl = b + (long long)f * B * B + (long long)l * l;
+    C *o = out + (long long)f * deg_offset(B) + deg_offset(l);
+    for (int q = threadIdx.x; q < cnt; q += 256) {
+        int row = (int)((float)q * rw);
+        int col = q - row * w;
+        if (col < 0) { --row; col += w; }
+        if (col >= w) { ++row; col -= w; }
+        o[q] = cmul_conj(al[row], bl[col]);
+    }
 }
 
 // Vector-Jacobian product, gradient of a: ga(l, M) = sum_M' g(l, M, M') b(l, M').
@@ -186,9 +184,8 @@ __global__ __launch_bounds__(256) void k_argmax_final(const ArgBest *__restrict_
 
 template <typename C>
 hipError_t launch_corr_coeffs(int B, int n, const C *a, const C *b, C *coeffs, hipStream_t s) {
-    const long long total = (long long)B * (4LL * B * B - 1) / 3 * n;
-    hipLaunchKernelGGL(k_corr_coeffs<C>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, B, n, a, b,
-                       coeffs);
+    if (n > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_corr_coeffs<C>, dim3(B, n), dim3(256), 0, s, B, a, b, coeffs);
     return hipGetLastError();
 }
 

@@ -87,6 +87,10 @@ namespace {
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Functions per plan: launch grids index the functions of a band (FFT) or
+// the pairs (matching head) in a 16-bit grid dimension.
+constexpr int kMaxFunctions = 65535;
+
 void free_plan(soft_plan_s *p) {
     if (!p) return;
     for (hipEvent_t e : p->free_events) (void)hipEventDestroy(e);
@@ -484,6 +488,10 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
                     lists[gi].push_back(w);
                 }
             }
+            if (lists[gi].size() > (size_t)0x7fffffff) {
+                delete p;
+                return SOFT_ERR_UNSUPPORTED;
+            }
             LaunchGroup lg;
             lg.nw = shapes[gi].first;
             lg.nsub = shapes[gi].second;
@@ -597,7 +605,7 @@ extern "C" {
 
 int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out) {
     if (!out || B < 1 || batch < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
-    if (!is_pow2(B) || B > 512) return SOFT_ERR_UNSUPPORTED;
+    if (!is_pow2(B) || B > 512 || batch > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     std::vector<int> Bs;
     try {
         Bs.assign(batch, B);
@@ -611,6 +619,7 @@ int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, so
     if (!out || !B_list || n < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
     for (int i = 0; i < n; ++i)
         if (B_list[i] < 1) return SOFT_ERR_INVALID;
+    if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     for (int i = 0; i < n; ++i)
         if (!is_pow2(B_list[i]) || B_list[i] > 512) return SOFT_ERR_UNSUPPORTED;
     return make_plan(B_list, n, precision, out);
@@ -694,7 +703,7 @@ int soft_plan_destroy(soft_plan_t p) {
 
 int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out) {
     if (!out || B < 1 || n < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
-    if (!is_pow2(B) || B > 512) return SOFT_ERR_UNSUPPORTED;
+    if (!is_pow2(B) || B > 512 || n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     soft_match_s *m = new (std::nothrow) soft_match_s;
     if (!m) return SOFT_ERR_OOM;
     m->B = B;

@@ -52,6 +52,8 @@ def test_argument_errors_need_no_gpu(L):
     assert L.soft_plan(8, 1, 0, 0, None) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(6, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert L.soft_plan(1024, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert L.soft_plan(8, 65536, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert L.soft_match_plan(8, 65536, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert h.value is None
     for name in ("soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse"):
         assert getattr(L, name)(None, None, None, None) == soft.SOFT_ERR_INVALID
