@@ -37,7 +37,6 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxB = 512;
 
 struct DD {
     double hi, lo;
@@ -110,11 +109,23 @@ __global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__
 // ---------------------------------------------------------------------------
 // Shared pieces
 // ---------------------------------------------------------------------------
-// The swizzle f(jl) = (jl + jl/16) mod 16 keeps the per-lane row writes
-// (jl = lane), the forward A reads (jl = 4s + k, r = lane%16) and the inverse A
-// reads (jl = 16t + lane%16, r = 4s + k) free of bank conflicts whether the LDS
-// serves 16 or 32 lanes of 8 bytes per clock.
-__device__ __forceinline__ int panel_idx(int jl, int r) { return jl * 16 + (r ^ ((jl + (jl >> 4)) & 15)); }
+// Wave panels hold row r (degree l0 + lp + r) of 64 beta samples at
+// pan[r * RS + jl].  The LDS has 64 four-byte banks and serves 8-byte reads 32
+// lanes at a time, so the row stride is padded per access pattern:
+//   writes (jl = lane, fixed r): contiguous, any stride;
+//   forward A reads (r = lane%16, jl = 4s + lane/16): RS = 66 puts the 32
+//     lanes of a pass on banks 4(lane%16) + 2(lane/16) + {0,1}, all distinct;
+//   inverse A reads (jl = 16t + lane%16, r = s + 4(lane/16), the k slot's
+//     degrees taken four apart): RS = 68 puts them on 32(lane/16) + 2(lane%16)
+//     + {0,1}.
+// Every address is then one per-lane base register plus an immediate offset.
+constexpr int kRowFwd = 66;
+constexpr int kRowInv = 68;
+
+// 32-bit flat index of f°(l, m, m') (fits for l < 512: l(4l^2-1)/3 < 2^31).
+__device__ __forceinline__ int coeff_index32(int l, int m, int mp) {
+    return l * (4 * l * l - 1) / 3 + (m + l) * (2 * l + 1) + (mp + l);
+}
 
 // s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), fenced so the
 // scheduler keeps later loads behind it.
@@ -176,9 +187,10 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
                                                     typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
-    __shared__ double panel[NW][64 * 16];
+    // s_l of the group's degrees: at most B = NW*NSUB*32 for this shape.
+    __shared__ double panel[NW][16 * kRowFwd];
     __shared__ double red[2][NW][256];
-    __shared__ double srow[kMaxB];
+    __shared__ double srow[NW * NSUB * 32];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
     const int B = it.B, N = 2 * B;
     const int m = it.m, mp = it.mp, mask = it.mask;
@@ -224,6 +236,20 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     double *pan = panel[wave];
     R *out = reinterpret_cast<R *>(coeffs + it.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
+    // Epilogue constants: thread slot q writes column t = threadIdx.x + q*NT of
+    // every panel; its member, sign and part never change, because the
+    // degrees of a panel row advance by 16 (the parity-dependent signs stay).
+    constexpr int NT = NW * 64, EPI = (256 + NT - 1) / NT;
+    int e_mm[EPI], e_mmp[EPI];
+    double e_sign[EPI];
+    bool e_on[EPI];
+#pragma unroll
+    for (int q = 0; q < EPI; ++q) {
+        const int t = threadIdx.x + q * NT;
+        const int slot = (t & 15) >> 1;
+        e_on[q] = t < 256 && ((mask >> slot) & 1);
+        group_member(slot, m, mp, m + (t >> 4), e_mm[q], e_mmp[q], e_sign[q]);
+    }
     int buf = 0;
     for (int lp = 0; lp < L; lp += 16, buf ^= 1) {
         double tot[4];
@@ -235,7 +261,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
             for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    panel_put<PR>(&pan[panel_idx(lane, r)], ecur[h]);
+                    panel_put<PR>(&pan[r * kRowFwd + lane], ecur[h]);
                     const double u = fma(c[r].x, x[h], -c[r].y);
                     const double en = fma(u, ecur[h], -eprev[h]);
                     eprev[h] = ecur[h];
@@ -243,7 +269,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
                 }
                 double a[16];
 #pragma unroll
-                for (int s = 0; s < 16; ++s) a[s] = pan[panel_idx(4 * s + krow, col)];
+                for (int s = 0; s < 16; ++s) a[s] = pan[col * kRowFwd + 4 * s + krow];
                 if (h == NSUB - 1) {
                     lds_wait_all();
 #pragma unroll
@@ -264,7 +290,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
             for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    panel_put<PR>(&pan[panel_idx(lane, r)], ecur[h]);
+                    panel_put<PR>(&pan[r * kRowFwd + lane], ecur[h]);
                     const double u = fma(c[r].x, x[h], -c[r].y);
                     const double en = fma(u, ecur[h], -eprev[h]);
                     eprev[h] = ecur[h];
@@ -273,7 +299,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
                 float2 a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s)
-                    a[s] = *reinterpret_cast<const float2 *>(&pan[panel_idx(4 * s + krow, col)]);
+                    a[s] = *reinterpret_cast<const float2 *>(&pan[col * kRowFwd + 4 * s + krow]);
                 if (h == NSUB - 1) {
                     lds_wait_all();
 #pragma unroll
@@ -300,18 +326,17 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         __syncthreads();
         // Epilogue (the reorder): column c = 2 slot + part of row lp + r is
         // f°(l, member of slot) up to the slot's symmetry sign, s_l and V_B.
-        for (int t = threadIdx.x; t < 256; t += NW * 64) {
-            double sum = 0.0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) sum += red[buf][w][t];
-            const int li = lp + (t >> 4), slot = (t & 15) >> 1;
-            if (li < L && ((mask >> slot) & 1)) {
+        for (int q = 0; q < EPI; ++q) {
+            const int t = threadIdx.x + q * NT;
+            const int li = lp + (t >> 4);
+            if (e_on[q] && li < L) {
+                double sum = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) sum += red[buf][w][t];
                 const int l = m + li;
-                int mm, mmp;
-                double sign;
-                group_member(slot, m, mp, l, mm, mmp, sign);
-                const double f = sign * srow[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
-                out[2 * coeff_index(l, mm, mmp) + (t & 1)] = (R)(sum * f);
+                const double f = e_sign[q] * srow[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
+                out[2 * coeff_index32(l, e_mm[q], e_mmp[q]) + (t & 1)] = (R)(sum * f);
             }
         }
     }
@@ -333,41 +358,61 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 // panel's LDS reads.  FP32 modes sum each panel in FP32 and the panels in FP64.
 constexpr int kChunk = 32;
 
+// Thread k-slot q of a block gathers element e = threadIdx.x + q*NT = row*16
+// + col of every chunk (degree c*32 + row, column col = 2 slot + part).  Its
+// member, sign and part are the same in every chunk (chunks advance the
+// degree by 32, so parity-dependent signs stay), so they are set once.
 template <int NT, typename R>
 struct InvGather {
     static constexpr int PER = (kChunk * 16 + NT - 1) / NT;  // values per thread
     R v[PER];
+    int mm[PER], mmp[PER];
+    double sign[PER];
+    bool on[PER];
 };
 
-// Gather chunk c (degrees c*32 .. c*32+31) of group g: element e = row*16 + col.
-template <int NT, typename R, typename C>
+template <int NT, typename R>
+__device__ __forceinline__ void inv_gather_init(InvGather<NT, R> &st, const WorkItem &it) {
+#pragma unroll
+    for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int slot = (e & 15) >> 1;
+        st.on[k] = e < kChunk * 16 && ((it.mask >> slot) & 1);
+        group_member(slot, it.m, it.mp, it.m + (e >> 4), st.mm[k], st.mmp[k], st.sign[k]);
+    }
+}
+
+// Gather chunk c (degrees c*32 .. c*32+31): the inverse reorder, with the
+// member's sign, s_l and optionally V_B applied; rows past L are zero.
+template <int NT, typename R>
 __device__ __forceinline__ void inv_gather(InvGather<NT, R> &st, const double *__restrict__ rscale,
                                            const R *__restrict__ cin, const WorkItem &it, int L, int c,
                                            double v0) {
 #pragma unroll
     for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
-        const int row = e >> 4, col = e & 15, slot = col >> 1;
-        const int li = c * kChunk + row;
+        const int li = c * kChunk + (e >> 4);
         double val = 0.0;
-        if (e < kChunk * 16 && li < L && ((it.mask >> slot) & 1)) {
+        if (st.on[k] && li < L) {
             const int l = it.m + li;
-            int mm, mmp;
-            double sign;
-            group_member(slot, it.m, it.mp, l, mm, mmp, sign);
-            const double f = sign * rscale[it.goff + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
-            val = (double)cin[2 * coeff_index(l, mm, mmp) + (col & 1)] * f;
+            const double f = st.sign[k] * rscale[it.goff + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
+            val = (double)cin[2 * coeff_index32(l, st.mm[k], st.mmp[k]) + (e & 1)] * f;
         }
         st.v[k] = (R)val;
     }
 }
 
+// Stage a gathered chunk.  Within each 16-degree block, degree d goes to row
+// 4(d%4) + d/4, so the MFMA k slot (s, lane/16) that takes degree s + 4(lane/16)
+// reads the contiguous rows 4s + lane/16.
 template <int NT, typename R>
 __device__ __forceinline__ void inv_put(const InvGather<NT, R> &st, R *buf) {
 #pragma unroll
     for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
-        if (e < kChunk * 16) buf[e] = st.v[k];
+        const int row = e >> 4;
+        const int prow = (row & ~15) | ((row & 3) << 2) | ((row >> 2) & 3);
+        if (e < kChunk * 16) buf[prow * 16 + (e & 15)] = st.v[k];
     }
 }
 
@@ -379,7 +424,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
     constexpr int NT = NW * 64;
-    __shared__ double panel[NW][64 * 16];
+    __shared__ double panel[NW][16 * kRowInv];
     __shared__ R stage[2][kChunk * 16];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
     const int B = it.B, N = 2 * B;
@@ -393,7 +438,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
 
     InvGather<NT, R> st;
-    inv_gather<NT, R, C>(st, tab.rscale, cin, it, L, 0, v0);
+    inv_gather_init<NT, R>(st, it);
+    inv_gather<NT, R>(st, tab.rscale, cin, it, L, 0, v0);
 
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
@@ -414,7 +460,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
 
     inv_put<NT, R>(st, stage[0]);
-    if (nchunk > 1) inv_gather<NT, R, C>(st, tab.rscale, cin, it, L, 1, v0);
+    if (nchunk > 1) inv_gather<NT, R>(st, tab.rscale, cin, it, L, 1, v0);
     __syncthreads();
 
     double *pan = panel[wave];
@@ -428,7 +474,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                panel_put<PR>(&pan[panel_idx(lane, r)], ecur[h]);
+                panel_put<PR>(&pan[r * kRowInv + lane], ecur[h]);
                 const double u = fma(c[r].x, x[h], -c[r].y);
                 const double en = fma(u, ecur[h], -eprev[h]);
                 eprev[h] = ecur[h];
@@ -439,7 +485,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) a[t][s] = pan[panel_idx(16 * t + col, 4 * s + krow)];
+                    for (int s = 0; s < 4; ++s) a[t][s] = pan[(s + 4 * krow) * kRowInv + 16 * t + col];
                 if (h == NSUB - 1) {
                     lds_wait_all();
 #pragma unroll
@@ -457,7 +503,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
                     for (int s = 0; s < 4; ++s)
-                        a[t][s] = *reinterpret_cast<const float2 *>(&pan[panel_idx(16 * t + col, 4 * s + krow)]);
+                        a[t][s] = *reinterpret_cast<const float2 *>(&pan[(s + 4 * krow) * kRowInv + 16 * t + col]);
                 if (h == NSUB - 1) {
                     lds_wait_all();
 #pragma unroll
@@ -482,7 +528,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         if (lp + 16 - ch * kChunk == kChunk || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
                 inv_put<NT, R>(st, stage[(ch + 1) & 1]);
-                if (ch + 2 < nchunk) inv_gather<NT, R, C>(st, tab.rscale, cin, it, L, ch + 2, v0);
+                if (ch + 2 < nchunk) inv_gather<NT, R>(st, tab.rscale, cin, it, L, ch + 2, v0);
             }
             __syncthreads();
         }
