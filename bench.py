@@ -134,11 +134,19 @@ def per_stage(stage_ms, Bs, steps, prec="fp64"):
     return out
 
 
+TUNE = True  # plans time their DWT launch shapes at creation (outside the timed region)
+
+
 def make_plan(Bs, prec, uniform):
     from paper_1808_00896_amd import soft
     if uniform:
-        return soft.Plan(Bs[0], batch=len(Bs), precision=prec)
-    return soft.UnevenPlan(Bs, precision=prec)
+        return soft.Plan(Bs[0], batch=len(Bs), precision=prec, tune=TUNE)
+    return soft.UnevenPlan(Bs, precision=prec, tune=TUNE)
+
+
+def shapes_of(plan):
+    return [{"max_2B": l["max_2B"], "forward": l["forward"], "inverse": l["inverse"], "tuned": l["tuned"]}
+            for l in plan.describe()["dwt_launches"]]
 
 
 def timed_steps(plan, c, steps, warmup):
@@ -200,7 +208,8 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=Fa
            "value": round(steps * n / el, 3), "unit": "function fwd+inv/s",
            "ms_per_step": round(el / steps * 1e3, 4),
            "round_trip_err": relerr_dev(c2, c),
-           "stages": per_stage(st, Bs, steps, prec)}
+           "stages": per_stage(st, Bs, steps, prec),
+           "dwt_shapes": shapes_of(plan)}
     out = None
     if ref is not None:
         res["inverse_err_vs_fp64"] = relerr_dev(grid, ref["grid"])
@@ -230,7 +239,7 @@ def match_leg(steps, B=128, n=64):
     ref = None
     for prec in ("fp64", "fp32_split"):
         log(f"match {n} pairs B={B} {prec}")
-        m = soft.MatchPlan(B, n, precision=prec)
+        m = soft.MatchPlan(B, n, precision=prec, tune=TUNE)
         a = torch.from_numpy(a_h).cuda().to(m.dtype)
         b = torch.from_numpy(b_h).cuda().to(m.dtype)
         grid = torch.empty(m.plan.grid_shape(), dtype=m.dtype, device="cuda")
@@ -251,7 +260,7 @@ def match_leg(steps, B=128, n=64):
         st = soft.soft_plan_stage_times(h, reset=True)
         r = {"pairs": n, "B": B, "precision": prec, "steps": k, "value": round(n * k / el, 2),
              "unit": "pairs/s (coefficients + inverse + argmax)", "ms_per_step": round(el / k * 1e3, 3),
-             "stages": per_stage(st, [B] * n, k, prec)}
+             "stages": per_stage(st, [B] * n, k, prec), "dwt_shapes": shapes_of(m.plan)}
         if ref is None:
             ref = {"grid": grid, "idx": idx.cpu().numpy()}
         else:
@@ -320,9 +329,12 @@ def main():
     ap.add_argument("--uneven-steps", type=int, default=5)
     ap.add_argument("--no-match", action="store_true")
     ap.add_argument("--match-steps", type=int, default=10)
+    ap.add_argument("--no-tune", action="store_true", help="fixed DWT launch shapes instead of tuned ones")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
+    global TUNE
+    TUNE = not args.no_tune
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform is built and timed on a single MI355X; "
@@ -361,6 +373,7 @@ def main():
                    "B": B, "batch": 1, "precision": "fp64"},
         "roofline": roofline(st_ms, B),
         "stages": main_leg["stages"],
+        "dwt_shapes": main_leg["dwt_shapes"],
         "round_trip_err": main_leg["round_trip_err"],
     }
     log(f"B={B}: {value:.1f} fwd+inv/s, round trip {main_leg['round_trip_err']:.2e}")

@@ -78,6 +78,17 @@ typedef enum {
     SOFT_FP32_SPLIT = 2
 } soft_precision;
 
+/*
+ * Plan flags (bitwise or).
+ *   SOFT_PLAN_TUNE  at plan time, time every DWT launch shape (waves per
+ *                   block, beta samples per lane) that fits each DWT launch,
+ *                   forward and inverse separately, on the plan's own work
+ *                   list with zeroed data, and keep the fastest.  Costs a few
+ *                   DWT launches per candidate at plan creation; without it
+ *                   a fixed shape per 2B is used.
+ */
+enum { SOFT_PLAN_TUNE = 1u };
+
 typedef enum {
     SOFT_OK = 0,
     SOFT_ERR_INVALID = -1,     /* null pointer, B < 1, batch < 1, unknown precision or flag, wrong device */
@@ -93,7 +104,7 @@ typedef enum {
  *   B          bandwidth, a power of two with 1 <= B <= 512.
  *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
- *   flags      must be 0.
+ *   flags      0 or SOFT_PLAN_TUNE; other bits are SOFT_ERR_INVALID.
  *   out        receives the plan handle; unchanged on error.
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
@@ -130,6 +141,27 @@ int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, so
  */
 int soft_plan_sizes(soft_plan_t plan, size_t *grid_elems, size_t *coeff_elems,
                     size_t *workspace_bytes);
+
+/*
+ * soft_plan_describe -- a one-line JSON description of the plan (bands,
+ * functions, workspace bytes, and per DWT launch its largest 2B, work items,
+ * forward and inverse launch shapes and whether they were tuned), written to
+ * buf as a NUL-terminated string truncated to len - 1 characters.
+ * Returns SOFT_OK or SOFT_ERR_INVALID (NULL plan or buf, len == 0).
+ */
+int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
+
+/*
+ * soft_plan_set_dwt_shape -- pin the launch shape of one DWT launch of the
+ * plan (as listed by soft_plan_describe, in order).
+ *   launch     index of the DWT launch (0 <= launch < number of launches).
+ *   direction  0 = forward DWT, 1 = inverse DWT.
+ *   waves, subsets  one of the built shapes (waves x subsets of 64 beta
+ *              samples per wave): 1x1, 2x1, 4x1, 8x1, 1x2, 2x2, 4x2, 8x2,
+ *              covering the launch: waves * subsets * 64 >= its largest 2B.
+ * Takes effect for later calls.  Returns SOFT_OK or SOFT_ERR_INVALID.
+ */
+int soft_plan_set_dwt_shape(soft_plan_t plan, int launch, int direction, int waves, int subsets);
 
 /*
  * soft_plan_offsets -- start of each function's grid and coefficients.

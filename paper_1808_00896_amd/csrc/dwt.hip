@@ -567,8 +567,8 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
     return hipGetLastError();
 }
 
-// Launch shapes (waves x subsets of 64 beta samples): 1x1, 2x1, 4x1, 8x1, 8x2
-// for 2B <= 64, 128, 256, 512, 1024.
+// Launch shapes (waves x subsets of 64 beta samples per wave): 1x1, 2x1, 4x1,
+// 8x1, 1x2, 2x2, 4x2, 8x2; a shape covers items with 2B <= waves*subsets*64.
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
@@ -586,6 +586,9 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_FWD(2, 1)
     SOFT_DWT_FWD(4, 1)
     SOFT_DWT_FWD(8, 1)
+    SOFT_DWT_FWD(1, 2)
+    SOFT_DWT_FWD(2, 2)
+    SOFT_DWT_FWD(4, 2)
     SOFT_DWT_FWD(8, 2)
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
@@ -608,6 +611,9 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_INV(2, 1)
     SOFT_DWT_INV(4, 1)
     SOFT_DWT_INV(8, 1)
+    SOFT_DWT_INV(1, 2)
+    SOFT_DWT_INV(2, 2)
+    SOFT_DWT_INV(4, 2)
     SOFT_DWT_INV(8, 2)
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;

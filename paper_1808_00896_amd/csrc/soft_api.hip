@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -41,14 +42,20 @@ struct Band {
 };
 
 struct LaunchGroup {
-    int nw = 1, nsub = 1, nitems = 0;
+    int nw_f = 1, nsub_f = 1;  // forward DWT launch shape (waves, subsets of 64 beta samples)
+    int nw_i = 1, nsub_i = 1;  // inverse DWT launch shape
+    int nmax = 0;              // largest 2B among the group's items
+    int nitems = 0;
+    bool tuned = false;
     size_t items_off = 0;  // byte offset of the work items in the table block
+    std::vector<int> bands;
 };
 
 }  // namespace
 
 struct soft_plan_s {
     int precision = 0, n = 0, device = 0;
+    unsigned flags = 0;
     std::vector<Band> bands;
     std::vector<FuncInfo> funcs;
     std::vector<LaunchGroup> groups;
@@ -90,6 +97,8 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // Functions per plan: launch grids index the functions of a band (FFT) or
 // the pairs (matching head) in a 16-bit grid dimension.
 constexpr int kMaxFunctions = 65535;
+
+constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE;
 
 void free_plan(soft_plan_s *p) {
     if (!p) return;
@@ -298,7 +307,8 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     }
     for (const LaunchGroup &lg : p->groups) {
         if (e == hipSuccess)
-            e = soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, S, cout_, scaled, s);
+            e = soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S, cout_, scaled,
+                                         s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
     }
     return e;
@@ -318,7 +328,8 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     hipError_t e = clk.start();
     for (const LaunchGroup &lg : p->groups) {
         if (e == hipSuccess)
-            e = soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw, lg.nsub, cin, S, scaled, s);
+            e = soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i, cin, S, scaled,
+                                         s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
     }
     for (const Band &b : p->bands) {
@@ -368,18 +379,96 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
     return e;
 }
 
+// DWT launch shapes the library instantiates (waves, subsets of 64 beta
+// samples per wave).
+constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}};
+
+// Autotuner: for every DWT launch group and direction, time each shape that
+// covers the group's largest 2B (and is at most twice that) on the plan's own
+// work list and workspace, with zeroed data, and keep the fastest.  Each
+// candidate runs once untimed, then kTuneReps timed launches between two HIP
+// events on the null stream.
+constexpr int kTuneReps = 3;
+
+template <int PR>
+hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
+    using C = typename soft::PrecT<PR>::C;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    C *S = static_cast<C *>(p->S), *cf = static_cast<C *>(coeffs);
+    for (LaunchGroup &lg : p->groups) {
+        for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+            float best = 0.f;
+            int bw = 0, bs = 0;
+            for (const auto &sh : kDwtShapes) {
+                const int cover = sh[0] * sh[1] * 64;
+                if (cover < lg.nmax || cover > 2 * lg.nmax) continue;
+                auto launch = [&]() {
+                    return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, sh[0], sh[1], S, cf,
+                                                               true, 0)
+                                    : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, sh[0], sh[1], cf, S,
+                                                               false, 0);
+                };
+                e = launch();
+                if (e == hipSuccess) e = hipEventRecord(t0, 0);
+                for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = launch();
+                if (e == hipSuccess) e = hipEventRecord(t1, 0);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) break;
+                if (bw == 0 || ms < best) {
+                    best = ms;
+                    bw = sh[0];
+                    bs = sh[1];
+                }
+            }
+            if (e == hipSuccess && bw) {
+                (dir == 0 ? lg.nw_f : lg.nw_i) = bw;
+                (dir == 0 ? lg.nsub_f : lg.nsub_i) = bs;
+            }
+        }
+        lg.tuned = e == hipSuccess;
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    return e;
+}
+
+int tune_dwt(soft_plan_s *p) {
+    void *coeffs = nullptr;
+    if (hipMalloc(&coeffs, p->coeff_total * p->csize) != hipSuccess) {
+        (void)hipGetLastError();
+        return SOFT_ERR_OOM;
+    }
+    hipError_t e = hipMemset(coeffs, 0, p->coeff_total * p->csize);
+    if (e == hipSuccess) e = hipMemset(p->S, 0, p->s_total * p->csize);
+    if (e == hipSuccess) {
+        switch (p->precision) {
+            case SOFT_FP64: e = tune_dwt_prec<soft::P64>(p, coeffs); break;
+            case SOFT_FP32: e = tune_dwt_prec<soft::P32>(p, coeffs); break;
+            default: e = tune_dwt_prec<soft::P32S>(p, coeffs); break;
+        }
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(coeffs);
+    return hip_status(e);
+}
+
 bool valid_precision(int precision) {
     return precision == SOFT_FP64 || precision == SOFT_FP32 || precision == SOFT_FP32_SPLIT;
 }
 
 // Builds bands, the function table and the DWT work lists of a plan for the
 // bandwidths Bs[0..n) (validated by the caller).
-int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
+int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *out) {
     soft_plan_s *p = new (std::nothrow) soft_plan_s;
     if (!p) return SOFT_ERR_OOM;
     try {
         p->precision = precision;
         p->n = n;
+        p->flags = flags;
         p->csize = precision == SOFT_FP64 ? sizeof(double2) : sizeof(float2);
         if (hipGetDevice(&p->device) != hipSuccess) {
             delete p;
@@ -493,8 +582,10 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
                 return SOFT_ERR_UNSUPPORTED;
             }
             LaunchGroup lg;
-            lg.nw = shapes[gi].first;
-            lg.nsub = shapes[gi].second;
+            lg.nw_f = lg.nw_i = shapes[gi].first;
+            lg.nsub_f = lg.nsub_i = shapes[gi].second;
+            lg.bands = group_bands[gi];
+            for (int bi : group_bands[gi]) lg.nmax = std::max(lg.nmax, p->bands[bi].N);
             lg.nitems = (int)lists[gi].size();
             p->groups.push_back(lg);
         }
@@ -587,6 +678,13 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
         for (const Band &b : p->bands)
             if (e == hipSuccess) e = soft::launch_fill_recurrence(b.view, p->rec, p->rscale, 0);
         if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess && (flags & SOFT_PLAN_TUNE)) {
+            const int rc = tune_dwt(p);
+            if (rc != SOFT_OK) {
+                free_plan(p);
+                return rc;
+            }
+        }
         if (e != hipSuccess) {
             free_plan(p);
             return SOFT_ERR_HIP;
@@ -604,7 +702,7 @@ int make_plan(const int *Bs, int n, int precision, soft_plan_t *out) {
 extern "C" {
 
 int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out) {
-    if (!out || B < 1 || batch < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!out || B < 1 || batch < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
     if (!is_pow2(B) || B > 512 || batch > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     std::vector<int> Bs;
     try {
@@ -612,17 +710,17 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
     } catch (const std::bad_alloc &) {
         return SOFT_ERR_OOM;
     }
-    return make_plan(Bs.data(), batch, precision, out);
+    return make_plan(Bs.data(), batch, precision, flags, out);
 }
 
 int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, soft_plan_t *out) {
-    if (!out || !B_list || n < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!out || !B_list || n < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
     for (int i = 0; i < n; ++i)
         if (B_list[i] < 1) return SOFT_ERR_INVALID;
     if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     for (int i = 0; i < n; ++i)
         if (!is_pow2(B_list[i]) || B_list[i] > 512) return SOFT_ERR_UNSUPPORTED;
-    return make_plan(B_list, n, precision, out);
+    return make_plan(B_list, n, precision, flags, out);
 }
 
 int soft_plan_sizes(soft_plan_t p, size_t *grid_elems, size_t *coeff_elems, size_t *workspace_bytes) {
@@ -630,6 +728,40 @@ int soft_plan_sizes(soft_plan_t p, size_t *grid_elems, size_t *coeff_elems, size
     if (grid_elems) *grid_elems = p->grid_total;
     if (coeff_elems) *coeff_elems = p->coeff_total;
     if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+    return SOFT_OK;
+}
+
+int soft_plan_describe(soft_plan_t p, char *buf, size_t len) {
+    if (!p || !buf || len == 0) return SOFT_ERR_INVALID;
+    std::string d = "{\"precision\": " + std::to_string(p->precision) + ", \"functions\": " + std::to_string(p->n) +
+                    ", \"workspace_bytes\": " + std::to_string(p->ws_bytes) + ", \"bands\": [";
+    for (size_t bi = 0; bi < p->bands.size(); ++bi)
+        d += std::string(bi ? ", " : "") + "{\"B\": " + std::to_string(p->bands[bi].B) +
+             ", \"functions\": " + std::to_string(p->bands[bi].funcs.size()) + "}";
+    d += "], \"dwt_launches\": [";
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const LaunchGroup &lg = p->groups[gi];
+        d += std::string(gi ? ", " : "") + "{\"max_2B\": " + std::to_string(lg.nmax) +
+             ", \"items\": " + std::to_string(lg.nitems) + ", \"forward\": [" + std::to_string(lg.nw_f) + ", " +
+             std::to_string(lg.nsub_f) + "], \"inverse\": [" + std::to_string(lg.nw_i) + ", " +
+             std::to_string(lg.nsub_i) + "], \"tuned\": " + (lg.tuned ? "true" : "false") + "}";
+    }
+    d += "]}";
+    const size_t k = std::min(len - 1, d.size());
+    std::memcpy(buf, d.data(), k);
+    buf[k] = '\0';
+    return SOFT_OK;
+}
+
+int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves, int subsets) {
+    if (!p || launch < 0 || launch >= (int)p->groups.size() || (direction != 0 && direction != 1))
+        return SOFT_ERR_INVALID;
+    LaunchGroup &lg = p->groups[launch];
+    bool known = false;
+    for (const auto &sh : kDwtShapes) known = known || (sh[0] == waves && sh[1] == subsets);
+    if (!known || waves * subsets * 64 < lg.nmax) return SOFT_ERR_INVALID;
+    (direction == 0 ? lg.nw_f : lg.nw_i) = waves;
+    (direction == 0 ? lg.nsub_f : lg.nsub_i) = subsets;
     return SOFT_OK;
 }
 
@@ -702,13 +834,13 @@ int soft_plan_destroy(soft_plan_t p) {
 }
 
 int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out) {
-    if (!out || B < 1 || n < 1 || flags != 0 || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!out || B < 1 || n < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
     if (!is_pow2(B) || B > 512 || n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     soft_match_s *m = new (std::nothrow) soft_match_s;
     if (!m) return SOFT_ERR_OOM;
     m->B = B;
     m->n = n;
-    int rc = soft_plan(B, n, precision, 0, &m->plan);
+    int rc = soft_plan(B, n, precision, flags, &m->plan);
     if (rc != SOFT_OK) {
         delete m;
         return rc;

@@ -24,6 +24,7 @@ SOFT_FP64 = 0
 SOFT_FP32 = 1
 SOFT_FP32_SPLIT = 2
 PRECISIONS = {"fp64": SOFT_FP64, "fp32": SOFT_FP32, "fp32_split": SOFT_FP32_SPLIT}
+SOFT_PLAN_TUNE = 1
 SOFT_OK = 0
 SOFT_ERR_INVALID = -1
 SOFT_ERR_UNSUPPORTED = -2
@@ -52,6 +53,8 @@ def lib():
                                        ctypes.POINTER(vp)]
         L.soft_plan_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.soft_plan_offsets.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.soft_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+        L.soft_plan_set_dwt_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         for name in ("soft_forward", "soft_inverse", "soft_adjoint", "soft_adjoint_inverse"):
             getattr(L, name).argtypes = [vp, vp, vp, vp]
         L.soft_plan_destroy.argtypes = [vp]
@@ -71,7 +74,7 @@ def lib():
             getattr(L, name).restype = ctypes.c_int
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
-        for name in ("soft_plan", "soft_plan_uneven", "soft_plan_sizes", "soft_plan_offsets", "soft_forward", "soft_inverse", "soft_adjoint",
+        for name in ("soft_plan", "soft_plan_uneven", "soft_plan_sizes", "soft_plan_offsets", "soft_plan_describe", "soft_plan_set_dwt_shape", "soft_forward", "soft_inverse", "soft_adjoint",
                      "soft_adjoint_inverse", "soft_plan_destroy", "soft_plan_set_timing",
                      "soft_plan_stage_times"):
             getattr(L, name).restype = ctypes.c_int
@@ -120,6 +123,22 @@ def soft_plan_offsets(plan, n):
     c = (ctypes.c_size_t * (n + 1))()
     _check(lib().soft_plan_offsets(ctypes.c_void_p(plan), g, c), "soft_plan_offsets")
     return list(g), list(c)
+
+
+def soft_plan_describe(plan):
+    """The plan's JSON self-description, parsed."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().soft_plan_describe(ctypes.c_void_p(plan), buf, len(buf)), "soft_plan_describe")
+    return json.loads(buf.value.decode())
+
+
+DWT_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (8, 2))
+
+
+def soft_plan_set_dwt_shape(plan, launch, direction, waves, subsets):
+    _check(lib().soft_plan_set_dwt_shape(ctypes.c_void_p(plan), int(launch), int(direction), int(waves),
+                                         int(subsets)), "soft_plan_set_dwt_shape")
 
 
 def soft_plan_sizes(plan):
@@ -288,6 +307,15 @@ class _PlanBase:
     def workspace_bytes(self):
         return soft_plan_sizes(self.handle)[2]
 
+    def describe(self):
+        """Bands, DWT launch shapes (tuned or fixed) and workspace of the plan."""
+        return soft_plan_describe(self.handle)
+
+    def set_dwt_shape(self, launch, direction, waves, subsets):
+        """Pin the (waves, subsets) shape of DWT launch ``launch``; direction
+        0 = forward, 1 = inverse."""
+        soft_plan_set_dwt_shape(self.handle, launch, direction, waves, subsets)
+
     def close(self):
         if getattr(self, "handle", None):
             soft_plan_destroy(self.handle)
@@ -332,10 +360,10 @@ class Plan(_PlanBase):
     Calls are asynchronous on the current torch stream.
     """
 
-    def __init__(self, B, batch=1, device=None, precision="fp64"):
+    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False):
         self._init_device(device, precision)
         with torch.cuda.device(self.device):
-            self.handle = soft_plan(B, batch, self.precision, 0)
+            self.handle = soft_plan(B, batch, self.precision, SOFT_PLAN_TUNE if tune else 0)
         self.B, self.batch, self.N = B, batch, 2 * B
         self.nc = num_coeffs(B)
 
@@ -355,11 +383,11 @@ class UnevenPlan(_PlanBase):
     where each starts, and ``split_grids`` / ``split_coeffs`` return views.
     """
 
-    def __init__(self, Bs, device=None, precision="fp64"):
+    def __init__(self, Bs, device=None, precision="fp64", tune=False):
         self._init_device(device, precision)
         self.Bs = [int(b) for b in Bs]
         with torch.cuda.device(self.device):
-            self.handle = soft_plan_uneven(self.Bs, self.precision, 0)
+            self.handle = soft_plan_uneven(self.Bs, self.precision, SOFT_PLAN_TUNE if tune else 0)
         self.grid_offsets, self.coeff_offsets = soft_plan_offsets(self.handle, len(self.Bs))
 
     def grid_shape(self):
@@ -384,13 +412,13 @@ class MatchPlan:
     tensors, coefficient (l, m) at l^2 + m + l.  ``plan`` is the owned
     soft.Plan of the n correlation functions (for backward passes)."""
 
-    def __init__(self, B, n=1, device=None, precision="fp64"):
+    def __init__(self, B, n=1, device=None, precision="fp64", tune=False):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.precision = _precision(precision)
         self.dtype = torch.complex128 if self.precision == SOFT_FP64 else torch.complex64
         with torch.cuda.device(self.device):
-            self.handle = soft_match_plan(B, n, self.precision, 0)
+            self.handle = soft_match_plan(B, n, self.precision, SOFT_PLAN_TUNE if tune else 0)
         self.B, self.n = B, n
         self.plan = Plan._borrow(soft_match_plan_soft(self.handle), B, n, self.device, self.precision)
 

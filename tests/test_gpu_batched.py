@@ -203,3 +203,83 @@ def test_precision_dtype_checks(dev):
         soft.Plan(4, precision="bf16")
     with pytest.raises(soft.SoftError):
         soft.UnevenPlan([4, 6])
+
+
+def _covering(nmax):
+    return [sh for sh in soft.DWT_SHAPES if sh[0] * sh[1] * 64 >= nmax]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_split"])
+@pytest.mark.parametrize("B", [16, 64])
+def test_every_dwt_shape_matches_oracle(oracle, dev, prec, B):
+    """Each built launch shape that covers 2B, pinned in turn for both
+    directions: inverse and forward against the oracle."""
+    c = rounded(inputs.coeffs_decay(B, 120 + B), prec)
+    g = rounded(inputs.grid_random(B, 130 + B), prec)
+    want_g, want_c = oracle.inverse(B, c), oracle.forward(B, g)
+    with soft.Plan(B, precision=prec) as p:
+        for sh in _covering(2 * B):
+            p.set_dwt_shape(0, 0, *sh)
+            p.set_dwt_shape(0, 1, *sh)
+            assert relerr(to_host(p.inverse(to_dev(c, dev, prec))), want_g) <= TOL[prec], sh
+            assert relerr(to_host(p.forward(to_dev(g, dev, prec))), want_c) <= TOL[prec], sh
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_split"])
+def test_every_dwt_shape_B256_agrees(dev, prec):
+    """At B = 256 every covering shape gives the default shape's result (the
+    default is pinned to the oracle by the parity tests) to the precision's
+    rounding: same sums, other order."""
+    B = 256
+    c = to_dev(inputs.coeffs_decay(B, 140), dev, prec)
+    with soft.Plan(B, precision=prec) as p:
+        ref_g = p.inverse(c).clone()
+        ref_c = p.forward(ref_g).clone()
+        tol = 1e-13 if prec == "fp64" else 1e-6
+        for sh in _covering(2 * B):
+            p.set_dwt_shape(0, 0, *sh)
+            p.set_dwt_shape(0, 1, *sh)
+            g = p.inverse(c)
+            assert float((g - ref_g).abs().max() / ref_g.abs().max()) <= tol, sh
+            cf = p.forward(ref_g)
+            assert float((cf - ref_c).abs().max() / ref_c.abs().max()) <= tol, sh
+            del g, cf
+    torch.cuda.empty_cache()
+
+
+def test_set_dwt_shape_rejects_bad_shapes(dev):
+    with soft.Plan(64) as p:
+        for args in ((1, 0, 2, 1), (0, 2, 2, 1), (0, 0, 1, 1), (0, 0, 3, 1), (0, 0, 16, 1)):
+            with pytest.raises(soft.SoftError):
+                p.set_dwt_shape(*args)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_split"])
+def test_tuned_plans_match_oracle(oracle, dev, prec):
+    """SOFT_PLAN_TUNE picks a covering shape per launch and direction; the
+    tuned one-bandwidth and uneven plans still meet the bar."""
+    B = 32
+    c = rounded(inputs.coeffs_decay(B, 150), prec)
+    with soft.Plan(B, precision=prec, tune=True) as p:
+        d = p.describe()
+        assert d["dwt_launches"][0]["tuned"]
+        for key in ("forward", "inverse"):
+            nw, ns = d["dwt_launches"][0][key]
+            assert (nw, ns) in soft.DWT_SHAPES and nw * ns * 64 >= 2 * B
+        g = to_host(p.inverse(to_dev(c, dev, prec)))
+        assert relerr(g, oracle.inverse(B, c)) <= TOL[prec]
+    Bs, cs = inputs.uneven_batch(10, [4, 16, 64, 256], seed=9)
+    cs = [rounded(x, prec) for x in cs]
+    with soft.UnevenPlan(Bs, precision=prec, tune=True) as p:
+        d = p.describe()
+        assert all(l["tuned"] for l in d["dwt_launches"])
+        assert sorted(b["B"] for b in d["bands"]) == sorted(set(Bs))
+        gflat = p.inverse(to_dev(np.concatenate(cs), dev, prec))
+        c2 = to_host(p.forward(gflat))
+        g = to_host(gflat)
+    for f, B in enumerate(Bs):
+        if B <= 64:
+            N = 2 * B
+            gf = g[p.grid_offsets[f]:p.grid_offsets[f + 1]].reshape(N, N, N)
+            assert relerr(gf, oracle.inverse(B, cs[f])) <= TOL[prec], (f, B)
+        assert relerr(c2[p.coeff_offsets[f]:p.coeff_offsets[f + 1]], cs[f]) <= TOL[prec], (f, B)
