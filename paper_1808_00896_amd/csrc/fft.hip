@@ -6,11 +6,12 @@
 // dropped on the way in and written as zero on the way out).
 //
 // Each direction is two HBM passes of batched 1-D FFTs over N points:
-//   gamma pass:  rows along k (contiguous) <-> t1[q][j][i]   (q = m' mod N)
+//   gamma pass:  rows along k (contiguous) <-> t1(j, q, i)   (q = m' mod N)
 //   alpha pass:  rows along i (contiguous in t1) <-> S[group slot][j]
 // A block transforms T independent length-N sequences that are neighbours
 // along the axis contiguous in the *other* layout, so every global access
-// moves runs of T * 16 bytes and the transposes cost no extra HBM pass.  The
+// moves runs of T elements (128 bytes or more from N = 512 up) and the
+// transposes cost no extra HBM pass.  The
 // forward alpha pass multiplies by the quadrature weight w_B(j) (the W_B
 // factor of the DWT) and writes members at pi - beta in reversed j order, so
 // the DWT sees every member of a symmetry group against the same d(l; b_j).
@@ -161,7 +162,7 @@ __device__ __forceinline__ void dft(C *v) {
 }
 
 // Shape of the transform of length N: E points per thread, P threads per
-// sequence, T sequences per block, radix R0 of the first stage, NSTAGE stages.
+// sequence, radix R0 of the first stage, NSTAGE stages.
 template <int N>
 struct Shape {
     static constexpr int E = N >= 16 ? 16 : N;
@@ -169,13 +170,20 @@ struct Shape {
     static constexpr int LOG = ilog2(N);
     static constexpr int R0 = N >= 16 ? (1 << (LOG % 4)) : N;  // 1, 2, 4, 8 (or N when N < 16)
     static constexpr int NSTAGE = N >= 16 ? LOG / 4 + (LOG % 4 ? 1 : 0) : 1;
-    // Neighbouring sequences per block: 32 for N <= 64, 16 up to 256, 8 at 512,
-    // 4 at 1024 (LDS ~ 70 KB, two blocks per CU); never more than N.
-    static constexpr int T0 = N <= 64 ? 32 : (N <= 256 ? 16 : (N == 512 ? 8 : 4));
-    static constexpr int T = T0 < N ? T0 : N;
-    static constexpr int NT = T * P;
     static constexpr int RS = N + N / 16 + 1;  // LDS row stride (complex), padded
-    static constexpr int LDS = P > 1 ? T * RS : 1;
+};
+
+// T neighbouring sequences per block: the transposed side of a pass moves
+// runs of T elements, so T is chosen for runs of at least 128 bytes (T = 8
+// complex128 or 16 complex64 from 2B = 512 up) within about 140 KB of LDS
+// (one block of 512-1024 threads per CU at 2B = 1024); 32 for N <= 64, 16 up
+// to 256; never more than N.
+template <int N, typename C>
+struct Tile {
+    static constexpr int T0 = N <= 64 ? 32 : (N <= 256 ? 16 : (sizeof(C) == 16 ? 8 : 16));
+    static constexpr int T = T0 < N ? T0 : N;
+    static constexpr int NT = T * Shape<N>::P;
+    static constexpr int LDS = Shape<N>::P > 1 ? T * Shape<N>::RS : 1;
 };
 
 // Radix of stage s: R0 first (when the decomposition needs it), then 16s.
@@ -244,6 +252,12 @@ __device__ __forceinline__ void get_stage(C (&v)[Shape<N>::E], const C *lds, int
     }
 }
 
+// Offset of t1(j, q, i) in the tile-blocked intermediate (see k_fft).
+template <int N, int T>
+__device__ __forceinline__ size_t t1_index(int j, int q, int i) {
+    return ((size_t)((j / T) * N + q) * T + (j % T)) * N + i;
+}
+
 // Pass kinds: where a block's T sequences come from and go to.
 enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
 
@@ -253,8 +267,8 @@ template <int KIND>
 constexpr bool transposed_out() { return KIND == GAMMA_FWD || KIND == ALPHA_FWD; }
 
 // Block -> (tile, line, batch).  Consecutive logical blocks are placed on the
-// same XCD (the hardware deals blocks round-robin over the 8 XCDs), so the two
-// halves of a 128-byte line touched by neighbouring tiles meet in one L2.
+// same XCD (the hardware deals blocks round-robin over the 8 XCDs), so the
+// neighbouring runs touched by neighbouring tiles meet in one L2.
 struct BlockPos {
     int tile, line, batch;
 };
@@ -279,19 +293,24 @@ __device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int
 
 // One pass over the functions of one band (blockIdx.z = index within the
 // band; t1 holds one N^3 intermediate per such index).  Element addresses:
-//   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out t1[(q*N + j)*N + i]
-//   ALPHA_FWD: block (j-tile, q): in t1[(q*N + j)*N + i],   out S[slot*N + j']
-//   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],         out t1[(q*N + j)*N + i]
-//   GAMMA_INV: block (i-tile, j): in t1[(q*N + j)*N + i],    out grid[(i*N + j)*N + k]
+//   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out t1(j, q, i)
+//   ALPHA_FWD: block (j-tile, q): in t1(j, q, i),             out S[slot*N + j']
+//   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],           out t1(j, q, i)
+//   GAMMA_INV: block (i-tile, j): in t1(j, q, i),              out grid[(i*N + j)*N + k]
+// with t1 blocked by the tile height T: t1(j, q, i) at
+// ((j/T * N + q) * T + j%T) * N + i.  An alpha block then reads or writes one
+// contiguous run of T*N elements, and a gamma block's runs of T elements for
+// the N values of q stay within one window of T*N^2 elements (instead of
+// striding over all N^3).
 template <int N, int KIND, int SIGN, typename C>
-__global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
+__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
                                                      int apply_w) {
     using Sh = Shape<N>;
-    constexpr int T = Sh::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
+    constexpr int T = Tile<N, C>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
     constexpr int B = N / 2;
     constexpr int LAST = NSTG - 1;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
-    __shared__ C lds[Sh::LDS];
+    __shared__ C lds[Tile<N, C>::LDS];
     const C *tw = twiddles<C>(p, SIGN);
 
     // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
@@ -334,7 +353,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__res
                 if constexpr (KIND == GAMMA_FWD) {
                     x = src[((size_t)row * N + line) * N + n];
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    x = src[((size_t)line * N + row) * N + n];
+                    x = src[t1_index<N, T>(row, line, n)];
                 } else if constexpr (KIND == ALPHA_INV) {
                     if (n == B) {
                         x = mk<C>(0.0, 0.0);
@@ -344,7 +363,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__res
                         x = src[(size_t)(sl >> 1) * N + jj];
                     }
                 } else {
-                    x = n == B ? mk<C>(0.0, 0.0) : src[((size_t)n * N + line) * N + row];
+                    x = n == B ? mk<C>(0.0, 0.0) : src[t1_index<N, T>(line, n, row)];
                 }
                 v[k * R + r] = x;
             }
@@ -386,7 +405,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__res
                 const int n = p_out + k * P + r * (N / R);
                 const C x = v[k * R + r];
                 if constexpr (KIND == GAMMA_FWD) {
-                    if (n != B) dst[((size_t)n * N + line) * N + row] = x;
+                    if (n != B) dst[t1_index<N, T>(line, n, row)] = x;
                 } else if constexpr (KIND == ALPHA_FWD) {
                     if (n != B) {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
@@ -394,7 +413,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__res
                         dst[(size_t)(sl >> 1) * N + jj] = cscale(x, wj);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
-                    dst[((size_t)line * N + row) * N + n] = x;
+                    dst[t1_index<N, T>(row, line, n)] = x;
                 } else {
                     dst[((size_t)row * N + line) * N + n] = cscale(x, wj);
                 }
@@ -405,12 +424,12 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_fft(PlanView p, const C *__res
 
 template <int N, int KIND, int SIGN, typename C>
 hipError_t launch_kind(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
-    using Sh = Shape<N>;
+    using Ti = Tile<N, C>;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
     const int nline = ALPHA ? N - 1 : N;
     // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
-    dim3 g(N / Sh::T, nline, p.nfunc);
-    hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Sh::NT), 0, s, p, in, out, apply_w);
+    dim3 g(N / Ti::T, nline, p.nfunc);
+    hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
     return hipGetLastError();
 }
 

@@ -283,3 +283,19 @@ def test_tuned_plans_match_oracle(oracle, dev, prec):
             gf = g[p.grid_offsets[f]:p.grid_offsets[f + 1]].reshape(N, N, N)
             assert relerr(gf, oracle.inverse(B, cs[f])) <= TOL[prec], (f, B)
         assert relerr(c2[p.coeff_offsets[f]:p.coeff_offsets[f + 1]], cs[f]) <= TOL[prec], (f, B)
+
+
+def test_fp32_split_B512_sampled(oracle, dev):
+    """B = 512 in FP32-split: sampled beta-slices of the inverse against the
+    FP64 oracle on the same FP32-rounded coefficients, and the round trip."""
+    B = 512
+    c = rounded(inputs.coeffs_decay(B, 3), "fp32_split")
+    with soft.Plan(B, precision="fp32_split") as p:
+        gd = p.inverse(to_dev(c, dev, "fp32_split"))
+        cd = to_host(p.forward(gd))
+        g = to_host(gd)
+        del gd
+    torch.cuda.empty_cache()
+    assert relerr(cd, c) <= 1e-6
+    for j in (0, 511, 700):
+        assert relerr(g[:, j, :], oracle.inverse_slice(B, c, j)) <= 1e-6, j
