@@ -108,9 +108,11 @@ typedef enum {
  *   out        receives the plan handle; unchanged on error.
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
- * samples, plus 12 bytes per recurrence row, about B^3/6 rows per bandwidth)
- * and its tables (quadrature weights, Wigner-d seed constants, FFT
- * twiddles, symmetry groups, work lists) on the current HIP device; later
+ * samples; per distinct bandwidth, 12 bytes per recurrence row, about B^3/6
+ * rows, and the 8-byte seeds d(l0, l0, m'; b_j) of every symmetry group at
+ * every beta sample, B(B+1)/2 x 2B of them) and its tables (quadrature
+ * weights, Wigner-d seed constants, FFT twiddles, symmetry groups, work
+ * lists) on the current HIP device; later
  * calls must run with the same device current.  Synchronous.
  * Returns SOFT_OK, SOFT_ERR_INVALID, SOFT_ERR_UNSUPPORTED, SOFT_ERR_OOM or
  * SOFT_ERR_HIP.

@@ -106,6 +106,16 @@ __global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__
     }
 }
 
+// Seeds of every group of a band at every beta sample, once per plan (the
+// DWT kernels load them instead of evaluating exp per work item).
+__global__ __launch_bounds__(256) void k_fill_seeds(PlanView p, double *__restrict__ seed) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)p.G * p.N) return;
+    const int g = (int)(e / p.N), j = (int)(e - (long long)g * p.N);
+    const GroupInfo gi = p.grp[g];
+    seed[e] = seed_d(p.lbin[g], p.lcs[j], gi.m, gi.mp);
+}
+
 // ---------------------------------------------------------------------------
 // Shared pieces
 // ---------------------------------------------------------------------------
@@ -210,19 +220,19 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         const int jbase = (wave * NSUB + h) * 64;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
+            // every lane loads (an in-range sample of its own slot row when its
+            // own is absent or past N), then absent entries are zeroed: no branches
             const int j = jbase + 4 * s + krow;
-            R v = 0;
-            if (col_present && j < N) v = reinterpret_cast<const R *>(Sg + (size_t)(col >> 1) * N + j)[col & 1];
-            xb[h][s] = v;
+            const bool on = col_present && j < N;
+            const R v = reinterpret_cast<const R *>(Sg + (size_t)(col >> 1) * N + (on ? j : 0))[col & 1];
+            xb[h][s] = on ? v : (R)0;
         }
         const int j = jbase + lane;
-        if (j < N) {
-            x[h] = tab.cosb[it.jbase + j];
-            ecur[h] = seed_d(tab.lbin[it.lbin], tab.lcs[it.jbase + j], m, mp);
-        } else {
-            x[h] = 0.0;
-            ecur[h] = 0.0;
-        }
+        const bool jin = j < N;
+        const double xv = tab.cosb[it.jbase + (jin ? j : 0)];
+        const double sv = tab.seed[it.seed_off + (jin ? j : 0)];
+        x[h] = jin ? xv : 0.0;
+        ecur[h] = jin ? sv : 0.0;
         eprev[h] = 0.0;
     }
 
@@ -445,8 +455,11 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int j = (wave * NSUB + h) * 64 + lane;
-        x[h] = j < N ? tab.cosb[it.jbase + j] : 0.0;
-        ecur[h] = j < N ? seed_d(tab.lbin[it.lbin], tab.lcs[it.jbase + j], m, mp) : 0.0;
+        const bool jin = j < N;
+        const double xv = tab.cosb[it.jbase + (jin ? j : 0)];
+        const double sv = tab.seed[it.seed_off + (jin ? j : 0)];
+        x[h] = jin ? xv : 0.0;
+        ecur[h] = jin ? sv : 0.0;
         eprev[h] = 0.0;
     }
     v4d acc[NSUB][4];
@@ -561,6 +574,12 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 }
 
 }  // namespace
+
+hipError_t launch_fill_seeds(const PlanView &p, double *seed, hipStream_t s) {
+    const long long n = (long long)p.G * p.N;
+    hipLaunchKernelGGL(k_fill_seeds, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, seed);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_recurrence, dim3((p.G + 255) / 256), dim3(256), 0, s, p, rec, rscale);

@@ -35,6 +35,7 @@ using soft::WorkItem;
 struct Band {
     int B = 0, N = 0, G = 0;
     int jbase = 0, gbase = 0;  // first entry in the plan-wide beta and group tables
+    long long seed_base = 0;   // first entry of the band's G x 2B seeds in the seed table
     long long Nc = 0, rows = 0, row_base = 0;
     std::vector<int> funcs;  // plan function indices, increasing
     size_t tab_off = 0;      // byte offset of the band's tables in the table block
@@ -66,6 +67,8 @@ struct soft_plan_s {
     void *S = nullptr, *t1 = nullptr;
     double2 *rec = nullptr;
     double *rscale = nullptr;
+    double *seed = nullptr;
+    long long seed_total = 0;
     soft::DwtTables dtab{};
     size_t ws_bytes = 0;
     // stage timing
@@ -109,6 +112,7 @@ void free_plan(soft_plan_s *p) {
     if (p->t1) (void)hipFree(p->t1);
     if (p->rec) (void)hipFree(p->rec);
     if (p->rscale) (void)hipFree(p->rscale);
+    if (p->seed) (void)hipFree(p->seed);
     delete p;
 }
 
@@ -486,6 +490,8 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             b.G = B * (B + 1) / 2;
             b.jbase = jtot;
             b.gbase = gtot;
+            b.seed_base = p->seed_total;
+            p->seed_total += (long long)b.G * b.N;
             jtot += b.N;
             gtot += b.G;
             b.Nc = (long long)B * (4LL * B * B - 1) / 3;
@@ -570,7 +576,7 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
                     w.coeff_off = fi.coeff_off;
                     w.B = b.B;
                     w.jbase = b.jbase;
-                    w.lbin = b.gbase + g;
+                    w.seed_off = b.seed_base + (long long)g * b.N;
                     w.m = m;
                     w.mp = mp;
                     w.mask = group_mask(m, mp);
@@ -632,19 +638,21 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         if (hipMalloc(&p->tables, total) != hipSuccess || hipMalloc(&p->S, p->s_total * p->csize) != hipSuccess ||
             hipMalloc(&p->t1, p->t1_elems * p->csize) != hipSuccess ||
             hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
-            hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess) {
+            hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess ||
+            hipMalloc(&p->seed, p->seed_total * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             free_plan(p);
             return SOFT_ERR_OOM;
         }
-        p->ws_bytes = total + (p->s_total + p->t1_elems) * p->csize + rec_rows * (sizeof(double2) + sizeof(double));
+        p->ws_bytes = total + (p->s_total + p->t1_elems) * p->csize + rec_rows * (sizeof(double2) + sizeof(double)) +
+                      p->seed_total * sizeof(double);
 
         // Band views with device pointers (kernel arguments of the FFT passes
         // and of the recurrence fill), and the DWT kernels' plan-wide tables.
         const double *cosb_d = reinterpret_cast<const double *>(p->tables + cosb_off);
         const double4 *lcs_d = reinterpret_cast<const double4 *>(p->tables + lcs_off);
         const double2 *lbin_d = reinterpret_cast<const double2 *>(p->tables + lbin_off);
-        p->dtab = soft::DwtTables{cosb_d, lcs_d, lbin_d, p->rscale, p->rec};
+        p->dtab = soft::DwtTables{cosb_d, p->seed, p->rscale, p->rec};
         for (size_t bi = 0; bi < p->bands.size(); ++bi) {
             Band &b = p->bands[bi];
             const BandLayout &lay = lays[bi];
@@ -675,8 +683,10 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         // Padding rows are read (never used) by prefetches; give them defined values.
         if (e == hipSuccess) e = hipMemset(p->rec, 0, rec_rows * sizeof(double2));
         if (e == hipSuccess) e = hipMemset(p->rscale, 0, rec_rows * sizeof(double));
-        for (const Band &b : p->bands)
+        for (const Band &b : p->bands) {
             if (e == hipSuccess) e = soft::launch_fill_recurrence(b.view, p->rec, p->rscale, 0);
+            if (e == hipSuccess) e = soft::launch_fill_seeds(b.view, p->seed + b.seed_base, 0);
+        }
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e == hipSuccess && (flags & SOFT_PLAN_TUNE)) {
             const int rc = tune_dwt(p);

@@ -126,18 +126,18 @@ struct WorkItem {
     long long goff;       // first row of the group in the plan-wide recurrence tables
     long long s_off;      // the group's beta-sample block in S (complex elements)
     long long coeff_off;  // the function's coefficient vector (complex elements)
+    long long seed_off;   // the group's 2B seeds d(l0, l0, m'; b_j) in the seed table
     int B;                // bandwidth of the function
     int jbase;            // the band's first entry in the plan-wide beta tables
-    int lbin;             // the group's entry in the plan-wide log-binomial table
     int m, mp;            // representative, m >= mp >= 0
     int mask;             // bit s set when slot s is present
+    int pad;
 };
 
 // Plan-wide tables of the DWT kernels (kernel arguments).
 struct DwtTables {
     const double *cosb;   // cos(beta_j), band by band
-    const double4 *lcs;   // (log cos(b_j/2) hi, lo, log sin(b_j/2) hi, lo), band by band
-    const double2 *lbin;  // 0.5 log((2m)!/((m+m')!(m-m')!)) as (hi, lo), group by group
+    const double *seed;   // d(l0, l0, m'; b_j) per group and beta sample, band by band
     const double *rscale; // s_l per row (d(l) = s_l e(l))
     const double2 *rec;   // (alpha_l, gamma_l) per row (the kernels take it as a separate
                           // restrict argument, so its loads can use the scalar cache)
@@ -178,6 +178,10 @@ hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool ap
 // Plan-time fill of the rescaled recurrence table of one band (rows from
 // goff[g]; rec and rscale are the plan-wide tables).
 hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s);
+
+// Plan-time fill of one band's seed table: seed[g*N + j] = d(l0, l0, m'; b_j)
+// for every group g of the band (N = 2B entries per group).
+hipError_t launch_fill_seeds(const PlanView &p, double *seed, hipStream_t s);
 
 // DWT and iDWT over a device work list (one block per item), all items
 // sharing one launch shape: nw waves, nsub subsets of 64 beta samples per
