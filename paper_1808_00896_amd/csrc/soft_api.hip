@@ -19,6 +19,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -230,12 +231,15 @@ int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double 
     return SOFT_OK;
 }
 
-// DWT launch shape (waves per block, beta sub-tiles per lane) of length N.
-std::pair<int, int> shape_for(int N) {
-    if (N <= 64) return {1, 1};
+// Default DWT launch shape (waves per block, subsets of 64 beta samples per
+// wave) of length N = 2B, forward and inverse: the fastest shape measured per
+// length on MI355X (SOFT_PLAN_TUNE re-measures on the plan itself).
+std::pair<int, int> shape_for(int N, bool forward) {
+    if (N <= 32) return {1, 1};
+    if (N == 64) return forward ? std::make_pair(1, 1) : std::make_pair(2, 1);
     if (N == 128) return {2, 1};
-    if (N == 256) return {4, 1};
-    if (N == 512) return {8, 1};
+    if (N == 256) return forward ? std::make_pair(2, 2) : std::make_pair(4, 1);
+    if (N == 512) return forward ? std::make_pair(4, 2) : std::make_pair(8, 1);
     return {8, 2};
 }
 
@@ -519,17 +523,16 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
 
         // DWT launch groups: in a plan of several bands, all bands with
-        // 2B <= 256 share one launch of 4-wave blocks; otherwise each length
-        // keeps its own shape.
+        // 2B <= 256 share one launch (with the 2B = 256 shapes); every other
+        // length has its own.
         const bool merged = p->bands.size() > 1;
-        std::vector<std::pair<int, int>> shapes;
+        std::vector<int> keys;  // 0 for the shared launch, else 2B
         std::vector<std::vector<int>> group_bands;
         for (size_t bi = 0; bi < p->bands.size(); ++bi) {
-            std::pair<int, int> sh = shape_for(p->bands[bi].N);
-            if (merged && p->bands[bi].N <= 256) sh = {4, 1};
-            size_t gi = std::find(shapes.begin(), shapes.end(), sh) - shapes.begin();
-            if (gi == shapes.size()) {
-                shapes.push_back(sh);
+            const int key = merged && p->bands[bi].N <= 256 ? 0 : p->bands[bi].N;
+            size_t gi = std::find(keys.begin(), keys.end(), key) - keys.begin();
+            if (gi == keys.size()) {
+                keys.push_back(key);
                 group_bands.emplace_back();
             }
             group_bands[gi].push_back((int)bi);
@@ -551,8 +554,8 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         // remap hands each run to one XCD), ordered by the cost (B - m) 2B of
         // their first group, largest first, so the long recurrences start
         // early and the short ones fill the tail.
-        std::vector<std::vector<WorkItem>> lists(shapes.size());
-        for (size_t gi = 0; gi < shapes.size(); ++gi) {
+        std::vector<std::vector<WorkItem>> lists(keys.size());
+        for (size_t gi = 0; gi < keys.size(); ++gi) {
             struct Run {
                 long long cost;
                 int band, func, g0, g1;
@@ -588,8 +591,9 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
                 return SOFT_ERR_UNSUPPORTED;
             }
             LaunchGroup lg;
-            lg.nw_f = lg.nw_i = shapes[gi].first;
-            lg.nsub_f = lg.nsub_i = shapes[gi].second;
+            const int len = keys[gi] ? keys[gi] : 256;
+            std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true);
+            std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false);
             lg.bands = group_bands[gi];
             for (int bi : group_bands[gi]) lg.nmax = std::max(lg.nmax, p->bands[bi].N);
             lg.nitems = (int)lists[gi].size();
