@@ -361,47 +361,51 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 // samples x 4 degrees of it and the B operand 4 degrees x 16 member columns of
 // the group's coefficients.  Those are gathered by the whole block straight
 // from the l-major layout (the inverse reorder: symmetry sign, s_l and
-// optionally V_B applied on the way) into double-buffered LDS chunks of 32
+// optionally V_B applied on the way) into double-buffered LDS chunks of KC
 // degrees, issued one chunk ahead; rows past the group's end are zero, so
 // panel rows past it (the continued recurrence) contribute nothing.  The
 // recurrence coefficients arrive through scalar loads issued after the
 // panel's LDS reads.  FP32 modes sum each panel in FP32 and the panels in FP64.
-constexpr int kChunk = 32;
+// Degrees per staged chunk: 16 for blocks of up to four waves (a smaller
+// stage buffer lets a fourth block share the CU), 32 above.
+template <int NW>
+constexpr int chunk_of() { return NW <= 4 ? 16 : 32; }
 
 // Thread k-slot q of a block gathers element e = threadIdx.x + q*NT = row*16
-// + col of every chunk (degree c*32 + row, column col = 2 slot + part).  Its
+// + col of every chunk (degree c*KC + row, column col = 2 slot + part).  Its
 // member, sign and part are the same in every chunk (chunks advance the
-// degree by 32, so parity-dependent signs stay), so they are set once.
-template <int NT, typename R>
+// degree by KC, an even number, so parity-dependent signs stay), so they are
+// set once.
+template <int NT, int KC, typename R>
 struct InvGather {
-    static constexpr int PER = (kChunk * 16 + NT - 1) / NT;  // values per thread
+    static constexpr int PER = (KC * 16 + NT - 1) / NT;  // values per thread
     R v[PER];
     int mm[PER], mmp[PER];
     double sign[PER];
     bool on[PER];
 };
 
-template <int NT, typename R>
-__device__ __forceinline__ void inv_gather_init(InvGather<NT, R> &st, const WorkItem &it) {
+template <int NT, int KC, typename R>
+__device__ __forceinline__ void inv_gather_init(InvGather<NT, KC, R> &st, const WorkItem &it) {
 #pragma unroll
-    for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT, KC, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
         const int slot = (e & 15) >> 1;
-        st.on[k] = e < kChunk * 16 && ((it.mask >> slot) & 1);
+        st.on[k] = e < KC * 16 && ((it.mask >> slot) & 1);
         group_member(slot, it.m, it.mp, it.m + (e >> 4), st.mm[k], st.mmp[k], st.sign[k]);
     }
 }
 
-// Gather chunk c (degrees c*32 .. c*32+31): the inverse reorder, with the
+// Gather chunk c (degrees c*KC .. c*KC+KC-1): the inverse reorder, with the
 // member's sign, s_l and optionally V_B applied; rows past L are zero.
-template <int NT, typename R>
-__device__ __forceinline__ void inv_gather(InvGather<NT, R> &st, const double *__restrict__ rscale,
+template <int NT, int KC, typename R>
+__device__ __forceinline__ void inv_gather(InvGather<NT, KC, R> &st, const double *__restrict__ rscale,
                                            const R *__restrict__ cin, const WorkItem &it, int L, int c,
                                            double v0) {
 #pragma unroll
-    for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT, KC, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
-        const int li = c * kChunk + (e >> 4);
+        const int li = c * KC + (e >> 4);
         double val = 0.0;
         if (st.on[k] && li < L) {
             const int l = it.m + li;
@@ -415,14 +419,14 @@ __device__ __forceinline__ void inv_gather(InvGather<NT, R> &st, const double *_
 // Stage a gathered chunk.  Within each 16-degree block, degree d goes to row
 // 4(d%4) + d/4, so the MFMA k slot (s, lane/16) that takes degree s + 4(lane/16)
 // reads the contiguous rows 4s + lane/16.
-template <int NT, typename R>
-__device__ __forceinline__ void inv_put(const InvGather<NT, R> &st, R *buf) {
+template <int NT, int KC, typename R>
+__device__ __forceinline__ void inv_put(const InvGather<NT, KC, R> &st, R *buf) {
 #pragma unroll
-    for (int k = 0; k < InvGather<NT, R>::PER; ++k) {
+    for (int k = 0; k < InvGather<NT, KC, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
         const int row = e >> 4;
         const int prow = (row & ~15) | ((row & 3) << 2) | ((row >> 2) & 3);
-        if (e < kChunk * 16) buf[prow * 16 + (e & 15)] = st.v[k];
+        if (e < KC * 16) buf[prow * 16 + (e & 15)] = st.v[k];
     }
 }
 
@@ -435,21 +439,22 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     using R = typename PrecT<PR>::R;
     constexpr int NT = NW * 64;
     __shared__ double panel[NW][16 * kRowInv];
-    __shared__ R stage[2][kChunk * 16];
+    constexpr int KC = chunk_of<NW>();
+    __shared__ R stage[2][KC * 16];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
     const int B = it.B, N = 2 * B;
     const int m = it.m, mp = it.mp;
     const int L = B - m;
-    const int nchunk = (L + kChunk - 1) / kChunk;
+    const int nchunk = (L + KC - 1) / KC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
     const double2 *__restrict__ Rr = rec + it.goff;
     const R *__restrict__ cin = reinterpret_cast<const R *>(coeffs + it.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
 
-    InvGather<NT, R> st;
-    inv_gather_init<NT, R>(st, it);
-    inv_gather<NT, R>(st, tab.rscale, cin, it, L, 0, v0);
+    InvGather<NT, KC, R> st;
+    inv_gather_init<NT, KC, R>(st, it);
+    inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 0, v0);
 
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
@@ -472,14 +477,14 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
 
-    inv_put<NT, R>(st, stage[0]);
-    if (nchunk > 1) inv_gather<NT, R>(st, tab.rscale, cin, it, L, 1, v0);
+    inv_put<NT, KC, R>(st, stage[0]);
+    if (nchunk > 1) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 1, v0);
     __syncthreads();
 
     double *pan = panel[wave];
     for (int lp = 0; lp < L; lp += 16) {
-        const int ch = lp / kChunk;
-        const R *fb = stage[ch & 1] + (lp - ch * kChunk) * 16;
+        const int ch = lp / KC;
+        const R *fb = stage[ch & 1] + (lp - ch * KC) * 16;
         R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
@@ -538,10 +543,10 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
             }
         }
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
-        if (lp + 16 - ch * kChunk == kChunk || lp + 16 >= L) {
+        if (lp + 16 - ch * KC == KC || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
-                inv_put<NT, R>(st, stage[(ch + 1) & 1]);
-                if (ch + 2 < nchunk) inv_gather<NT, R>(st, tab.rscale, cin, it, L, ch + 2, v0);
+                inv_put<NT, KC, R>(st, stage[(ch + 1) & 1]);
+                if (ch + 2 < nchunk) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, ch + 2, v0);
             }
             __syncthreads();
         }
