@@ -183,9 +183,11 @@ __device__ __forceinline__ int out_row(int krow, int r) {
 // recurrence value at degree l0 + lp + r for j-local jl in the wave's own LDS
 // region.  Panel rows past the group's last degree hold values of the
 // continued recurrence; they only reach output rows that are never written.
-// A wave's LDS operations complete in order, so the panel needs no block
-// barrier; the only barrier per panel is the one before the cross-wave FP64
-// sum, whose buffer alternates between two halves.  The recurrence
+// A wave's LDS operations complete in order, so filling and reading its own
+// panel needs no block barrier.  Once its A operands are in registers, each
+// wave parks its 16 x 16 partial sums in its own panel; one barrier before
+// and one after the cross-wave FP64 sum (no separate reduction buffer, which
+// keeps four 4-wave blocks within a CU's LDS).  The recurrence
 // coefficients of a panel (16 x (alpha, gamma)) sit in scalar registers; the
 // next panel's are loaded after this panel's LDS reads, behind the MFMAs.
 // Four accumulators keep four MFMA chains in flight (in the FP32 modes each
@@ -199,7 +201,6 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     using R = typename PrecT<PR>::R;
     // s_l of the group's degrees: at most B = NW*NSUB*32 for this shape.
     __shared__ double panel[NW][16 * kRowFwd];
-    __shared__ double red[2][NW][256];
     __shared__ double srow[NW * NSUB * 32];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
     const int B = it.B, N = 2 * B;
@@ -260,8 +261,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         e_on[q] = t < 256 && ((mask >> slot) & 1);
         group_member(slot, m, mp, m + (t >> 4), e_mm[q], e_mmp[q], e_sign[q]);
     }
-    int buf = 0;
-    for (int lp = 0; lp < L; lp += 16, buf ^= 1) {
+    for (int lp = 0; lp < L; lp += 16) {
         double tot[4];
         if constexpr (PR == P64) {
             v4d acc[4];
@@ -331,8 +331,10 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
                 tot[r] = t;
             }
         }
+        // The wave's panel is free once its A operands are in registers: park
+        // the wave's 16 x 16 partial sums there for the cross-wave sum.
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[buf][wave][out_row<PR>(krow, r) * 16 + col] = tot[r];
+        for (int r = 0; r < 4; ++r) pan[out_row<PR>(krow, r) * 16 + col] = tot[r];
         __syncthreads();
         // Epilogue (the reorder): column c = 2 slot + part of row lp + r is
         // f°(l, member of slot) up to the slot's symmetry sign, s_l and V_B.
@@ -343,12 +345,14 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
             if (e_on[q] && li < L) {
                 double sum = 0.0;
 #pragma unroll
-                for (int w = 0; w < NW; ++w) sum += red[buf][w][t];
+                for (int w = 0; w < NW; ++w) sum += panel[w][t];
                 const int l = m + li;
                 const double f = e_sign[q] * srow[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
                 out[2 * coeff_index32(l, e_mm[q], e_mmp[q]) + (t & 1)] = (R)(sum * f);
             }
         }
+        // every wave has read the partial sums before any panel is refilled
+        __syncthreads();
     }
 }
 

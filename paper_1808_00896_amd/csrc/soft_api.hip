@@ -239,7 +239,7 @@ std::pair<int, int> shape_for(int N, bool forward) {
     if (N == 64) return forward ? std::make_pair(1, 1) : std::make_pair(2, 1);
     if (N == 128) return {2, 1};
     if (N == 256) return forward ? std::make_pair(2, 2) : std::make_pair(4, 1);
-    if (N == 512) return forward ? std::make_pair(4, 2) : std::make_pair(8, 1);
+    if (N == 512) return {4, 2};
     return {8, 2};
 }
 
