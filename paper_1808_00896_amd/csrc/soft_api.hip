@@ -393,10 +393,12 @@ constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2},
 
 // Autotuner: for every DWT launch group and direction, time each shape that
 // covers the group's largest 2B (and is at most twice that) on the plan's own
-// work list and workspace, with zeroed data, and keep the fastest.  Each
-// candidate runs once untimed, then kTuneReps timed launches between two HIP
-// events on the null stream.
-constexpr int kTuneReps = 3;
+// work list and workspace, with zeroed data, and keep the fastest.  Every
+// candidate runs once untimed (which also brings the clocks up), then
+// kTuneRounds rounds launch each candidate once in turn, each launch between
+// two HIP events on the null stream; a candidate's time is its fastest
+// launch, so a slow outlier or a clock ramp inside one round decides nothing.
+constexpr int kTuneRounds = 5;
 
 template <int PR>
 hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
@@ -407,35 +409,35 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
     C *S = static_cast<C *>(p->S), *cf = static_cast<C *>(coeffs);
     for (LaunchGroup &lg : p->groups) {
         for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-            float best = 0.f;
-            int bw = 0, bs = 0;
-            for (const auto &sh : kDwtShapes) {
-                const int cover = sh[0] * sh[1] * 64;
-                if (cover < lg.nmax || cover > 2 * lg.nmax) continue;
-                auto launch = [&]() {
-                    return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, sh[0], sh[1], S, cf,
-                                                               true, 0)
-                                    : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, sh[0], sh[1], cf, S,
-                                                               false, 0);
-                };
-                e = launch();
-                if (e == hipSuccess) e = hipEventRecord(t0, 0);
-                for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = launch();
-                if (e == hipSuccess) e = hipEventRecord(t1, 0);
-                if (e == hipSuccess) e = hipEventSynchronize(t1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                if (e != hipSuccess) break;
-                if (bw == 0 || ms < best) {
-                    best = ms;
-                    bw = sh[0];
-                    bs = sh[1];
+            std::vector<int> cand;
+            for (int c = 0; c < (int)(sizeof(kDwtShapes) / sizeof(kDwtShapes[0])); ++c) {
+                const int cover = kDwtShapes[c][0] * kDwtShapes[c][1] * 64;
+                if (cover >= lg.nmax && cover <= 2 * lg.nmax) cand.push_back(c);
+            }
+            auto launch = [&](int c) {
+                const int nw = kDwtShapes[c][0], ns = kDwtShapes[c][1];
+                return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true, 0)
+                                : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false, 0);
+            };
+            std::vector<float> best(cand.size(), 0.f);
+            for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) e = launch(cand[i]);
+            for (int r = 0; r < kTuneRounds && e == hipSuccess; ++r) {
+                for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+                    e = hipEventRecord(t0, 0);
+                    if (e == hipSuccess) e = launch(cand[i]);
+                    if (e == hipSuccess) e = hipEventRecord(t1, 0);
+                    if (e == hipSuccess) e = hipEventSynchronize(t1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                    if (e == hipSuccess && (r == 0 || ms < best[i])) best[i] = ms;
                 }
             }
-            if (e == hipSuccess && bw) {
-                (dir == 0 ? lg.nw_f : lg.nw_i) = bw;
-                (dir == 0 ? lg.nsub_f : lg.nsub_i) = bs;
-            }
+            if (e != hipSuccess || cand.empty()) continue;
+            size_t bi = 0;
+            for (size_t i = 1; i < cand.size(); ++i)
+                if (best[i] < best[bi]) bi = i;
+            (dir == 0 ? lg.nw_f : lg.nw_i) = kDwtShapes[cand[bi]][0];
+            (dir == 0 ? lg.nsub_f : lg.nsub_i) = kDwtShapes[cand[bi]][1];
         }
         lg.tuned = e == hipSuccess;
     }
