@@ -86,8 +86,17 @@ typedef enum {
  *                   list with zeroed data, and keep the fastest.  Costs a few
  *                   DWT launches per candidate at plan creation; without it
  *                   a fixed shape per 2B is used.
+ *   SOFT_INPLACE_OK the plan may use the grid buffers as scratch, and holds
+ *                   no FFT intermediate of its own (that saves (2B)^3 complex
+ *                   elements per function of the largest band: 16 GiB at
+ *                   B = 512 in FP64).  soft_forward and soft_adjoint_inverse
+ *                   then overwrite their input grid (its contents are
+ *                   unspecified after the call); soft_inverse and
+ *                   soft_adjoint stage in their output grid.  Results are
+ *                   bit-identical to a plan without the flag; the FFT passes
+ *                   move shorter runs and are somewhat slower.
  */
-enum { SOFT_PLAN_TUNE = 1u };
+enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u };
 
 typedef enum {
     SOFT_OK = 0,
@@ -104,12 +113,13 @@ typedef enum {
  *   B          bandwidth, a power of two with 1 <= B <= 512.
  *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
- *   flags      0 or SOFT_PLAN_TUNE; other bits are SOFT_ERR_INVALID.
+ *   flags      0, SOFT_PLAN_TUNE, SOFT_INPLACE_OK or both; other bits are
+ *              SOFT_ERR_INVALID.
  *   out        receives the plan handle; unchanged on error.
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
- * samples; per distinct bandwidth, 12 bytes per recurrence row, about B^3/6
- * rows, and the 8-byte seeds d(l0, l0, m'; b_j) of every symmetry group at
+ * samples, or about (2B)^3 with SOFT_INPLACE_OK; per distinct bandwidth,
+ * 12 bytes per recurrence row, about B^3/6 rows, and the 8-byte seeds d(l0, l0, m'; b_j) of every symmetry group at
  * every beta sample, B(B+1)/2 x 2B of them) and its tables (quadrature
  * weights, Wigner-d seed constants, FFT twiddles, symmetry groups, work
  * lists) on the current HIP device; later
@@ -179,7 +189,8 @@ int soft_plan_offsets(soft_plan_t plan, size_t *grid_offsets, size_t *coeff_offs
 /*
  * soft_forward -- FSOFT (eq. "quadrature" via Sect. 2.4): coefficients of
  * the sampled functions.
- *   grid    device pointer, the plan's grids (read only).
+ *   grid    device pointer, the plan's grids (read only; overwritten with
+ *           scratch by a SOFT_INPLACE_OK plan).
  *   coeffs  device pointer, the plan's coefficient vectors (written).
  *   stream  HIP stream the work is enqueued on (0 = null stream).
  * The input grid need not be band-limited; the result is the quadrature sum.

@@ -5,7 +5,9 @@ convention the backward of y = A x is grad_x = A^H grad_y:
   SoftForward  (F, the quadrature of eq. "quadrature"):  backward = F^H = W I V
   SoftInverse  (I, eq. "fourier_representation"):        backward = I^H = V^-1 F W^-1
 Both adjoints are entry points of the library (soft_adjoint,
-soft_adjoint_inverse); nothing here computes on the host.
+soft_adjoint_inverse); nothing here computes on the host.  With an
+``inplace_ok`` plan the forward-type calls overwrite their input grid, so
+the grid handed to them here is a copy.
 
 SoftCorrelation forms the correlation coefficients a(l,M) conj(b(l,M')) of
 the rotational-matching head; its backward is the library's vector-Jacobian
@@ -16,11 +18,17 @@ import torch
 from . import soft
 
 
+def _scratch_copy(grid, plan):
+    """The grid to hand to a forward-type call: a private copy when the plan
+    may overwrite it."""
+    return grid.clone(memory_format=torch.contiguous_format) if plan.inplace_ok else grid.contiguous()
+
+
 class SoftForward(torch.autograd.Function):
     @staticmethod
     def forward(ctx, grid, plan):
         ctx.plan = plan
-        return plan.forward(grid.contiguous())
+        return plan.forward(_scratch_copy(grid, plan))
 
     @staticmethod
     def backward(ctx, grad_coeffs):
@@ -35,7 +43,7 @@ class SoftInverse(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_grid):
-        return ctx.plan.adjoint_inverse(grad_grid.contiguous()), None
+        return ctx.plan.adjoint_inverse(_scratch_copy(grad_grid, ctx.plan)), None
 
 
 def soft_forward(grid, plan):

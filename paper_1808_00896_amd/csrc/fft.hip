@@ -261,10 +261,52 @@ __device__ __forceinline__ size_t t1_index(int j, int q, int i) {
 // Pass kinds: where a block's T sequences come from and go to.
 enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
 
-template <int KIND>
-constexpr bool transposed_in() { return KIND == ALPHA_INV || KIND == GAMMA_INV; }
-template <int KIND>
-constexpr bool transposed_out() { return KIND == GAMMA_FWD || KIND == ALPHA_FWD; }
+// Lane order of a side of a pass: ROWS puts a sequence's elements on
+// neighbouring lanes (the side is contiguous along the sequence); TILES puts
+// the T sequences of the block on neighbouring lanes (the side is contiguous
+// across sequences); TILES_J is TILES for the natural-layout alpha passes,
+// whose T = TJ x TQ sequences are ordered q-fastest, with the lanes walking
+// them j-fastest (the S side of those passes is contiguous along j).
+enum LaneOrder { ROWS = 0, TILES = 1, TILES_J = 2 };
+
+// The default layout goes through the tile-blocked t1; the natural layout
+// (NAT) keeps the intermediate in grid order [i][j][q], in the grid buffer
+// itself: the gamma passes then work in place, and the alpha passes take a
+// TJ x TQ tile of (j, q).
+template <int KIND, bool NAT>
+constexpr int order_in() {
+    if constexpr (NAT) return KIND == ALPHA_FWD ? TILES : (KIND == ALPHA_INV ? TILES_J : ROWS);
+    return KIND == ALPHA_INV || KIND == GAMMA_INV ? TILES : ROWS;
+}
+template <int KIND, bool NAT>
+constexpr int order_out() {
+    if constexpr (NAT) return KIND == ALPHA_FWD ? TILES_J : (KIND == ALPHA_INV ? TILES : ROWS);
+    return KIND == GAMMA_FWD || KIND == ALPHA_FWD ? TILES : ROWS;
+}
+
+// Natural-layout alpha tile: TQ = 2^floor(log2(T)/2) frequencies q by
+// TJ = T / TQ samples j.
+template <int T>
+struct NatTile {
+    static constexpr int TQ = 1 << (ilog2(T) / 2);
+    static constexpr int TJ = T / TQ;
+};
+
+// (sequence, position) of lane tid for a side with the given order.
+template <int ORDER, int T, int P, int TJ, int TQ>
+__device__ __forceinline__ void lane_seq(int tid, int &t, int &pos) {
+    if constexpr (ORDER == ROWS) {
+        t = tid / P;
+        pos = tid % P;
+    } else if constexpr (ORDER == TILES) {
+        t = tid % T;
+        pos = tid / T;
+    } else {
+        const int u = tid % T;
+        t = (u % TJ) * TQ + u / TJ;
+        pos = tid / T;
+    }
+}
 
 // Block -> (tile, line, batch).  Consecutive logical blocks are placed on the
 // same XCD (the hardware deals blocks round-robin over the 8 XCDs), so the
@@ -302,48 +344,65 @@ __device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int
 // contiguous run of T*N elements, and a gamma block's runs of T elements for
 // the N values of q stay within one window of T*N^2 elements (instead of
 // striding over all N^3).
-template <int N, int KIND, int SIGN, typename C>
-__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
-                                                     int apply_w) {
+//
+// NAT: the intermediate sits in grid order, u[(i*N + j)*N + q], inside the
+// grid buffer of the function.  The gamma blocks (i-tile, j) read and write
+// the same T rows (every load of a block is consumed before its first
+// barrier, so the pass is safe in place); the alpha blocks (j-tile, q-tile)
+// move runs of TQ elements on the grid side and TJ on the S side.  The
+// sequences at the +-B frequency q = B run like the others (so that every
+// sequence sees the same arithmetic as in the tile-blocked passes): the
+// forward drops them, the inverse stores them where its gamma pass writes
+// the final values.
+template <int N, int KIND, int SIGN, typename C, bool NAT>
+__device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int apply_w) {
     using Sh = Shape<N>;
     constexpr int T = Tile<N, C>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
     constexpr int B = N / 2;
     constexpr int LAST = NSTG - 1;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
+    constexpr bool NAT_ALPHA = NAT && ALPHA;
+    constexpr int TQ = NAT_ALPHA ? NatTile<T>::TQ : 1, TJ = NAT_ALPHA ? NatTile<T>::TJ : T;
     __shared__ C lds[Tile<N, C>::LDS];
     const C *tw = twiddles<C>(p, SIGN);
 
-    // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
-    const BlockPos bp = block_pos(N / T, ALPHA ? N - 1 : N);
+    // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1),
+    // q-tiles for natural-layout alpha passes (N / TQ).
+    const BlockPos bp = NAT_ALPHA ? block_pos(N / TJ, N / TQ) : block_pos(N / T, ALPHA ? N - 1 : N);
     const int tile = bp.tile;
-    const int line = ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line;
+    const int line = NAT_ALPHA ? bp.line : (ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line);
     const size_t N3 = (size_t)N * N * N;
     const FuncInfo fi = p.funcs[p.band_funcs[bp.batch]];
     const C *src;
     C *dst;
     if constexpr (KIND == GAMMA_FWD) {
         src = in + fi.grid_off;
-        dst = out + bp.batch * N3;
+        dst = out + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
     } else if constexpr (KIND == ALPHA_FWD) {
-        src = in + bp.batch * N3;
+        src = in + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
         dst = out + fi.s_off;
     } else if constexpr (KIND == ALPHA_INV) {
         src = in + fi.s_off;
-        dst = out + bp.batch * N3;
+        dst = out + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
     } else {
-        src = in + bp.batch * N3;
+        src = in + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
         dst = out + fi.grid_off;
     }
     const int tid = threadIdx.x;
-    const int mp_line = line < B ? line : line - N;  // m' of an alpha-pass block
+
+    // Sequence t of the block: row (i for gamma, j for alpha) and q (alpha).
+    auto seq_row = [&](int t) { return NAT_ALPHA ? tile * TJ + t / TQ : tile * T + t; };
+    auto seq_q = [&](int t) { return NAT_ALPHA ? line * TQ + t % TQ : line; };
 
     C v[E];
     // ---- stage 0 inputs from HBM: element b + r*N/R ----
-    const int t_in = transposed_in<KIND>() ? tid % T : tid / P;
-    const int p_in = transposed_in<KIND>() ? tid / T : tid % P;
+    int t_in, p_in;
+    lane_seq<order_in<KIND, NAT>(), T, P, TJ, TQ>(tid, t_in, p_in);
     {
         constexpr int R = radix_of<N, 0>(), BPT = N / R / P;
-        const int row = tile * T + t_in;  // i (gamma) or j (alpha)
+        const int row = seq_row(t_in);  // i (gamma) or j (alpha)
+        const int q = seq_q(t_in);
+        const int mp = q < B ? q : q - N;  // m' of an alpha-pass sequence
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
 #pragma unroll
@@ -353,17 +412,27 @@ __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *_
                 if constexpr (KIND == GAMMA_FWD) {
                     x = src[((size_t)row * N + line) * N + n];
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    x = src[t1_index<N, T>(row, line, n)];
+                    if constexpr (NAT) {
+                        x = src[((size_t)n * N + row) * N + q];  // q = B: loaded, transformed, dropped
+                    } else {
+                        x = src[t1_index<N, T>(row, line, n)];
+                    }
                 } else if constexpr (KIND == ALPHA_INV) {
                     if (n == B) {
                         x = mk<C>(0.0, 0.0);
                     } else {
-                        const int sl = slot_code(n < B ? n : n - N, mp_line);
+                        // q = B (natural layout only) reads a valid slot; its
+                        // sequence lands where the gamma pass writes last.
+                        const int sl = slot_code(n < B ? n : n - N, NAT && q == B ? B - 1 : mp);
                         const int jj = (sl & 1) ? N - 1 - row : row;
                         x = src[(size_t)(sl >> 1) * N + jj];
                     }
                 } else {
-                    x = n == B ? mk<C>(0.0, 0.0) : src[t1_index<N, T>(line, n, row)];
+                    if constexpr (NAT) {
+                        x = n == B ? mk<C>(0.0, 0.0) : src[((size_t)row * N + line) * N + n];
+                    } else {
+                        x = n == B ? mk<C>(0.0, 0.0) : src[t1_index<N, T>(line, n, row)];
+                    }
                 }
                 v[k * R + r] = x;
             }
@@ -384,8 +453,7 @@ __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *_
             put_stage<N, 1, C>(v, lds, t, pp);
             __syncthreads();
         }
-        t_out = transposed_out<KIND>() ? tid % T : t;
-        p_out = transposed_out<KIND>() ? tid / T : pp;
+        lane_seq<order_out<KIND, NAT>(), T, P, TJ, TQ>(tid, t_out, p_out);
         get_stage<N, LAST, C>(v, lds, t_out, p_out);
         run_stage<N, LAST, SIGN, C>(v, p_out, tw);
     }
@@ -393,7 +461,9 @@ __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *_
     // ---- last stage outputs to HBM: element b + r*N/R ----
     {
         constexpr int R = radix_of<N, LAST>(), BPT = N / R / P;
-        const int row = tile * T + t_out;
+        const int row = seq_row(t_out);
+        const int q = seq_q(t_out);
+        const int mp = q < B ? q : q - N;
         double wj = 1.0;
         if constexpr (KIND == ALPHA_FWD || KIND == GAMMA_INV) {
             if (apply_w) wj = p.w[KIND == ALPHA_FWD ? row : line];
@@ -405,15 +475,23 @@ __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *_
                 const int n = p_out + k * P + r * (N / R);
                 const C x = v[k * R + r];
                 if constexpr (KIND == GAMMA_FWD) {
-                    if (n != B) dst[t1_index<N, T>(line, n, row)] = x;
+                    if constexpr (NAT) {
+                        if (n != B) dst[((size_t)row * N + line) * N + n] = x;
+                    } else {
+                        if (n != B) dst[t1_index<N, T>(line, n, row)] = x;
+                    }
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    if (n != B) {
-                        const int sl = slot_code(n < B ? n : n - N, mp_line);
+                    if (n != B && !(NAT && q == B)) {
+                        const int sl = slot_code(n < B ? n : n - N, mp);
                         const int jj = (sl & 1) ? N - 1 - row : row;
                         dst[(size_t)(sl >> 1) * N + jj] = cscale(x, wj);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
-                    dst[t1_index<N, T>(row, line, n)] = x;
+                    if constexpr (NAT) {
+                        dst[((size_t)n * N + row) * N + q] = x;
+                    } else {
+                        dst[t1_index<N, T>(row, line, n)] = x;
+                    }
                 } else {
                     dst[((size_t)row * N + line) * N + n] = cscale(x, wj);
                 }
@@ -422,57 +500,85 @@ __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *_
     }
 }
 
+// Tile-blocked passes: input and output never alias.
 template <int N, int KIND, int SIGN, typename C>
+__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
+                                                     int apply_w) {
+    fft_pass<N, KIND, SIGN, C, false>(p, in, out, apply_w);
+}
+
+// Natural-layout passes: the gamma passes run in place (in == out).
+template <int N, int KIND, int SIGN, typename C>
+__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_nat(PlanView p, const C *in, C *out, int apply_w) {
+    fft_pass<N, KIND, SIGN, C, true>(p, in, out, apply_w);
+}
+
+template <int N, int KIND, int SIGN, typename C, bool NAT>
 hipError_t launch_kind(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
     using Ti = Tile<N, C>;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
-    const int nline = ALPHA ? N - 1 : N;
     // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
-    dim3 g(N / Ti::T, nline, p.nfunc);
-    hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+    if constexpr (NAT && ALPHA) {
+        using Nt = NatTile<Ti::T>;
+        dim3 g(N / Nt::TJ, N / Nt::TQ, p.nfunc);
+        hipLaunchKernelGGL((k_fft_nat<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+    } else if constexpr (NAT) {
+        dim3 g(N / Ti::T, N, p.nfunc);
+        hipLaunchKernelGGL((k_fft_nat<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+    } else {
+        dim3 g(N / Ti::T, ALPHA ? N - 1 : N, p.nfunc);
+        hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+    }
     return hipGetLastError();
 }
 
-template <int KIND, int SIGN, typename C>
+template <int KIND, int SIGN, typename C, bool NAT>
 hipError_t dispatch(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
     switch (p.N) {
-        case 2: return launch_kind<2, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 4: return launch_kind<4, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 8: return launch_kind<8, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 16: return launch_kind<16, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 32: return launch_kind<32, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 64: return launch_kind<64, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 128: return launch_kind<128, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 256: return launch_kind<256, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 512: return launch_kind<512, KIND, SIGN, C>(p, in, out, apply_w, s);
-        case 1024: return launch_kind<1024, KIND, SIGN, C>(p, in, out, apply_w, s);
+        case 2: return launch_kind<2, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 4: return launch_kind<4, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 8: return launch_kind<8, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 16: return launch_kind<16, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 32: return launch_kind<32, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 64: return launch_kind<64, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 128: return launch_kind<128, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 256: return launch_kind<256, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 512: return launch_kind<512, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 1024: return launch_kind<1024, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
+// Entry points.  With t1 == nullptr a pass uses the natural layout in the
+// grid buffer: the forward gamma pass then overwrites the input grid, the
+// inverse alpha pass stages in the output grid.
 template <typename C>
 hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s) {
-    return dispatch<GAMMA_FWD, +1, C>(p, grid, t1, 0, s);
+    if (!t1) return dispatch<GAMMA_FWD, +1, C, true>(p, grid, const_cast<C *>(grid), 0, s);
+    return dispatch<GAMMA_FWD, +1, C, false>(p, grid, t1, 0, s);
 }
 template <typename C>
-hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, C *S, bool apply_w, hipStream_t s) {
-    return dispatch<ALPHA_FWD, +1, C>(p, t1, S, (int)apply_w, s);
+hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, const C *grid, C *S, bool apply_w, hipStream_t s) {
+    if (!t1) return dispatch<ALPHA_FWD, +1, C, true>(p, grid, S, (int)apply_w, s);
+    return dispatch<ALPHA_FWD, +1, C, false>(p, t1, S, (int)apply_w, s);
 }
 template <typename C>
-hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, hipStream_t s) {
-    return dispatch<ALPHA_INV, -1, C>(p, S, t1, 0, s);
+hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, hipStream_t s) {
+    if (!t1) return dispatch<ALPHA_INV, -1, C, true>(p, S, grid, 0, s);
+    return dispatch<ALPHA_INV, -1, C, false>(p, S, t1, 0, s);
 }
 template <typename C>
 hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, hipStream_t s) {
-    return dispatch<GAMMA_INV, -1, C>(p, t1, grid, (int)apply_w, s);
+    if (!t1) return dispatch<GAMMA_INV, -1, C, true>(p, grid, grid, (int)apply_w, s);
+    return dispatch<GAMMA_INV, -1, C, false>(p, t1, grid, (int)apply_w, s);
 }
 
-#define SOFT_FFT_INSTANTIATE(C)                                                                         \
-    template hipError_t launch_fft_gamma_fwd<C>(const PlanView &, const C *, C *, hipStream_t);          \
-    template hipError_t launch_fft_alpha_fwd<C>(const PlanView &, const C *, C *, bool, hipStream_t);    \
-    template hipError_t launch_fft_alpha_inv<C>(const PlanView &, const C *, C *, hipStream_t);          \
+#define SOFT_FFT_INSTANTIATE(C)                                                                                \
+    template hipError_t launch_fft_gamma_fwd<C>(const PlanView &, const C *, C *, hipStream_t);                 \
+    template hipError_t launch_fft_alpha_fwd<C>(const PlanView &, const C *, const C *, C *, bool, hipStream_t); \
+    template hipError_t launch_fft_alpha_inv<C>(const PlanView &, const C *, C *, C *, hipStream_t);             \
     template hipError_t launch_fft_gamma_inv<C>(const PlanView &, const C *, C *, bool, hipStream_t);
 SOFT_FFT_INSTANTIATE(double2)
 SOFT_FFT_INSTANTIATE(float2)

@@ -102,7 +102,7 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // the pairs (matching head) in a 16-bit grid dimension.
 constexpr int kMaxFunctions = 65535;
 
-constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE;
+constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE | SOFT_INPLACE_OK;
 
 void free_plan(soft_plan_s *p) {
     if (!p) return;
@@ -310,7 +310,7 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     for (const Band &b : p->bands) {
         if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_FWD);
-        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, S, scaled, s);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_FWD);
     }
     for (const LaunchGroup &lg : p->groups) {
@@ -341,7 +341,7 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
     }
     for (const Band &b : p->bands) {
-        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, s);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_INV);
         if (e == hipSuccess) e = soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, s);
         if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_INV);
@@ -521,8 +521,11 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             p->s_total += (size_t)b.G * kSlots * b.N;
             b.funcs.push_back(f);
         }
-        for (const Band &b : p->bands)
-            p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
+        // The tile-blocked FFT intermediate; a SOFT_INPLACE_OK plan has none
+        // and stages the intermediate in the grid buffer instead.
+        if (!(flags & SOFT_INPLACE_OK))
+            for (const Band &b : p->bands)
+                p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
 
         // DWT launch groups: in a plan of several bands, all bands with
         // 2B <= 256 share one launch (with the 2B = 256 shapes); every other
@@ -642,7 +645,7 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
 
         const size_t rec_rows = (size_t)p->rows_total + soft::kPadRows;
         if (hipMalloc(&p->tables, total) != hipSuccess || hipMalloc(&p->S, p->s_total * p->csize) != hipSuccess ||
-            hipMalloc(&p->t1, p->t1_elems * p->csize) != hipSuccess ||
+            (p->t1_elems && hipMalloc(&p->t1, p->t1_elems * p->csize) != hipSuccess) ||
             hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
             hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->seed, p->seed_total * sizeof(double)) != hipSuccess) {
@@ -750,7 +753,8 @@ int soft_plan_sizes(soft_plan_t p, size_t *grid_elems, size_t *coeff_elems, size
 int soft_plan_describe(soft_plan_t p, char *buf, size_t len) {
     if (!p || !buf || len == 0) return SOFT_ERR_INVALID;
     std::string d = "{\"precision\": " + std::to_string(p->precision) + ", \"functions\": " + std::to_string(p->n) +
-                    ", \"workspace_bytes\": " + std::to_string(p->ws_bytes) + ", \"bands\": [";
+                    ", \"workspace_bytes\": " + std::to_string(p->ws_bytes) +
+                    ", \"inplace_ok\": " + ((p->flags & SOFT_INPLACE_OK) ? "true" : "false") + ", \"bands\": [";
     for (size_t bi = 0; bi < p->bands.size(); ++bi)
         d += std::string(bi ? ", " : "") + "{\"B\": " + std::to_string(p->bands[bi].B) +
              ", \"functions\": " + std::to_string(p->bands[bi].funcs.size()) + "}";

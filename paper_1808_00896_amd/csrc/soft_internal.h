@@ -165,13 +165,16 @@ struct PlanView {
 };
 
 // FFT stage (separation of variables, Sect. 2.4), one launch per band; t1 is
-// the band's intermediate, [nfunc][N^3].
+// the band's tile-blocked intermediate, [nfunc][N^3].  With t1 == nullptr the
+// passes keep the intermediate in grid order inside the grid buffer: the
+// forward gamma pass overwrites the input grid in place and the inverse alpha
+// pass stages in the output grid.
 template <typename C>
 hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s);
 template <typename C>
-hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, C *S, bool apply_w, hipStream_t s);
+hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, const C *grid, C *S, bool apply_w, hipStream_t s);
 template <typename C>
-hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, hipStream_t s);
+hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, hipStream_t s);
 template <typename C>
 hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, hipStream_t s);
 

@@ -25,6 +25,7 @@ SOFT_FP32 = 1
 SOFT_FP32_SPLIT = 2
 PRECISIONS = {"fp64": SOFT_FP64, "fp32": SOFT_FP32, "fp32_split": SOFT_FP32_SPLIT}
 SOFT_PLAN_TUNE = 1
+SOFT_INPLACE_OK = 2
 SOFT_OK = 0
 SOFT_ERR_INVALID = -1
 SOFT_ERR_UNSUPPORTED = -2
@@ -250,6 +251,10 @@ def _precision(precision):
     return int(precision)
 
 
+def _flags(tune, inplace_ok):
+    return (SOFT_PLAN_TUNE if tune else 0) | (SOFT_INPLACE_OK if inplace_ok else 0)
+
+
 class _PlanBase:
     """Shape and dtype checks shared by Plan and UnevenPlan."""
 
@@ -277,7 +282,8 @@ class _PlanBase:
 
     # transforms -----------------------------------------------------------
     def forward(self, grid, out=None):
-        """FSOFT: coefficients of the sampled function(s)."""
+        """FSOFT: coefficients of the sampled function(s).  An ``inplace_ok``
+        plan overwrites ``grid`` with scratch."""
         g = self._checked(grid, self.grid_shape(), "grid")
         c = self._out(out, self.coeff_shape(), "out")
         soft_forward(self.handle, g, c)
@@ -298,7 +304,8 @@ class _PlanBase:
         return g
 
     def adjoint_inverse(self, grid, out=None):
-        """I^H = V^-1 F W^-1, adjoint of inverse."""
+        """I^H = V^-1 F W^-1, adjoint of inverse.  An ``inplace_ok`` plan
+        overwrites ``grid`` with scratch."""
         g = self._checked(grid, self.grid_shape(), "grid")
         c = self._out(out, self.coeff_shape(), "out")
         soft_adjoint_inverse(self.handle, g, c)
@@ -336,10 +343,11 @@ class _PlanBase:
 
 class Plan(_PlanBase):
     @classmethod
-    def _borrow(cls, handle, B, batch, device, precision):
+    def _borrow(cls, handle, B, batch, device, precision, inplace_ok=False):
         """A Plan over a handle owned elsewhere (closing it does nothing)."""
         self = cls.__new__(cls)
         self._init_device(device, precision)
+        self.inplace_ok = inplace_ok
         self.handle = handle
         self._owned = False
         self.B, self.batch, self.N = B, batch, 2 * B
@@ -357,13 +365,17 @@ class Plan(_PlanBase):
     Grids are tensors of shape [batch, 2B, 2B, 2B] (or [2B, 2B, 2B] when
     batch == 1); coefficient vectors are [batch, B(4B^2-1)/3] (or flat).
     ``precision`` is "fp64" (complex128), "fp32" or "fp32_split" (complex64).
+    ``tune`` times the DWT launch shapes at plan time; ``inplace_ok`` drops
+    the plan's FFT intermediate and stages it in the grid tensors instead
+    (forward and adjoint_inverse then overwrite their input grid).
     Calls are asynchronous on the current torch stream.
     """
 
-    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False):
+    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False, inplace_ok=False):
         self._init_device(device, precision)
+        self.inplace_ok = bool(inplace_ok)
         with torch.cuda.device(self.device):
-            self.handle = soft_plan(B, batch, self.precision, SOFT_PLAN_TUNE if tune else 0)
+            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok))
         self.B, self.batch, self.N = B, batch, 2 * B
         self.nc = num_coeffs(B)
 
@@ -383,11 +395,12 @@ class UnevenPlan(_PlanBase):
     where each starts, and ``split_grids`` / ``split_coeffs`` return views.
     """
 
-    def __init__(self, Bs, device=None, precision="fp64", tune=False):
+    def __init__(self, Bs, device=None, precision="fp64", tune=False, inplace_ok=False):
         self._init_device(device, precision)
+        self.inplace_ok = bool(inplace_ok)
         self.Bs = [int(b) for b in Bs]
         with torch.cuda.device(self.device):
-            self.handle = soft_plan_uneven(self.Bs, self.precision, SOFT_PLAN_TUNE if tune else 0)
+            self.handle = soft_plan_uneven(self.Bs, self.precision, _flags(tune, inplace_ok))
         self.grid_offsets, self.coeff_offsets = soft_plan_offsets(self.handle, len(self.Bs))
 
     def grid_shape(self):
@@ -410,17 +423,19 @@ class MatchPlan:
     """Rotational-matching head for ``n`` pairs of functions on the sphere at
     bandwidth ``B``: a, b are [n, B^2] (or [B^2] when n == 1) complex
     tensors, coefficient (l, m) at l^2 + m + l.  ``plan`` is the owned
-    soft.Plan of the n correlation functions (for backward passes)."""
+    soft.Plan of the n correlation functions (for backward passes);
+    ``inplace_ok`` makes it a plan without an FFT intermediate of its own."""
 
-    def __init__(self, B, n=1, device=None, precision="fp64", tune=False):
+    def __init__(self, B, n=1, device=None, precision="fp64", tune=False, inplace_ok=False):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.precision = _precision(precision)
         self.dtype = torch.complex128 if self.precision == SOFT_FP64 else torch.complex64
         with torch.cuda.device(self.device):
-            self.handle = soft_match_plan(B, n, self.precision, SOFT_PLAN_TUNE if tune else 0)
+            self.handle = soft_match_plan(B, n, self.precision, _flags(tune, inplace_ok))
         self.B, self.n = B, n
-        self.plan = Plan._borrow(soft_match_plan_soft(self.handle), B, n, self.device, self.precision)
+        self.plan = Plan._borrow(soft_match_plan_soft(self.handle), B, n, self.device, self.precision,
+                                 bool(inplace_ok))
 
     def sh_shape(self):
         return (self.B * self.B,) if self.n == 1 else (self.n, self.B * self.B)
