@@ -137,11 +137,11 @@ def per_stage(stage_ms, Bs, steps, prec="fp64"):
 TUNE = True  # plans time their DWT launch shapes at creation (outside the timed region)
 
 
-def make_plan(Bs, prec, uniform):
+def make_plan(Bs, prec, uniform, inplace=False):
     from paper_1808_00896_amd import soft
     if uniform:
-        return soft.Plan(Bs[0], batch=len(Bs), precision=prec, tune=TUNE)
-    return soft.UnevenPlan(Bs, precision=prec, tune=TUNE)
+        return soft.Plan(Bs[0], batch=len(Bs), precision=prec, tune=TUNE, inplace_ok=inplace)
+    return soft.UnevenPlan(Bs, precision=prec, tune=TUNE, inplace_ok=inplace)
 
 
 def shapes_of(plan):
@@ -149,9 +149,15 @@ def shapes_of(plan):
             for l in plan.describe()["dwt_launches"]]
 
 
+def percentiles(ms):
+    q = np.percentile(np.asarray(ms), [10, 50, 90])
+    return {"p10": round(float(q[0]), 4), "median": round(float(q[1]), 4), "p90": round(float(q[2]), 4)}
+
+
 def timed_steps(plan, c, steps, warmup):
     """Run warmup + timed steps of inverse then forward; returns (seconds,
-    stage timers, grid, round-tripped coefficients)."""
+    stage timers, grid, round-tripped coefficients, per-step ms from HIP
+    events recorded between the steps on the launch stream)."""
     import torch
     from paper_1808_00896_amd import soft
     grid = torch.empty(plan.grid_shape(), dtype=plan.dtype, device="cuda")
@@ -166,15 +172,19 @@ def timed_steps(plan, c, steps, warmup):
     torch.cuda.synchronize()
     soft.soft_plan_stage_times(plan.handle, reset=True)
     soft.soft_plan_set_timing(plan.handle, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         step()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     soft.soft_plan_set_timing(plan.handle, False)
     st = soft.soft_plan_stage_times(plan.handle, reset=True)
-    return t1 - t0, st, grid, c2
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return t1 - t0, st, grid, c2, step_ms
 
 
 def relerr_dev(a, b, chunk=1 << 27):
@@ -191,22 +201,27 @@ def relerr_dev(a, b, chunk=1 << 27):
     return num / den
 
 
-def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=False):
+def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=False, inplace=False):
     """Time `steps` fwd+inv of the functions Bs in precision prec.
 
     ref: dict with the FP64 path's grid and coefficients on the same inputs
     (flat or batched like this plan), for the error report.  keep_ref returns
-    this leg's own grid for use as such a reference.
+    this leg's own grid for use as such a reference.  inplace: a
+    SOFT_INPLACE_OK plan (its forward overwrites the grid it reads).
     """
     import torch
-    plan = make_plan(Bs, prec, uniform)
+    plan = make_plan(Bs, prec, uniform, inplace)
     dt = plan.dtype
     c = torch.from_numpy(c_host).to("cuda").to(dt).reshape(plan.coeff_shape())
-    el, st, grid, c2 = timed_steps(plan, c, steps, warmup)
+    el, st, grid, c2, step_ms = timed_steps(plan, c, steps, warmup)
+    if inplace:
+        plan.inverse(c, out=grid)  # the timed forward overwrote it
     n = len(Bs)
     res = {"functions": n, "precision": prec, "steps": steps,
            "value": round(steps * n / el, 3), "unit": "function fwd+inv/s",
            "ms_per_step": round(el / steps * 1e3, 4),
+           "step_ms": percentiles(step_ms),
+           "workspace_bytes": plan.workspace_bytes(),
            "round_trip_err": relerr_dev(c2, c),
            "stages": per_stage(st, Bs, steps, prec),
            "dwt_shapes": shapes_of(plan)}
@@ -215,6 +230,8 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=Fa
         res["inverse_err_vs_fp64"] = relerr_dev(grid, ref["grid"])
         # forward of the FP64 path's grid, rounded to this precision
         g_in = ref["grid"].to(dt).reshape(plan.grid_shape())
+        if inplace:
+            g_in = g_in.clone()  # the forward overwrites its input
         plan.forward(g_in, out=c2)
         del g_in
         res["forward_err_vs_fp64"] = relerr_dev(c2, ref["coeffs"])
@@ -297,6 +314,42 @@ def cpu_baseline(B, c_host, budget_s=12.0, max_reps=3):
             "seconds": round(t, 2)}
 
 
+def ceilings(copy_bytes):
+    """What the chip sustains outside this library, for reading the roofline
+    fractions: a plain device copy of `copy_bytes` (torch), and FP64 / FP32
+    GEMMs of 8192^3 through the vendor BLAS (torch.matmul), best of several."""
+    import torch
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = 1e30
+        for _ in range(reps):
+            s.record()
+            fn()
+            e.record()
+            e.synchronize()
+            t = min(t, s.elapsed_time(e))
+        return t
+
+    n = copy_bytes // 16
+    a = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    ms = best(lambda: b.copy_(a), 10)
+    out = {"copy_bytes": 2 * n * 16, "copy_GB/s": round(2 * n * 16 / ms / 1e6, 1)}
+    del a, b
+    k = 8192
+    for name, dt in (("dgemm", torch.float64), ("sgemm", torch.float32)):
+        x = torch.randn(k, k, dtype=dt, device="cuda")
+        y = torch.randn(k, k, dtype=dt, device="cuda")
+        ms = best(lambda: torch.matmul(x, y), 5)
+        out[f"{name}_TFLOP/s"] = round(2 * k ** 3 / ms / 1e9, 1)
+        del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy(gib=1.0):
     """A plain device copy of known size, for scaling the rocprofv3 byte counters."""
     import torch
@@ -375,6 +428,7 @@ def main():
         "stages": main_leg["stages"],
         "dwt_shapes": main_leg["dwt_shapes"],
         "round_trip_err": main_leg["round_trip_err"],
+        "step_ms": main_leg["step_ms"],
     }
     log(f"B={B}: {value:.1f} fwd+inv/s, round trip {main_leg['round_trip_err']:.2e}")
 
@@ -414,6 +468,10 @@ def main():
             r, _ = run_leg([512], prec, args.b512_steps, 1, c5, ref=ref5)
             legs[f"B512_{prec}"] = r
         legs["B512_fp32_split"]["speedup_vs_fp64"] = round(legs["B512_fp32_split"]["value"] / r5["value"], 3)
+        log("B=512 FP64, SOFT_INPLACE_OK plan")
+        r, _ = run_leg([512], "fp64", args.b512_steps, 1, c5, ref=ref5, inplace=True)
+        r["speedup_vs_fp64"] = round(r["value"] / r5["value"], 3)
+        legs["B512_fp64_inplace"] = r
         del ref5
         torch.cuda.empty_cache()
 
@@ -440,6 +498,9 @@ def main():
         legs.update(match_leg(args.match_steps))
 
     out["legs"] = legs
+    if not args.quick:
+        log("ceilings")
+        out["ceilings"] = ceilings(16 * (2 * B) ** 3)
     if args.calibrate_copy:
         out["copy_calibration_bytes"] = calibrate_copy()
 

@@ -6,8 +6,11 @@
 // dropped on the way in and written as zero on the way out).
 //
 // Each direction is two HBM passes of batched 1-D FFTs over N points:
-//   gamma pass:  rows along k (contiguous) <-> t1(j, q, i)   (q = m' mod N)
-//   alpha pass:  rows along i (contiguous in t1) <-> S[group slot][j]
+//   gamma pass:  rows along k (contiguous) <-> u(j, q, i)   (q = m' mod N)
+//   alpha pass:  rows along i (runs of T in u) <-> S[group slot][j]
+// where u, the intermediate, is the plan's own tile-blocked t1 or, for plans
+// that may use the grid buffer as scratch, a blocked layout inside the grid
+// (see u_index).
 // A block transforms T independent length-N sequences that are neighbours
 // along the axis contiguous in the *other* layout, so every global access
 // moves runs of T elements (128 bytes or more from N = 512 up) and the
@@ -252,61 +255,33 @@ __device__ __forceinline__ void get_stage(C (&v)[Shape<N>::E], const C *lds, int
     }
 }
 
-// Offset of t1(j, q, i) in the tile-blocked intermediate (see k_fft).
-template <int N, int T>
-__device__ __forceinline__ size_t t1_index(int j, int q, int i) {
-    return ((size_t)((j / T) * N + q) * T + (j % T)) * N + i;
+// Offset of the intermediate element u(j, q, i) (q = m' mod N after the
+// gamma pass, i the alpha sample), in one of two layouts:
+//   t1 (plan-owned, tile-blocked by T):  ((j/T * N + q) * T + j%T) * N + i
+//   in-grid (SOFT_INPLACE_OK plans): inside the grid buffer, where the T
+//     rows i0..i0+T-1 of beta sample j (the elements one gamma block reads)
+//     hold that block's outputs in the order L = q * T + i%T:
+//       ((i0 + L / N) * N + j) * N + L % N,   i0 = i - i%T.
+// In both, an alpha block reads or writes runs of T elements (all of one
+// contiguous T*N run for t1), and a gamma block only touches its own T rows
+// in the in-grid layout, so that pass is safe in place.
+template <int N, int T, bool INGRID>
+__device__ __forceinline__ size_t u_index(int j, int q, int i) {
+    if constexpr (INGRID) {
+        const int L = q * T + i % T;
+        return ((size_t)(i - i % T + L / N) * N + j) * N + L % N;
+    } else {
+        return ((size_t)((j / T) * N + q) * T + (j % T)) * N + i;
+    }
 }
 
 // Pass kinds: where a block's T sequences come from and go to.
 enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
 
-// Lane order of a side of a pass: ROWS puts a sequence's elements on
-// neighbouring lanes (the side is contiguous along the sequence); TILES puts
-// the T sequences of the block on neighbouring lanes (the side is contiguous
-// across sequences); TILES_J is TILES for the natural-layout alpha passes,
-// whose T = TJ x TQ sequences are ordered q-fastest, with the lanes walking
-// them j-fastest (the S side of those passes is contiguous along j).
-enum LaneOrder { ROWS = 0, TILES = 1, TILES_J = 2 };
-
-// The default layout goes through the tile-blocked t1; the natural layout
-// (NAT) keeps the intermediate in grid order [i][j][q], in the grid buffer
-// itself: the gamma passes then work in place, and the alpha passes take a
-// TJ x TQ tile of (j, q).
-template <int KIND, bool NAT>
-constexpr int order_in() {
-    if constexpr (NAT) return KIND == ALPHA_FWD ? TILES : (KIND == ALPHA_INV ? TILES_J : ROWS);
-    return KIND == ALPHA_INV || KIND == GAMMA_INV ? TILES : ROWS;
-}
-template <int KIND, bool NAT>
-constexpr int order_out() {
-    if constexpr (NAT) return KIND == ALPHA_FWD ? TILES_J : (KIND == ALPHA_INV ? TILES : ROWS);
-    return KIND == GAMMA_FWD || KIND == ALPHA_FWD ? TILES : ROWS;
-}
-
-// Natural-layout alpha tile: TQ = 2^floor(log2(T)/2) frequencies q by
-// TJ = T / TQ samples j.
-template <int T>
-struct NatTile {
-    static constexpr int TQ = 1 << (ilog2(T) / 2);
-    static constexpr int TJ = T / TQ;
-};
-
-// (sequence, position) of lane tid for a side with the given order.
-template <int ORDER, int T, int P, int TJ, int TQ>
-__device__ __forceinline__ void lane_seq(int tid, int &t, int &pos) {
-    if constexpr (ORDER == ROWS) {
-        t = tid / P;
-        pos = tid % P;
-    } else if constexpr (ORDER == TILES) {
-        t = tid % T;
-        pos = tid / T;
-    } else {
-        const int u = tid % T;
-        t = (u % TJ) * TQ + u / TJ;
-        pos = tid / T;
-    }
-}
+template <int KIND>
+constexpr bool transposed_in() { return KIND == ALPHA_INV || KIND == GAMMA_INV; }
+template <int KIND>
+constexpr bool transposed_out() { return KIND == GAMMA_FWD || KIND == ALPHA_FWD; }
 
 // Block -> (tile, line, batch).  Consecutive logical blocks are placed on the
 // same XCD (the hardware deals blocks round-robin over the 8 XCDs), so the
@@ -335,74 +310,59 @@ __device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int
 
 // One pass over the functions of one band (blockIdx.z = index within the
 // band; t1 holds one N^3 intermediate per such index).  Element addresses:
-//   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out t1(j, q, i)
-//   ALPHA_FWD: block (j-tile, q): in t1(j, q, i),             out S[slot*N + j']
-//   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],           out t1(j, q, i)
-//   GAMMA_INV: block (i-tile, j): in t1(j, q, i),              out grid[(i*N + j)*N + k]
-// with t1 blocked by the tile height T: t1(j, q, i) at
-// ((j/T * N + q) * T + j%T) * N + i.  An alpha block then reads or writes one
-// contiguous run of T*N elements, and a gamma block's runs of T elements for
-// the N values of q stay within one window of T*N^2 elements (instead of
-// striding over all N^3).
-//
-// NAT: the intermediate sits in grid order, u[(i*N + j)*N + q], inside the
-// grid buffer of the function.  The gamma blocks (i-tile, j) read and write
-// the same T rows (every load of a block is consumed before its first
-// barrier, so the pass is safe in place); the alpha blocks (j-tile, q-tile)
-// move runs of TQ elements on the grid side and TJ on the S side.  The
-// sequences at the +-B frequency q = B run like the others (so that every
-// sequence sees the same arithmetic as in the tile-blocked passes): the
-// forward drops them, the inverse stores them where its gamma pass writes
-// the final values.
-template <int N, int KIND, int SIGN, typename C, bool NAT>
+//   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out u(j, q, i)
+//   ALPHA_FWD: block (j-tile, q): in u(j, q, i),               out S[slot*N + j']
+//   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],           out u(j, q, i)
+//   GAMMA_INV: block (i-tile, j): in u(j, q, i),               out grid[(i*N + j)*N + k]
+// with u the intermediate in the t1 or the in-grid layout (u_index).  With
+// t1, an alpha block then reads or writes one contiguous run of T*N
+// elements, and a gamma block's runs of T elements for the N values of q
+// stay within one window of T*N^2 elements (instead of striding over all
+// N^3).  In the grid, every gamma block reads and writes only its own T
+// rows, and all its loads are consumed before its first barrier (or, for
+// N <= 16, by the one thread that owns the sequence), so in == out is safe.
+template <int N, int KIND, int SIGN, typename C, bool INGRID>
 __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int apply_w) {
     using Sh = Shape<N>;
     constexpr int T = Tile<N, C>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
     constexpr int B = N / 2;
     constexpr int LAST = NSTG - 1;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
-    constexpr bool NAT_ALPHA = NAT && ALPHA;
-    constexpr int TQ = NAT_ALPHA ? NatTile<T>::TQ : 1, TJ = NAT_ALPHA ? NatTile<T>::TJ : T;
     __shared__ C lds[Tile<N, C>::LDS];
     const C *tw = twiddles<C>(p, SIGN);
 
-    // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1),
-    // q-tiles for natural-layout alpha passes (N / TQ).
-    const BlockPos bp = NAT_ALPHA ? block_pos(N / TJ, N / TQ) : block_pos(N / T, ALPHA ? N - 1 : N);
+    // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
+    const BlockPos bp = block_pos(N / T, ALPHA ? N - 1 : N);
     const int tile = bp.tile;
-    const int line = NAT_ALPHA ? bp.line : (ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line);
+    const int line = ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line;
     const size_t N3 = (size_t)N * N * N;
     const FuncInfo fi = p.funcs[p.band_funcs[bp.batch]];
     const C *src;
     C *dst;
+    const size_t u_off = INGRID ? (size_t)fi.grid_off : bp.batch * N3;  // the intermediate of this function
     if constexpr (KIND == GAMMA_FWD) {
         src = in + fi.grid_off;
-        dst = out + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
+        dst = out + u_off;
     } else if constexpr (KIND == ALPHA_FWD) {
-        src = in + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
+        src = in + u_off;
         dst = out + fi.s_off;
     } else if constexpr (KIND == ALPHA_INV) {
         src = in + fi.s_off;
-        dst = out + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
+        dst = out + u_off;
     } else {
-        src = in + (NAT ? (size_t)fi.grid_off : bp.batch * N3);
+        src = in + u_off;
         dst = out + fi.grid_off;
     }
     const int tid = threadIdx.x;
-
-    // Sequence t of the block: row (i for gamma, j for alpha) and q (alpha).
-    auto seq_row = [&](int t) { return NAT_ALPHA ? tile * TJ + t / TQ : tile * T + t; };
-    auto seq_q = [&](int t) { return NAT_ALPHA ? line * TQ + t % TQ : line; };
+    const int mp_line = line < B ? line : line - N;  // m' of an alpha-pass block
 
     C v[E];
     // ---- stage 0 inputs from HBM: element b + r*N/R ----
-    int t_in, p_in;
-    lane_seq<order_in<KIND, NAT>(), T, P, TJ, TQ>(tid, t_in, p_in);
+    const int t_in = transposed_in<KIND>() ? tid % T : tid / P;
+    const int p_in = transposed_in<KIND>() ? tid / T : tid % P;
     {
         constexpr int R = radix_of<N, 0>(), BPT = N / R / P;
-        const int row = seq_row(t_in);  // i (gamma) or j (alpha)
-        const int q = seq_q(t_in);
-        const int mp = q < B ? q : q - N;  // m' of an alpha-pass sequence
+        const int row = tile * T + t_in;  // i (gamma) or j (alpha)
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
 #pragma unroll
@@ -412,27 +372,17 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                 if constexpr (KIND == GAMMA_FWD) {
                     x = src[((size_t)row * N + line) * N + n];
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    if constexpr (NAT) {
-                        x = src[((size_t)n * N + row) * N + q];  // q = B: loaded, transformed, dropped
-                    } else {
-                        x = src[t1_index<N, T>(row, line, n)];
-                    }
+                    x = src[u_index<N, T, INGRID>(row, line, n)];
                 } else if constexpr (KIND == ALPHA_INV) {
                     if (n == B) {
                         x = mk<C>(0.0, 0.0);
                     } else {
-                        // q = B (natural layout only) reads a valid slot; its
-                        // sequence lands where the gamma pass writes last.
-                        const int sl = slot_code(n < B ? n : n - N, NAT && q == B ? B - 1 : mp);
+                        const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
                         x = src[(size_t)(sl >> 1) * N + jj];
                     }
                 } else {
-                    if constexpr (NAT) {
-                        x = n == B ? mk<C>(0.0, 0.0) : src[((size_t)row * N + line) * N + n];
-                    } else {
-                        x = n == B ? mk<C>(0.0, 0.0) : src[t1_index<N, T>(line, n, row)];
-                    }
+                    x = n == B ? mk<C>(0.0, 0.0) : src[u_index<N, T, INGRID>(line, n, row)];
                 }
                 v[k * R + r] = x;
             }
@@ -453,7 +403,8 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
             put_stage<N, 1, C>(v, lds, t, pp);
             __syncthreads();
         }
-        lane_seq<order_out<KIND, NAT>(), T, P, TJ, TQ>(tid, t_out, p_out);
+        t_out = transposed_out<KIND>() ? tid % T : t;
+        p_out = transposed_out<KIND>() ? tid / T : pp;
         get_stage<N, LAST, C>(v, lds, t_out, p_out);
         run_stage<N, LAST, SIGN, C>(v, p_out, tw);
     }
@@ -461,9 +412,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     // ---- last stage outputs to HBM: element b + r*N/R ----
     {
         constexpr int R = radix_of<N, LAST>(), BPT = N / R / P;
-        const int row = seq_row(t_out);
-        const int q = seq_q(t_out);
-        const int mp = q < B ? q : q - N;
+        const int row = tile * T + t_out;
         double wj = 1.0;
         if constexpr (KIND == ALPHA_FWD || KIND == GAMMA_INV) {
             if (apply_w) wj = p.w[KIND == ALPHA_FWD ? row : line];
@@ -475,23 +424,15 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                 const int n = p_out + k * P + r * (N / R);
                 const C x = v[k * R + r];
                 if constexpr (KIND == GAMMA_FWD) {
-                    if constexpr (NAT) {
-                        if (n != B) dst[((size_t)row * N + line) * N + n] = x;
-                    } else {
-                        if (n != B) dst[t1_index<N, T>(line, n, row)] = x;
-                    }
+                    if (n != B) dst[u_index<N, T, INGRID>(line, n, row)] = x;
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    if (n != B && !(NAT && q == B)) {
-                        const int sl = slot_code(n < B ? n : n - N, mp);
+                    if (n != B) {
+                        const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
                         dst[(size_t)(sl >> 1) * N + jj] = cscale(x, wj);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
-                    if constexpr (NAT) {
-                        dst[((size_t)n * N + row) * N + q] = x;
-                    } else {
-                        dst[t1_index<N, T>(row, line, n)] = x;
-                    }
+                    dst[u_index<N, T, INGRID>(row, line, n)] = x;
                 } else {
                     dst[((size_t)row * N + line) * N + n] = cscale(x, wj);
                 }
@@ -500,60 +441,55 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     }
 }
 
-// Tile-blocked passes: input and output never alias.
+// Intermediate in the plan's t1: input and output never alias.
 template <int N, int KIND, int SIGN, typename C>
 __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
                                                      int apply_w) {
     fft_pass<N, KIND, SIGN, C, false>(p, in, out, apply_w);
 }
 
-// Natural-layout passes: the gamma passes run in place (in == out).
+// Intermediate in the grid buffer: the gamma passes run in place (in == out).
 template <int N, int KIND, int SIGN, typename C>
-__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_nat(PlanView p, const C *in, C *out, int apply_w) {
+__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_ingrid(PlanView p, const C *in, C *out, int apply_w) {
     fft_pass<N, KIND, SIGN, C, true>(p, in, out, apply_w);
 }
 
-template <int N, int KIND, int SIGN, typename C, bool NAT>
+template <int N, int KIND, int SIGN, typename C, bool INGRID>
 hipError_t launch_kind(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
     using Ti = Tile<N, C>;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
+    const int nline = ALPHA ? N - 1 : N;
     // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
-    if constexpr (NAT && ALPHA) {
-        using Nt = NatTile<Ti::T>;
-        dim3 g(N / Nt::TJ, N / Nt::TQ, p.nfunc);
-        hipLaunchKernelGGL((k_fft_nat<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
-    } else if constexpr (NAT) {
-        dim3 g(N / Ti::T, N, p.nfunc);
-        hipLaunchKernelGGL((k_fft_nat<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
-    } else {
-        dim3 g(N / Ti::T, ALPHA ? N - 1 : N, p.nfunc);
+    dim3 g(N / Ti::T, nline, p.nfunc);
+    if constexpr (INGRID)
+        hipLaunchKernelGGL((k_fft_ingrid<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+    else
         hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
-    }
     return hipGetLastError();
 }
 
-template <int KIND, int SIGN, typename C, bool NAT>
+template <int KIND, int SIGN, typename C, bool INGRID>
 hipError_t dispatch(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
     switch (p.N) {
-        case 2: return launch_kind<2, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 4: return launch_kind<4, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 8: return launch_kind<8, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 16: return launch_kind<16, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 32: return launch_kind<32, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 64: return launch_kind<64, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 128: return launch_kind<128, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 256: return launch_kind<256, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 512: return launch_kind<512, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
-        case 1024: return launch_kind<1024, KIND, SIGN, C, NAT>(p, in, out, apply_w, s);
+        case 2: return launch_kind<2, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 4: return launch_kind<4, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 8: return launch_kind<8, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 16: return launch_kind<16, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 32: return launch_kind<32, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 64: return launch_kind<64, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 128: return launch_kind<128, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 256: return launch_kind<256, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 512: return launch_kind<512, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 1024: return launch_kind<1024, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// Entry points.  With t1 == nullptr a pass uses the natural layout in the
-// grid buffer: the forward gamma pass then overwrites the input grid, the
-// inverse alpha pass stages in the output grid.
+// Entry points.  With t1 == nullptr the intermediate lives in the grid
+// buffer: the forward gamma pass overwrites the input grid, the inverse
+// alpha pass stages in the output grid.
 template <typename C>
 hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s) {
     if (!t1) return dispatch<GAMMA_FWD, +1, C, true>(p, grid, const_cast<C *>(grid), 0, s);

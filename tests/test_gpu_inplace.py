@@ -1,10 +1,11 @@
 """Plans made with SOFT_INPLACE_OK, through the C-ABI.
 Such a plan holds no FFT intermediate of its own: the inverse stages it in
-its output grid and the forward in its (overwritten) input grid, in grid
-order.  The natural-layout FFT passes do the same arithmetic in the same
-order as the tile-blocked ones, so every transform must equal a plan without
-the flag bit for bit, at every FFT length and tile shape (2B = 2 ... 1024,
-complex128 and complex64), and the oracle to the FP64 bar.
+its output grid and the forward in its (overwritten) input grid, each gamma
+block in the rows it reads.  The FFT passes do the same arithmetic in the
+same order as with the plan-owned intermediate (only the addresses of the
+intermediate differ), so every transform must equal a plan without the flag
+bit for bit, at every FFT length and tile height (2B = 2 ... 1024, complex128
+and complex64), and the oracle to the FP64 bar.
 Inputs are seeded synthetic data from paper_1808_00896_amd.inputs.
 """
 
