@@ -156,8 +156,9 @@ int soft_plan_sizes(soft_plan_t plan, size_t *grid_elems, size_t *coeff_elems,
 
 /*
  * soft_plan_describe -- a one-line JSON description of the plan (bands,
- * functions, workspace bytes, and per DWT launch its largest 2B, work items,
- * forward and inverse launch shapes and whether they were tuned), written to
+ * functions, workspace bytes, whether it was made with SOFT_INPLACE_OK, and
+ * per DWT launch its largest 2B, work items, forward and inverse launch
+ * shapes and whether they were tuned), written to
  * buf as a NUL-terminated string truncated to len - 1 characters.
  * Returns SOFT_OK or SOFT_ERR_INVALID (NULL plan or buf, len == 0).
  */
@@ -290,9 +291,11 @@ typedef struct soft_match_s *soft_match_t;
  * soft_match_plan -- plan the head for n pairs at bandwidth B.
  *   B, precision, flags as for soft_plan; n >= 1 pairs.
  *   out  receives the handle; unchanged on error.
- * Owns a soft_plan of n functions of bandwidth B, one set of n coefficient
- * vectors, and the argmax partial results (16 bytes per pair and scanned
- * block).  Synchronous.  Returns as soft_plan.
+ * Owns a soft_plan of n functions of bandwidth B (made with the same flags:
+ * with SOFT_INPLACE_OK it holds no FFT intermediate, and soft_adjoint_inverse
+ * on it overwrites its input grid), one set of n coefficient vectors, and the
+ * argmax partial results (16 bytes per pair and scanned block).
+ * Synchronous.  Returns as soft_plan.
  */
 int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out);
 
