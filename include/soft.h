@@ -67,10 +67,12 @@ typedef struct soft_plan_s *soft_plan_t;
  *                    the FP32 partial sums (at most 32 beta samples in the
  *                    forward, 16 degrees in the inverse) in FP64.
  *   SOFT_FP32_SPLIT  as SOFT_FP32, but d is split into an FP32 head and an
- *                    FP32 tail (d = hi + lo to about 2^-48 relative), both
- *                    contracted, so the DWT error is that of FP32 data rather
- *                    than of FP32 d; relative error about 1e-6 or below at
- *                    B <= 512 for data of unit scale.
+ *                    FP32 tail (d = hi + lo to about 2^-48 relative); the
+ *                    head is contracted on FP32 matrix cores and the tail
+ *                    (about 2^-24 of d) on bf16 matrix cores, which keeps d
+ *                    to about 2^-32 relative, so the DWT error is that of
+ *                    FP32 data rather than of FP32 d; relative error about
+ *                    1e-6 or below at B <= 512 for data of unit scale.
  */
 typedef enum {
     SOFT_FP64 = 0,

@@ -28,7 +28,9 @@
 //   inverse: 16 samples x 4 degrees (A) times 4 degrees x 16 columns (B, the
 //            coefficients) reduce over degrees inside each wave.
 // In the FP32 modes the partial sums over one k-slot (16 beta samples) or one
-// panel (16 degrees) are FP32 and are combined in FP64.
+// panel (16 degrees) are FP32 and are combined in FP64.  The split mode's
+// tail products (d - hi(d), about 2^-24 of d) run on bf16 matrix cores, four
+// FP32 k steps per v_mfma_f32_16x16x16_bf16.
 #include "soft_internal.h"
 
 namespace soft {
@@ -36,6 +38,20 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+
+// Four values as the bf16 operand of v_mfma_f32_16x16x16_bf16 (round to
+// nearest even).  The split mode contracts the tail of d, about 2^-24 of d,
+// on bf16 matrix cores: rounding tail and data to bf16 changes the tail's
+// product by about 2^-8 of itself, about 2^-32 of the total.
+__device__ __forceinline__ v4bf bf4(float a, float b, float c, float d) {
+    v4bf r;
+    r[0] = (__bf16)a;
+    r[1] = (__bf16)b;
+    r[2] = (__bf16)c;
+    r[3] = (__bf16)d;
+    return r;
+}
 
 
 struct DD {
@@ -293,9 +309,10 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 #pragma unroll
             for (int r = 0; r < 4; ++r) tot[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
         } else {
-            v4f acc[4], acl[4];
+            v4f acc[4], acl[1];  // acl: the split mode's tail products
+            acl[0] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int a = 0; a < 4; ++a) acc[a] = acl[a] = (v4f){0.f, 0.f, 0.f, 0.f};
+            for (int a = 0; a < 4; ++a) acc[a] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
@@ -317,17 +334,24 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
-                for (int s = 0; s < 16; ++s) {
+                for (int s = 0; s < 16; ++s)
                     acc[s & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s].x, xb[h][s], acc[s & 3], 0, 0, 0);
-                    if constexpr (PR == P32S)
-                        acl[s & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s].y, xb[h][s], acl[s & 3], 0, 0, 0);
+                // The tail: four k steps per bf16 MFMA (bf16 element e of the
+                // lane is step 4t + e, the sample it feeds at that FP32 step),
+                // all into one accumulator.
+                if constexpr (PR == P32S) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acl[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            bf4(a[4 * t].y, a[4 * t + 1].y, a[4 * t + 2].y, a[4 * t + 3].y),
+                            bf4(xb[h][4 * t], xb[h][4 * t + 1], xb[h][4 * t + 2], xb[h][4 * t + 3]), acl[0], 0, 0, 0);
                 }
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                double t = 0.0;
+                double t = PR == P32S ? (double)acl[0][r] : 0.0;
 #pragma unroll
-                for (int a = 0; a < 4; ++a) t += (double)acc[a][r] + (PR == P32S ? (double)acl[a][r] : 0.0);
+                for (int a = 0; a < 4; ++a) t += (double)acc[a][r];
                 tot[r] = t;
             }
         }
@@ -492,6 +516,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
+        v4bf bopb;
+        if constexpr (PR == P32S) bopb = bf4((float)bop[0], (float)bop[1], (float)bop[2], (float)bop[3]);
 #pragma unroll
         for (int h = 0; h < NSUB; ++h) {
 #pragma unroll
@@ -536,11 +562,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
                 for (int t = 0; t < 4; ++t) {
                     v4f ap = {0.f, 0.f, 0.f, 0.f}, al = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
+                    for (int s = 0; s < 4; ++s)
                         ap = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s].x, bop[s], ap, 0, 0, 0);
-                        if constexpr (PR == P32S)
-                            al = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s].y, bop[s], al, 0, 0, 0);
-                    }
+                    // the tail: the panel's four k steps in one bf16 MFMA
+                    // (element s of the lane is step s, as above)
+                    if constexpr (PR == P32S)
+                        al = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            bf4(a[t][0].y, a[t][1].y, a[t][2].y, a[t][3].y), bopb, al, 0, 0, 0);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[h][t][r] += (double)ap[r] + (PR == P32S ? (double)al[r] : 0.0);
                 }

@@ -96,10 +96,11 @@ struct GroupInfo {
 
 // Arithmetic of a plan.  P64: complex128 data, FP64 throughout.  P32:
 // complex64 data, FP32 FFTs and FP32 MFMA contractions with d rounded to
-// FP32.  P32S: as P32 but d is split into hi + lo FP32 parts (two MFMA
-// products).  In both FP32 modes the partial sums (at most 32 beta samples
-// or 16 degrees) are combined in FP64.  In every mode the seeds, the recurrence, s_l, V_B and w_B(j) stay
-// in FP64.
+// FP32.  P32S: as P32 but d is split into hi + lo FP32 parts: hi contracted
+// on FP32 matrix cores, the tail lo (about 2^-24 of d) on bf16 matrix cores.
+// In both FP32 modes the partial sums (at most 32 beta samples or 16
+// degrees) are combined in FP64.  In every mode the seeds, the recurrence,
+// s_l, V_B and w_B(j) stay in FP64.
 enum Prec { P64 = 0, P32 = 1, P32S = 2 };
 template <int PR>
 struct PrecT {
