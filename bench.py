@@ -314,6 +314,104 @@ def cpu_baseline(B, c_host, budget_s=12.0, max_reps=3):
             "seconds": round(t, 2)}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def gpu_fwd_inv_ms(B, reps):
+    """FP64 GPU inverse and forward ms at bandwidth B (library stage timers)."""
+    import torch
+    from paper_1808_00896_amd import inputs, soft
+    with soft.Plan(B, tune=TUNE) as p:
+        c = torch.from_numpy(inputs.coeffs_decay(B, 1)).cuda()
+        g = p.inverse(c)
+        c2 = p.forward(g)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ti = tf = 0.0
+        for _ in range(reps):
+            s.record(); p.inverse(c, out=g); e.record(); e.synchronize(); ti += s.elapsed_time(e)
+            s.record(); p.forward(g, out=c2); e.record(); e.synchronize(); tf += s.elapsed_time(e)
+        del c, g, c2
+    torch.cuda.empty_cache()
+    return ti / reps, tf / reps
+
+
+def oracle_leg(B, what):
+    """Seconds of one oracle call at bandwidth B (run in a child process, so
+    OMP_NUM_THREADS applies).  what: "inverse", "forward" or "inverse_slices"
+    (the full inverse computed slice by slice, printing progress)."""
+    from oracle import oracle as O
+    from paper_1808_00896_amd import inputs
+    c = inputs.coeffs_decay(B, 1)
+    if what == "inverse_slices":
+        t = 0.0
+        N = 2 * B
+        for j in range(N):
+            t0 = time.perf_counter()
+            O.inverse_slice(B, c, j)
+            t += time.perf_counter() - t0
+            if (j + 1) % max(1, N // 16) == 0:
+                log(f"oracle inverse B={B}: {j + 1}/{N} slices, {t:.1f} s")
+        return t
+    if what == "forward":
+        g = inputs.grid_random(B, 1)
+        t0 = time.perf_counter()
+        O.forward(B, g)
+        return time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.inverse(B, c)
+    return time.perf_counter() - t0
+
+
+def oracle_table(Bs_all, Bs_single, slices_B):
+    """The FP64 oracle's seconds per inverse and forward at several B, on all
+    host threads and on one, beside the GPU's milliseconds for the same calls."""
+    import subprocess
+    rows = []
+
+    def child(B, what, threads):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-leg", f"{B}:{what}"],
+                           env=env, capture_output=True, text=True)
+        sys.stderr.write(r.stderr)
+        if r.returncode != 0:
+            raise RuntimeError(f"oracle leg B={B} {what} failed")
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    for B in sorted(set(Bs_all) | set(Bs_single) | {slices_B} - {None}):
+        gi, gf = gpu_fwd_inv_ms(B, 5 if B >= 256 else 20)
+        row = {"B": B, "gpu_inverse_ms": round(gi, 4), "gpu_forward_ms": round(gf, 4)}
+        if B in Bs_all:
+            for what in ("inverse", "forward"):
+                r = child(B, what, None)
+                row[f"oracle_{what}_s"] = round(r["seconds"], 3)
+                row["threads"] = r["threads"]
+                row[f"{what}_ratio"] = round(r["seconds"] * 1e3 / (gi if what == "inverse" else gf), 1)
+        if B == slices_B:
+            r = child(B, "inverse_slices", None)
+            row["oracle_inverse_s"] = round(r["seconds"], 1)
+            row["oracle_inverse_how"] = "slice by slice (every beta sample), summed"
+            row["threads"] = r["threads"]
+            row["inverse_ratio"] = round(r["seconds"] * 1e3 / gi, 1)
+        if B in Bs_single:
+            for what in ("inverse", "forward"):
+                r = child(B, what, 1)
+                row[f"oracle_{what}_s_1thread"] = round(r["seconds"], 3)
+        log(f"oracle table: {row}")
+        rows.append(row)
+    return {"cpu": cpu_model(), "nproc": os.cpu_count(), "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "rows": rows}
+
+
 def ceilings(copy_bytes):
     """What the chip sustains outside this library, for reading the roofline
     fractions: a plain device copy of `copy_bytes` (torch), and FP64 / FP32
@@ -383,11 +481,21 @@ def main():
     ap.add_argument("--no-match", action="store_true")
     ap.add_argument("--match-steps", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true", help="fixed DWT launch shapes instead of tuned ones")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time the FP64 oracle per direction at B = 16, 128, 256 (all threads; one thread "
+                         "at 16 and 128) and the B = 512 inverse slice by slice, beside the GPU, instead of "
+                         "the legs")
+    ap.add_argument("--oracle-leg", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
     global TUNE
     TUNE = not args.no_tune
+    if args.oracle_leg:
+        from oracle import oracle as O
+        b, what = args.oracle_leg.split(":")
+        print(json.dumps({"seconds": oracle_leg(int(b), what), "threads": O.num_threads()}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform is built and timed on a single MI355X; "
@@ -437,6 +545,11 @@ def main():
         out["cpu_baseline"] = cpu_baseline(B, c_host)
     else:
         out["cpu_baseline"] = None
+
+    if args.oracle_table:
+        out["oracle_table"] = oracle_table([16, 128, 256], [16, 128], 512)
+        print(json.dumps(out))
+        return
 
     legs = {}
     if not args.quick:

@@ -33,23 +33,28 @@ __device__ __forceinline__ int sh_degree(int q) {
 
 // f°(l, M, M') = a(l, M) conj(b(l, M')); block (l', f) writes the
 // (2l+1)^2 contiguous coefficients of degree l = B-1-l' of pair f (largest
-// degrees first), 256 at a time.  Row and column come from a float
-// reciprocal of 2l+1 with one exact integer correction.
+// degrees first): a(l, .) and b(l, .) are staged in LDS (2l+1 <= 1023
+// values each), then each wave writes whole rows M, its lanes on
+// neighbouring M', so every store is part of a contiguous run.
 template <typename C>
 __global__ __launch_bounds__(256) void k_corr_coeffs(int B, const C *__restrict__ a, const C *__restrict__ b,
                                                      C *__restrict__ out) {
+    __shared__ C sa[1024], sb[1024];
     const int l = B - 1 - (int)blockIdx.x, f = blockIdx.y;
-    const int w = 2 * l + 1, cnt = w * w;
-    const float rw = 1.0f / (float)w;
+    const int w = 2 * l + 1;
     const C *al = a + (long long)f * B * B + (long long)l * l;
     const C *bl = b + (long long)f * B * B + (long long)l * l;
     C *o = out + (long long)f * deg_offset(B) + deg_offset(l);
-    for (int q = threadIdx.x; q < cnt; q += 256) {
-        int row = (int)((float)q * rw);
-        int col = q - row * w;
-        if (col < 0) { --row; col += w; }
-        if (col >= w) { ++row; col -= w; }
-        o[q] = cmul_conj(al[row], bl[col]);
+    for (int t = threadIdx.x; t < w; t += 256) {
+        sa[t] = al[t];
+        sb[t] = bl[t];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int row = wave; row < w; row += 4) {
+        const C x = sa[row];
+        C *orow = o + (long long)row * w;
+        for (int c = lane; c < w; c += 64) orow[c] = cmul_conj(x, sb[c]);
     }
 }
 
