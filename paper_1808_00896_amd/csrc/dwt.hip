@@ -624,7 +624,7 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
 }
 
 // Launch shapes (waves x subsets of 64 beta samples per wave): 1x1, 2x1, 4x1,
-// 8x1, 1x2, 2x2, 4x2, 8x2; a shape covers items with 2B <= waves*subsets*64.
+// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1; a shape covers items with 2B <= waves*subsets*64.
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
@@ -646,6 +646,7 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_FWD(2, 2)
     SOFT_DWT_FWD(4, 2)
     SOFT_DWT_FWD(8, 2)
+    SOFT_DWT_FWD(16, 1)
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
 }
@@ -671,6 +672,7 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_INV(2, 2)
     SOFT_DWT_INV(4, 2)
     SOFT_DWT_INV(8, 2)
+    SOFT_DWT_INV(16, 1)
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;
 }

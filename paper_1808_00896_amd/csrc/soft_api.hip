@@ -389,7 +389,7 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
 
 // DWT launch shapes the library instantiates (waves, subsets of 64 beta
 // samples per wave).
-constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}};
+constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}};
 
 // Autotuner: for every DWT launch group and direction, time each shape that
 // covers the group's largest 2B (and is at most twice that) on the plan's own

@@ -249,7 +249,7 @@ def test_every_dwt_shape_B256_agrees(dev, prec):
 
 def test_set_dwt_shape_rejects_bad_shapes(dev):
     with soft.Plan(64) as p:
-        for args in ((1, 0, 2, 1), (0, 2, 2, 1), (0, 0, 1, 1), (0, 0, 3, 1), (0, 0, 16, 1)):
+        for args in ((1, 0, 2, 1), (0, 2, 2, 1), (0, 0, 1, 1), (0, 0, 3, 1), (0, 0, 16, 2)):
             with pytest.raises(soft.SoftError):
                 p.set_dwt_shape(*args)
 
