@@ -226,7 +226,8 @@ int soft_adjoint_inverse(soft_plan_t plan, const void *grid, void *coeffs, hipSt
 
 /*
  * Stage timing (measurement support).  When enabled, every transform call
- * records a HIP event on its stream before and after each kernel it enqueues;
+ * records a HIP event on its stream before and after each kernel of a timed
+ * stage it enqueues (adjacent timed kernels share one);
  * soft_plan_stage_times() waits for the recorded events and returns, per
  * stage, the summed elapsed milliseconds and the number of launches timed.
  * A plan of several bandwidths launches the FFT stages once per distinct B
@@ -251,10 +252,19 @@ enum {
 };
 
 /*
- * soft_plan_set_timing -- enable (1) or disable (0) stage timing for later
- * calls on this plan.  Returns SOFT_OK or SOFT_ERR_INVALID.
+ * soft_plan_set_timing -- enable (1) or disable (0) stage timing of every
+ * stage for later calls on this plan.  Returns SOFT_OK or SOFT_ERR_INVALID.
  */
 int soft_plan_set_timing(soft_plan_t plan, int enable);
+
+/*
+ * soft_plan_set_timing_stages -- time only the stages whose bit is set in
+ * mask (bit s = stage s, s < SOFT_NUM_STAGES; 0 disables timing), for later
+ * calls on this plan.  Each timed kernel costs about two event records on
+ * its stream, so timing one stage perturbs a call less than timing all.
+ * Returns SOFT_OK or SOFT_ERR_INVALID (unknown bits).
+ */
+int soft_plan_set_timing_stages(soft_plan_t plan, unsigned mask);
 
 /*
  * soft_plan_stage_times -- wait for all recorded stage events of this plan,

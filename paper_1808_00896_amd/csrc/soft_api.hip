@@ -77,7 +77,7 @@ struct soft_plan_s {
         int stage;
         hipEvent_t start, end;
     };
-    bool timing = false;
+    unsigned timing_mask = 0;  // bit s: time the kernels of stage s
     std::vector<hipEvent_t> free_events, used_events;
     std::vector<Pending> pending;
     double stage_ms[SOFT_NUM_STAGES] = {};
@@ -255,24 +255,37 @@ int check_call(soft_plan_t plan, const void *a, const void *b) {
 
 // Records one HIP event between consecutive kernels of a call when the plan
 // has timing enabled; each lap is charged to the stage of the kernel before it.
+// Stage timer of one call: HIP events on the call's stream around the
+// kernels of the stages in the plan's timing mask.  Adjacent timed kernels
+// share an event (the end of one is the start of the next).
 class StageClock {
   public:
     StageClock(soft_plan_s *p, hipStream_t s) : p_(p), s_(s) {}
-    hipError_t start() { return p_->timing ? record(&prev_) : hipSuccess; }
-    // Continue from the last event another clock on the same plan recorded.
-    void restart_after(soft_plan_s *p) {
-        if (p_->timing && !p->pending.empty()) prev_ = p->pending.back().end;
+    // Before launching a kernel of `stage`: an event marks its start.
+    hipError_t before(int stage) {
+        if (!on(stage) || have_) return hipSuccess;
+        const hipError_t r = record(&prev_);
+        have_ = r == hipSuccess;
+        return r;
     }
-    hipError_t lap(int stage) {
-        if (!p_->timing) return hipSuccess;
+    // After launching it: its end, which also starts a kernel launched next.
+    hipError_t after(int stage) {
+        if (!on(stage)) {
+            have_ = false;
+            return hipSuccess;
+        }
         hipEvent_t e;
         const hipError_t r = record(&e);
         if (r == hipSuccess) p_->pending.push_back({stage, prev_, e});
         prev_ = e;
+        have_ = r == hipSuccess;
         return r;
     }
+    // Other work was enqueued since the last event.
+    void lose_mark() { have_ = false; }
 
   private:
+    bool on(int stage) const { return (p_->timing_mask >> stage) & 1u; }
     hipError_t record(hipEvent_t *out) {
         hipEvent_t e;
         if (!p_->free_events.empty()) {
@@ -289,6 +302,7 @@ class StageClock {
     soft_plan_s *p_;
     hipStream_t s_;
     hipEvent_t prev_ = nullptr;
+    bool have_ = false;
 };
 
 const WorkItem *items_of(const soft_plan_s *p, const LaunchGroup &lg) {
@@ -306,18 +320,21 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     C *t1 = static_cast<C *>(p->t1);
     C *S = static_cast<C *>(p->S);
     StageClock clk(p, s);
-    hipError_t e = clk.start();
+    hipError_t e = hipSuccess;
     for (const Band &b : p->bands) {
+        if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_FWD);
         if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, s);
-        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_FWD);
+        if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_FWD);
+        if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_FWD);
         if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, s);
-        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_FWD);
+        if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_FWD);
     }
     for (const LaunchGroup &lg : p->groups) {
+        if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_FWD);
         if (e == hipSuccess)
             e = soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S, cout_, scaled,
                                          s);
-        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_FWD);
+        if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_FWD);
     }
     return e;
 }
@@ -333,18 +350,21 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     C *t1 = static_cast<C *>(p->t1);
     C *S = static_cast<C *>(p->S);
     StageClock clk(p, s);
-    hipError_t e = clk.start();
+    hipError_t e = hipSuccess;
     for (const LaunchGroup &lg : p->groups) {
+        if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_INV);
         if (e == hipSuccess)
             e = soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i, cin, S, scaled,
                                          s);
-        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_DWT_INV);
+        if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_INV);
     }
     for (const Band &b : p->bands) {
+        if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_INV);
         if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, s);
-        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_ALPHA_INV);
+        if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
+        if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_INV);
         if (e == hipSuccess) e = soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, s);
-        if (e == hipSuccess) e = clk.lap(SOFT_STAGE_FFT_GAMMA_INV);
+        if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_INV);
     }
     return e;
 }
@@ -373,17 +393,18 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
     using C = typename soft::PrecT<PR>::C;
     soft_plan_s *p = m->plan;
     StageClock clk(p, s);
-    hipError_t e = clk.start();
+    hipError_t e = clk.before(SOFT_STAGE_MATCH_COEFFS);
     if (e == hipSuccess)
         e = soft::launch_corr_coeffs<C>(m->B, m->n, static_cast<const C *>(a), static_cast<const C *>(b),
                                         static_cast<C *>(m->coeffs), s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_MATCH_COEFFS);
+    if (e == hipSuccess) e = clk.after(SOFT_STAGE_MATCH_COEFFS);
     if (e == hipSuccess) e = run_inverse<PR>(p, m->coeffs, grid, s, false);
-    clk.restart_after(p);
+    clk.lose_mark();
+    if (e == hipSuccess) e = clk.before(SOFT_STAGE_ARGMAX);
     if (e == hipSuccess)
         e = soft::launch_argmax_real<C>(static_cast<const C *>(grid), 8LL * m->B * m->B * m->B, m->n, m->part, index,
                                         s);
-    if (e == hipSuccess) e = clk.lap(SOFT_STAGE_ARGMAX);
+    if (e == hipSuccess) e = clk.after(SOFT_STAGE_ARGMAX);
     return e;
 }
 
@@ -814,7 +835,13 @@ int soft_adjoint(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s) {
 
 int soft_plan_set_timing(soft_plan_t p, int enable) {
     if (!p) return SOFT_ERR_INVALID;
-    p->timing = enable != 0;
+    p->timing_mask = enable ? (1u << SOFT_NUM_STAGES) - 1u : 0u;
+    return SOFT_OK;
+}
+
+int soft_plan_set_timing_stages(soft_plan_t p, unsigned mask) {
+    if (!p || (mask >> SOFT_NUM_STAGES)) return SOFT_ERR_INVALID;
+    p->timing_mask = mask;
     return SOFT_OK;
 }
 

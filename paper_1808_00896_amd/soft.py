@@ -60,6 +60,7 @@ def lib():
             getattr(L, name).argtypes = [vp, vp, vp, vp]
         L.soft_plan_destroy.argtypes = [vp]
         L.soft_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.soft_plan_set_timing_stages.argtypes = [vp, ctypes.c_uint]
         L.soft_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.soft_match_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(vp)]
@@ -76,7 +77,7 @@ def lib():
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
         for name in ("soft_plan", "soft_plan_uneven", "soft_plan_sizes", "soft_plan_offsets", "soft_plan_describe", "soft_plan_set_dwt_shape", "soft_forward", "soft_inverse", "soft_adjoint",
-                     "soft_adjoint_inverse", "soft_plan_destroy", "soft_plan_set_timing",
+                     "soft_adjoint_inverse", "soft_plan_destroy", "soft_plan_set_timing", "soft_plan_set_timing_stages",
                      "soft_plan_stage_times"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -177,6 +178,14 @@ STAGES = ("fft_gamma_fwd", "fft_alpha_fwd", "dwt_fwd", "dwt_inv", "fft_alpha_inv
 
 def soft_plan_set_timing(plan, enable):
     _check(lib().soft_plan_set_timing(ctypes.c_void_p(plan), int(bool(enable))), "soft_plan_set_timing")
+
+
+def soft_plan_set_timing_stages(plan, stages):
+    """Time only the named stages (names of STAGES) in later calls."""
+    mask = 0
+    for st in stages:
+        mask |= 1 << STAGES.index(st)
+    _check(lib().soft_plan_set_timing_stages(ctypes.c_void_p(plan), mask), "soft_plan_set_timing_stages")
 
 
 def soft_plan_stage_times(plan, reset=False):
