@@ -84,8 +84,10 @@ typedef enum {
  * Plan flags (bitwise or).
  *   SOFT_PLAN_TUNE  at plan time, time every DWT launch shape (waves per
  *                   block, beta samples per lane) that fits each DWT launch,
- *                   forward and inverse separately, on the plan's own work
- *                   list with zeroed data, and keep the fastest.  Costs a few
+ *                   forward and inverse separately, and for the inverse also
+ *                   the Clenshaw form (see soft_plan_set_dwt_shape), on the
+ *                   plan's own work list with zeroed data, and keep the
+ *                   fastest.  Costs a few
  *                   DWT launches per candidate at plan creation; without it
  *                   a fixed shape per 2B is used.
  *   SOFT_INPLACE_OK the plan may use the grid buffers as scratch, and holds
@@ -173,7 +175,11 @@ int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
  *   direction  0 = forward DWT, 1 = inverse DWT.
  *   waves, subsets  one of the built shapes (waves x subsets of 64 beta
  *              samples per wave): 1x1, 2x1, 4x1, 8x1, 1x2, 2x2, 4x2, 8x2, 16x1,
- *              covering the launch: waves * subsets * 64 >= its largest 2B.
+ *              covering the launch: waves * subsets * 64 >= its largest 2B;
+ *              or, for the inverse (direction 1), 0x0: the inverse DWT by
+ *              Clenshaw's backward summation over degrees (FP64 vector
+ *              arithmetic, one beta sample per lane) instead of the matrix
+ *              contraction.  soft_plan_describe reports it as [0, 0].
  * Takes effect for later calls.  Returns SOFT_OK or SOFT_ERR_INVALID.
  */
 int soft_plan_set_dwt_shape(soft_plan_t plan, int launch, int direction, int waves, int subsets);

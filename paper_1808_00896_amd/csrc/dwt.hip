@@ -161,16 +161,6 @@ __device__ __forceinline__ void lds_wait_all() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Work item of a block: runs of 64 items are re-dealt so that one XCD gets 8
-// consecutive items (8 neighbouring groups of one function, whose scattered
-// 16-byte coefficient accesses then meet in one L2); the list itself is
-// largest-cost first.  Everything a block indexes uniformly comes from its
-// item and from the kernel arguments, so it stays in scalar registers.
-__device__ __forceinline__ int item_of_block(int b, int n) {
-    if (b >= (n & ~63)) return b;
-    return (b & ~63) + ((b & 7) << 3) + ((b >> 3) & 7);
-}
-
 // Panel entry for the precision: FP64 stores e; FP32 stores (hi, lo) floats
 // in the same 8 bytes (lo = e - hi, used by the split mode).
 template <int PR>

@@ -354,8 +354,10 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     for (const LaunchGroup &lg : p->groups) {
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_INV);
         if (e == hipSuccess)
-            e = soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i, cin, S, scaled,
-                                         s);
+            e = lg.nw_i == 0 ? soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cin, S,
+                                                               scaled, s)
+                             : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i, cin,
+                                                        S, scaled, s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_INV);
     }
     for (const Band &b : p->bands) {
@@ -413,8 +415,9 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
 constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}};
 
 // Autotuner: for every DWT launch group and direction, time each shape that
-// covers the group's largest 2B (and is at most twice that) on the plan's own
-// work list and workspace, with zeroed data, and keep the fastest.  Every
+// covers the group's largest 2B (and is at most twice that), and for the
+// inverse also the Clenshaw kernel, on the plan's own work list and
+// workspace, with zeroed data, and keep the fastest.  Every
 // candidate runs once untimed (which also brings the clocks up), then
 // kTuneRounds rounds launch each candidate once in turn, each launch between
 // two HIP events on the null stream; a candidate's time is its fastest
@@ -430,12 +433,16 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
     C *S = static_cast<C *>(p->S), *cf = static_cast<C *>(coeffs);
     for (LaunchGroup &lg : p->groups) {
         for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+            // candidate c: index into kDwtShapes, or -1 for the Clenshaw inverse
             std::vector<int> cand;
             for (int c = 0; c < (int)(sizeof(kDwtShapes) / sizeof(kDwtShapes[0])); ++c) {
                 const int cover = kDwtShapes[c][0] * kDwtShapes[c][1] * 64;
                 if (cover >= lg.nmax && cover <= 2 * lg.nmax) cand.push_back(c);
             }
+            if (dir == 1) cand.push_back(-1);
             auto launch = [&](int c) {
+                if (c < 0)
+                    return soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cf, S, false, 0);
                 const int nw = kDwtShapes[c][0], ns = kDwtShapes[c][1];
                 return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true, 0)
                                 : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false, 0);
@@ -457,8 +464,8 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
             size_t bi = 0;
             for (size_t i = 1; i < cand.size(); ++i)
                 if (best[i] < best[bi]) bi = i;
-            (dir == 0 ? lg.nw_f : lg.nw_i) = kDwtShapes[cand[bi]][0];
-            (dir == 0 ? lg.nsub_f : lg.nsub_i) = kDwtShapes[cand[bi]][1];
+            (dir == 0 ? lg.nw_f : lg.nw_i) = cand[bi] < 0 ? 0 : kDwtShapes[cand[bi]][0];
+            (dir == 0 ? lg.nsub_f : lg.nsub_i) = cand[bi] < 0 ? 0 : kDwtShapes[cand[bi]][1];
         }
         lg.tuned = e == hipSuccess;
     }
@@ -798,6 +805,10 @@ int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves,
     if (!p || launch < 0 || launch >= (int)p->groups.size() || (direction != 0 && direction != 1))
         return SOFT_ERR_INVALID;
     LaunchGroup &lg = p->groups[launch];
+    if (direction == 1 && waves == 0 && subsets == 0) {  // the Clenshaw inverse
+        lg.nw_i = lg.nsub_i = 0;
+        return SOFT_OK;
+    }
     bool known = false;
     for (const auto &sh : kDwtShapes) known = known || (sh[0] == waves && sh[1] == subsets);
     if (!known || waves * subsets * 64 < lg.nmax) return SOFT_ERR_INVALID;

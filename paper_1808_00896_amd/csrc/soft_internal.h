@@ -136,6 +136,17 @@ struct WorkItem {
 };
 
 // Plan-wide tables of the DWT kernels (kernel arguments).
+// Work item of DWT block b of n: runs of 64 items are re-dealt so that one XCD
+// gets 8 consecutive items (8 neighbouring groups of one function, whose
+// scattered 16-byte coefficient accesses then meet in one L2); the list
+// itself is largest-cost first.  Everything a block indexes uniformly comes
+// from its item and from the kernel arguments, so it stays in scalar
+// registers.
+__device__ __forceinline__ int item_of_block(int b, int n) {
+    if (b >= (n & ~63)) return b;
+    return (b & ~63) + ((b & 7) << 3) + ((b >> 3) & 7);
+}
+
 struct DwtTables {
     const double *cosb;   // cos(beta_j), band by band
     const double *seed;   // d(l0, l0, m'; b_j) per group and beta sample, band by band
@@ -200,6 +211,14 @@ template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
                           hipStream_t s);
+
+// The same inverse DWT by Clenshaw's backward summation (clenshaw.hip): one
+// block of nmax rounded up to 64 lanes per work item, nmax/2 x 128 bytes of
+// LDS; nmax is the largest 2B of the items (2 .. 1024).
+template <int PR>
+hipError_t launch_idwt_clenshaw(const DwtTables &tab, const WorkItem *items, int nitems, int nmax,
+                                const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
+                                hipStream_t s);
 
 // Rotational-matching head (match.hip).  n pairs of functions on the sphere
 // (B^2 coefficients each): correlation coefficients a(l,M) conj(b(l,M')), the

@@ -136,6 +136,7 @@ def soft_plan_describe(plan):
 
 
 DWT_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (8, 2), (16, 1))
+CLENSHAW = (0, 0)  # inverse-DWT "shape" of the Clenshaw kernel (soft_plan_set_dwt_shape)
 
 
 def soft_plan_set_dwt_shape(plan, launch, direction, waves, subsets):

@@ -265,7 +265,8 @@ def test_tuned_plans_match_oracle(oracle, dev, prec):
         assert d["dwt_launches"][0]["tuned"]
         for key in ("forward", "inverse"):
             nw, ns = d["dwt_launches"][0][key]
-            assert (nw, ns) in soft.DWT_SHAPES and nw * ns * 64 >= 2 * B
+            assert ((nw, ns) in soft.DWT_SHAPES and nw * ns * 64 >= 2 * B) or \
+                (key == "inverse" and (nw, ns) == soft.CLENSHAW)
         g = to_host(p.inverse(to_dev(c, dev, prec)))
         assert relerr(g, oracle.inverse(B, c)) <= TOL[prec]
     Bs, cs = inputs.uneven_batch(10, [4, 16, 64, 256], seed=9)
