@@ -393,11 +393,14 @@ constexpr int chunk_of() { return NW <= 4 ? 16 : 32; }
 // + col of every chunk (degree c*KC + row, column col = 2 slot + part).  Its
 // member, sign and part are the same in every chunk (chunks advance the
 // degree by KC, an even number, so parity-dependent signs stay), so they are
-// set once.
+// set once.  A gather only issues the loads (the coefficient part and s_l, as
+// stored); the scaling waits for the staging a chunk later, so the loads of
+// chunk c + 1 are in flight while chunk c is contracted.
 template <int NT, int KC, typename R>
 struct InvGather {
     static constexpr int PER = (KC * 16 + NT - 1) / NT;  // values per thread
-    R v[PER];
+    R raw[PER];
+    double rs[PER];
     int mm[PER], mmp[PER];
     double sign[PER];
     bool on[PER];
@@ -414,37 +417,46 @@ __device__ __forceinline__ void inv_gather_init(InvGather<NT, KC, R> &st, const 
     }
 }
 
-// Gather chunk c (degrees c*KC .. c*KC+KC-1): the inverse reorder, with the
-// member's sign, s_l and optionally V_B applied; rows past L are zero.
+// Issue the loads of chunk c (degrees c*KC .. c*KC+KC-1).  Rows past the
+// group's last degree load that degree instead (every member has |mm|, |mmp|
+// <= m <= l, so each index stays inside the function's coefficients); their
+// values are dropped at staging.
 template <int NT, int KC, typename R>
 __device__ __forceinline__ void inv_gather(InvGather<NT, KC, R> &st, const double *__restrict__ rscale,
-                                           const R *__restrict__ cin, const WorkItem &it, int L, int c,
-                                           double v0) {
+                                           const R *__restrict__ cin, const WorkItem &it, int L, int c) {
 #pragma unroll
     for (int k = 0; k < InvGather<NT, KC, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
-        const int li = c * KC + (e >> 4);
-        double val = 0.0;
-        if (st.on[k] && li < L) {
-            const int l = it.m + li;
-            const double f = st.sign[k] * rscale[it.goff + li] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0);
-            val = (double)cin[2 * coeff_index32(l, st.mm[k], st.mmp[k]) + (e & 1)] * f;
+        if (e < KC * 16) {
+            const int li = min(c * KC + (e >> 4), L - 1);
+            st.raw[k] = cin[2 * coeff_index32(it.m + li, st.mm[k], st.mmp[k]) + (e & 1)];
+            st.rs[k] = rscale[it.goff + li];
         }
-        st.v[k] = (R)val;
     }
 }
 
-// Stage a gathered chunk.  Within each 16-degree block, degree d goes to row
-// 4(d%4) + d/4, so the MFMA k slot (s, lane/16) that takes degree s + 4(lane/16)
-// reads the contiguous rows 4s + lane/16.
+// Stage chunk c: the inverse reorder, with the member's sign, s_l and
+// optionally V_B applied; absent members and rows past L are zero.  Within
+// each 16-degree block, degree d goes to row 4(d%4) + d/4, so the MFMA k slot
+// (s, lane/16) that takes degree s + 4(lane/16) reads the contiguous rows
+// 4s + lane/16.
 template <int NT, int KC, typename R>
-__device__ __forceinline__ void inv_put(const InvGather<NT, KC, R> &st, R *buf) {
+__device__ __forceinline__ void inv_put(const InvGather<NT, KC, R> &st, R *buf, const WorkItem &it, int L, int c,
+                                        double v0) {
 #pragma unroll
     for (int k = 0; k < InvGather<NT, KC, R>::PER; ++k) {
         const int e = threadIdx.x + k * NT;
         const int row = e >> 4;
+        const int li = c * KC + row;
         const int prow = (row & ~15) | ((row & 3) << 2) | ((row >> 2) & 3);
-        if (e < KC * 16) buf[prow * 16 + (e & 15)] = st.v[k];
+        if (e < KC * 16) {
+            double val = 0.0;
+            if (st.on[k] && li < L) {
+                const int l = it.m + li;
+                val = (double)st.raw[k] * (st.sign[k] * st.rs[k] * (v0 != 0.0 ? (2.0 * l + 1.0) * v0 : 1.0));
+            }
+            buf[prow * 16 + (e & 15)] = (R)val;
+        }
     }
 }
 
@@ -472,7 +484,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 
     InvGather<NT, KC, R> st;
     inv_gather_init<NT, KC, R>(st, it);
-    inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 0, v0);
+    inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 0);
 
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
@@ -495,8 +507,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
 
-    inv_put<NT, KC, R>(st, stage[0]);
-    if (nchunk > 1) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 1, v0);
+    inv_put<NT, KC, R>(st, stage[0], it, L, 0, v0);
+    if (nchunk > 1) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 1);
     __syncthreads();
 
     double *pan = panel[wave];
@@ -567,8 +579,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
         if (lp + 16 - ch * KC == KC || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
-                inv_put<NT, KC, R>(st, stage[(ch + 1) & 1]);
-                if (ch + 2 < nchunk) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, ch + 2, v0);
+                inv_put<NT, KC, R>(st, stage[(ch + 1) & 1], it, L, ch + 1, v0);
+                if (ch + 2 < nchunk) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, ch + 2);
             }
             __syncthreads();
         }
