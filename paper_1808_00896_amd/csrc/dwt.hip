@@ -161,6 +161,15 @@ __device__ __forceinline__ void lds_wait_all() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Value of the neighbouring lane (lane ^ 1): DPP quad_perm [1, 0, 3, 2].
+__device__ __forceinline__ int swap_pair_lanes(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float swap_pair_lanes(float v) { return __int_as_float(swap_pair_lanes(__float_as_int(v))); }
+__device__ __forceinline__ double swap_pair_lanes(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = swap_pair_lanes((int)b), hi = swap_pair_lanes((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Panel entry for the precision: FP64 stores e; FP32 stores (hi, lo) floats
 // in the same 8 bytes (lo = e - hi, used by the split mode).
 template <int PR>
@@ -225,14 +234,21 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int jbase = (wave * NSUB + h) * 64;
+        // Lanes load whole complex samples: the even lane of a pair (re) that
+        // of step s, the odd lane (im) that of step s + 1; one swap of a half
+        // between the two lanes leaves each with its part of both steps.  A
+        // load then reads 4 x 2 neighbouring samples, 128 contiguous bytes in
+        // FP64, per slot row.  Samples past N load sample 0 and, like absent
+        // slots, are zeroed: no branches.
+        const bool odd = col & 1;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            // every lane loads (an in-range sample of its own slot row when its
-            // own is absent or past N), then absent entries are zeroed: no branches
-            const int j = jbase + 4 * s + krow;
-            const bool on = col_present && j < N;
-            const R v = reinterpret_cast<const R *>(Sg + (size_t)(col >> 1) * N + (on ? j : 0))[col & 1];
-            xb[h][s] = on ? v : (R)0;
+        for (int s = 0; s < 16; s += 2) {
+            const int j0 = jbase + 4 * s + krow, j1 = j0 + 4;
+            const int jl = odd ? j1 : j0;
+            const C v = Sg[(size_t)(col >> 1) * N + (jl < N ? jl : 0)];
+            const R recv = swap_pair_lanes(odd ? v.x : v.y);
+            xb[h][s] = col_present && j0 < N ? (odd ? recv : v.x) : (R)0;
+            xb[h][s + 1] = col_present && j1 < N ? (odd ? v.y : recv) : (R)0;
         }
         const int j = jbase + lane;
         const bool jin = j < N;
