@@ -37,9 +37,10 @@ template <int PR, int NB>
 __global__ __launch_bounds__(1024 / NB) void k_idwt_clenshaw(DwtTables tab, const double2 *__restrict__ rec,
                                                        const WorkItem *__restrict__ items, int nitems,
                                                        const typename PrecT<PR>::C *__restrict__ coeffs,
-                                                       typename PrecT<PR>::C *__restrict__ S, int apply_v) {
+                                                       typename PrecT<PR>::C *__restrict__ S, int flags) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
+    const bool apply_v = flags & kFlagScale, stream = flags & kFlagStream;
     extern __shared__ double cl[];  // [L][16]
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
     const int B = it.B, N = 2 * B;
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(1024 / NB) void k_idwt_clenshaw(DwtTables tab, cons
             C o;
             o.x = (R)(seed[h] * b1[h][2 * s]);
             o.y = (R)(seed[h] * b1[h][2 * s + 1]);
-            Sg[(size_t)s * N + j] = o;
+            put_c(&Sg[(size_t)s * N + j], o, stream);
         }
     }
 }
@@ -117,21 +118,21 @@ __global__ __launch_bounds__(1024 / NB) void k_idwt_clenshaw(DwtTables tab, cons
 template <int PR>
 hipError_t launch_idwt_clenshaw(const DwtTables &tab, const WorkItem *items, int nitems, int nmax,
                                 const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                                hipStream_t s) {
+                                bool stream, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (nmax < 2 || nmax > 1024) return hipErrorInvalidValue;
     constexpr int NB = 1;
     const int threads = (nmax + 64 * NB - 1) / (64 * NB) * 64;  // NB beta samples per lane
     const size_t lds = (size_t)(nmax / 2) * 16 * sizeof(double);  // L <= B = nmax / 2 degrees
     hipLaunchKernelGGL((k_idwt_clenshaw<PR, NB>), dim3(nitems), dim3(threads), lds, s, tab, tab.rec, items, nitems,
-                       coeffs, S, (int)apply_v);
+                       coeffs, S, (apply_v ? kFlagScale : 0) | (stream ? kFlagStream : 0));
     return hipGetLastError();
 }
 
 #define SOFT_CLENSHAW_INSTANTIATE(PR)                                                                          \
     template hipError_t launch_idwt_clenshaw<PR>(const DwtTables &, const WorkItem *, int, int,              \
                                                  const typename PrecT<PR>::C *, typename PrecT<PR>::C *, bool, \
-                                                 hipStream_t);
+                                                 bool, hipStream_t);
 SOFT_CLENSHAW_INSTANTIATE(P64)
 SOFT_CLENSHAW_INSTANTIATE(P32)
 SOFT_CLENSHAW_INSTANTIATE(P32S)

@@ -480,10 +480,11 @@ template <int NW, int NSUB, int PR>
 __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
                                                     const typename PrecT<PR>::C *__restrict__ coeffs,
-                                                    typename PrecT<PR>::C *__restrict__ S, int apply_v) {
+                                                    typename PrecT<PR>::C *__restrict__ S, int flags) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
     constexpr int NT = NW * 64;
+    const bool apply_v = flags & kFlagScale, stream = flags & kFlagStream;
     __shared__ double panel[NW][16 * kRowInv];
     constexpr int KC = chunk_of<NW>();
     __shared__ R stage[2][KC * 16];
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
             C o;
             o.x = (R)v.x;
             o.y = (R)v.y;
-            if (j < N && ((it.mask >> s2) & 1)) Sg[(size_t)s2 * N + j] = o;
+            if (j < N && ((it.mask >> s2) & 1)) put_c(&Sg[(size_t)s2 * N + j], o, stream);
         }
     }
 }
@@ -672,9 +673,9 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
 template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                          hipStream_t s) {
+                          bool stream, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    const int av = apply_v;
+    const int av = (apply_v ? kFlagScale : 0) | (stream ? kFlagStream : 0);
     const dim3 grid(nitems);
 #define SOFT_DWT_INV(NW_, NS_)                                                                               \
     if (nw == NW_ && nsub == NS_) {                                                                          \
@@ -699,7 +700,7 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
     template hipError_t launch_dwt_fwd<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
                                            const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);       \
     template hipError_t launch_dwt_inv<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
-                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);
+                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, bool, hipStream_t);
 SOFT_DWT_INSTANTIATE(P64)
 SOFT_DWT_INSTANTIATE(P32)
 SOFT_DWT_INSTANTIATE(P32S)

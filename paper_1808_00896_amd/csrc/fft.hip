@@ -322,7 +322,9 @@ __device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int
 // rows, and all its loads are consumed before its first barrier (or, for
 // N <= 16, by the one thread that owns the sequence), so in == out is safe.
 template <int N, int KIND, int SIGN, typename C, bool INGRID>
-__device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int apply_w) {
+__device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int flags) {
+    // streaming stores are built for 2B <= 512 only (stream_stores never asks above)
+    const bool apply_w = flags & kFlagScale, stream = N <= 512 && (flags & kFlagStream);
     using Sh = Shape<N>;
     constexpr int T = Tile<N, C>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
     constexpr int B = N / 2;
@@ -424,17 +426,17 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                 const int n = p_out + k * P + r * (N / R);
                 const C x = v[k * R + r];
                 if constexpr (KIND == GAMMA_FWD) {
-                    if (n != B) dst[u_index<N, T, INGRID>(line, n, row)] = x;
+                    if (n != B) put_c(&dst[u_index<N, T, INGRID>(line, n, row)], x, stream);
                 } else if constexpr (KIND == ALPHA_FWD) {
                     if (n != B) {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
-                        dst[(size_t)(sl >> 1) * N + jj] = cscale(x, wj);
+                        put_c(&dst[(size_t)(sl >> 1) * N + jj], cscale(x, wj), stream);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
-                    dst[u_index<N, T, INGRID>(row, line, n)] = x;
+                    put_c(&dst[u_index<N, T, INGRID>(row, line, n)], x, stream);
                 } else {
-                    dst[((size_t)row * N + line) * N + n] = cscale(x, wj);
+                    put_c(&dst[((size_t)row * N + line) * N + n], cscale(x, wj), stream);
                 }
             }
         }
@@ -444,43 +446,43 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
 // Intermediate in the plan's t1: input and output never alias.
 template <int N, int KIND, int SIGN, typename C>
 __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
-                                                     int apply_w) {
-    fft_pass<N, KIND, SIGN, C, false>(p, in, out, apply_w);
+                                                     int flags) {
+    fft_pass<N, KIND, SIGN, C, false>(p, in, out, flags);
 }
 
 // Intermediate in the grid buffer: the gamma passes run in place (in == out).
 template <int N, int KIND, int SIGN, typename C>
-__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_ingrid(PlanView p, const C *in, C *out, int apply_w) {
-    fft_pass<N, KIND, SIGN, C, true>(p, in, out, apply_w);
+__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_ingrid(PlanView p, const C *in, C *out, int flags) {
+    fft_pass<N, KIND, SIGN, C, true>(p, in, out, flags);
 }
 
 template <int N, int KIND, int SIGN, typename C, bool INGRID>
-hipError_t launch_kind(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
+hipError_t launch_kind(const PlanView &p, const C *in, C *out, int flags, hipStream_t s) {
     using Ti = Tile<N, C>;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
     const int nline = ALPHA ? N - 1 : N;
     // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
     dim3 g(N / Ti::T, nline, p.nfunc);
     if constexpr (INGRID)
-        hipLaunchKernelGGL((k_fft_ingrid<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+        hipLaunchKernelGGL((k_fft_ingrid<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, flags);
     else
-        hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, apply_w);
+        hipLaunchKernelGGL((k_fft<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, flags);
     return hipGetLastError();
 }
 
 template <int KIND, int SIGN, typename C, bool INGRID>
-hipError_t dispatch(const PlanView &p, const C *in, C *out, int apply_w, hipStream_t s) {
+hipError_t dispatch(const PlanView &p, const C *in, C *out, int flags, hipStream_t s) {
     switch (p.N) {
-        case 2: return launch_kind<2, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 4: return launch_kind<4, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 8: return launch_kind<8, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 16: return launch_kind<16, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 32: return launch_kind<32, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 64: return launch_kind<64, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 128: return launch_kind<128, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 256: return launch_kind<256, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 512: return launch_kind<512, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
-        case 1024: return launch_kind<1024, KIND, SIGN, C, INGRID>(p, in, out, apply_w, s);
+        case 2: return launch_kind<2, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 4: return launch_kind<4, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 8: return launch_kind<8, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 16: return launch_kind<16, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 32: return launch_kind<32, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 64: return launch_kind<64, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 128: return launch_kind<128, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 256: return launch_kind<256, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 512: return launch_kind<512, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 1024: return launch_kind<1024, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -491,31 +493,37 @@ hipError_t dispatch(const PlanView &p, const C *in, C *out, int apply_w, hipStre
 // buffer: the forward gamma pass overwrites the input grid, the inverse
 // alpha pass stages in the output grid.
 template <typename C>
-hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s) {
-    if (!t1) return dispatch<GAMMA_FWD, +1, C, true>(p, grid, const_cast<C *>(grid), 0, s);
-    return dispatch<GAMMA_FWD, +1, C, false>(p, grid, t1, 0, s);
+hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, bool stream, hipStream_t s) {
+    const int f = stream ? kFlagStream : 0;
+    if (!t1) return dispatch<GAMMA_FWD, +1, C, true>(p, grid, const_cast<C *>(grid), f, s);
+    return dispatch<GAMMA_FWD, +1, C, false>(p, grid, t1, f, s);
 }
 template <typename C>
-hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, const C *grid, C *S, bool apply_w, hipStream_t s) {
-    if (!t1) return dispatch<ALPHA_FWD, +1, C, true>(p, grid, S, (int)apply_w, s);
-    return dispatch<ALPHA_FWD, +1, C, false>(p, t1, S, (int)apply_w, s);
+hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, const C *grid, C *S, bool apply_w, bool stream,
+                                hipStream_t s) {
+    const int f = (apply_w ? kFlagScale : 0) | (stream ? kFlagStream : 0);
+    if (!t1) return dispatch<ALPHA_FWD, +1, C, true>(p, grid, S, f, s);
+    return dispatch<ALPHA_FWD, +1, C, false>(p, t1, S, f, s);
 }
 template <typename C>
-hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, hipStream_t s) {
-    if (!t1) return dispatch<ALPHA_INV, -1, C, true>(p, S, grid, 0, s);
-    return dispatch<ALPHA_INV, -1, C, false>(p, S, t1, 0, s);
+hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, bool stream, hipStream_t s) {
+    const int f = stream ? kFlagStream : 0;
+    if (!t1) return dispatch<ALPHA_INV, -1, C, true>(p, S, grid, f, s);
+    return dispatch<ALPHA_INV, -1, C, false>(p, S, t1, f, s);
 }
 template <typename C>
-hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, hipStream_t s) {
-    if (!t1) return dispatch<GAMMA_INV, -1, C, true>(p, grid, grid, (int)apply_w, s);
-    return dispatch<GAMMA_INV, -1, C, false>(p, t1, grid, (int)apply_w, s);
+hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, bool stream, hipStream_t s) {
+    const int f = (apply_w ? kFlagScale : 0) | (stream ? kFlagStream : 0);
+    if (!t1) return dispatch<GAMMA_INV, -1, C, true>(p, grid, grid, f, s);
+    return dispatch<GAMMA_INV, -1, C, false>(p, t1, grid, f, s);
 }
 
-#define SOFT_FFT_INSTANTIATE(C)                                                                                \
-    template hipError_t launch_fft_gamma_fwd<C>(const PlanView &, const C *, C *, hipStream_t);                 \
-    template hipError_t launch_fft_alpha_fwd<C>(const PlanView &, const C *, const C *, C *, bool, hipStream_t); \
-    template hipError_t launch_fft_alpha_inv<C>(const PlanView &, const C *, C *, C *, hipStream_t);             \
-    template hipError_t launch_fft_gamma_inv<C>(const PlanView &, const C *, C *, bool, hipStream_t);
+#define SOFT_FFT_INSTANTIATE(C)                                                                               \
+    template hipError_t launch_fft_gamma_fwd<C>(const PlanView &, const C *, C *, bool, hipStream_t);            \
+    template hipError_t launch_fft_alpha_fwd<C>(const PlanView &, const C *, const C *, C *, bool, bool,         \
+                                                hipStream_t);                                                  \
+    template hipError_t launch_fft_alpha_inv<C>(const PlanView &, const C *, C *, C *, bool, hipStream_t);       \
+    template hipError_t launch_fft_gamma_inv<C>(const PlanView &, const C *, C *, bool, bool, hipStream_t);
 SOFT_FFT_INSTANTIATE(double2)
 SOFT_FFT_INSTANTIATE(float2)
 

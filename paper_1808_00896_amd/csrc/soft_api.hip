@@ -312,6 +312,19 @@ const WorkItem *items_of(const soft_plan_s *p, const LaunchGroup &lg) {
 // Forward-type transform: per band the gamma then alpha FFT pass (optional W),
 // then the DWT launches, which write the l-major coefficients (optional V).
 // soft_forward uses W and V; soft_adjoint_inverse uses neither.
+// Streaming stores (soft::stream_stores) by the bytes a launch writes: a
+// band's FFT pass writes nfunc N^3 elements, an inverse-DWT launch 8 slot rows
+// of up to 2B samples per item.
+template <typename C>
+bool band_streams(const Band &b) {
+    const double n = b.view.N;
+    return soft::stream_stores((double)b.view.nfunc * n * n * n * sizeof(C));
+}
+template <typename C>
+bool group_streams(const LaunchGroup &lg) {
+    return soft::stream_stores((double)lg.nitems * soft::kSlots * lg.nmax * sizeof(C));
+}
+
 template <int PR>
 hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bool scaled) {
     using C = typename soft::PrecT<PR>::C;
@@ -323,10 +336,10 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     hipError_t e = hipSuccess;
     for (const Band &b : p->bands) {
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_FWD);
-        if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, s);
+        if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, band_streams<C>(b), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_FWD);
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_FWD);
-        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, s);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, band_streams<C>(b), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_FWD);
     }
     for (const LaunchGroup &lg : p->groups) {
@@ -355,17 +368,17 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_INV);
         if (e == hipSuccess)
             e = lg.nw_i == 0 ? soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cin, S,
-                                                               scaled, s)
+                                                               scaled, group_streams<C>(lg), s)
                              : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i, cin,
-                                                        S, scaled, s);
+                                                        S, scaled, group_streams<C>(lg), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_INV);
     }
     for (const Band &b : p->bands) {
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_INV);
-        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, s);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, band_streams<C>(b), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_INV);
-        if (e == hipSuccess) e = soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, s);
+        if (e == hipSuccess) e = soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, band_streams<C>(b), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_INV);
     }
     return e;
@@ -442,10 +455,12 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
             if (dir == 1) cand.push_back(-1);
             auto launch = [&](int c) {
                 if (c < 0)
-                    return soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cf, S, false, 0);
+                    return soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cf, S, false,
+                                                          group_streams<C>(lg), 0);
                 const int nw = kDwtShapes[c][0], ns = kDwtShapes[c][1];
                 return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true, 0)
-                                : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false, 0);
+                                : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false,
+                                                           group_streams<C>(lg), 0);
             };
             std::vector<float> best(cand.size(), 0.f);
             for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) e = launch(cand[i]);

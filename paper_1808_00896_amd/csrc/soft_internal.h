@@ -31,6 +31,31 @@ constexpr int kSlots = 8;
 // prefetch up to 32 rows past a group's end (the values are never used).
 constexpr int kPadRows = 32;
 
+// Kernel flag bits (the int flag argument of the FFT and inverse-DWT kernels).
+constexpr int kFlagScale = 1;   // apply w_B(j) (FFT) or V_B (inverse DWT)
+constexpr int kFlagStream = 2;  // write the main output with streaming stores
+
+// Whether a launch writes its main output with streaming (non-temporal)
+// stores.  Measured on MI355X: they speed up the next kernel when the array
+// written exceeds the 256 MB last-level cache, up to a few GB (B = 128 with
+// 1 to 16 functions, B = 256: 2-4 % per step); below that, plain stores
+// leave the array cached for the next kernel, and at B = 512 (8.6 GB a pass
+// in FP32, 17 GB in FP64) streaming stores slow the passes down.  The FFT
+// passes of 2B = 1024 never stream.
+inline bool stream_stores(double bytes) { return bytes > 192.0 * (1 << 20) && bytes <= 6.0 * (1 << 30); }
+
+// Store of one complex value, streaming (non-temporal) when asked.
+__device__ __forceinline__ void put_c(double2 *p, double2 x, bool stream) {
+    typedef double r2 __attribute__((ext_vector_type(2)));
+    if (stream) __builtin_nontemporal_store((r2){x.x, x.y}, reinterpret_cast<r2 *>(p));
+    else *p = x;
+}
+__device__ __forceinline__ void put_c(float2 *p, float2 x, bool stream) {
+    typedef float r2 __attribute__((ext_vector_type(2)));
+    if (stream) __builtin_nontemporal_store((r2){x.x, x.y}, reinterpret_cast<r2 *>(p));
+    else *p = x;
+}
+
 // Group slot code of order pair (m, m'), |m|, |m'| < B: (g*8 + s)*2 + (s >= 4)
 // with g = a(a+1)/2 + b for the representative a = max(|m|,|m'|),
 // b = min(|m|,|m'|) (groups ordered by a, then b) and s the member slot above.
@@ -180,15 +205,17 @@ struct PlanView {
 // the band's tile-blocked intermediate, [nfunc][N^3].  With t1 == nullptr the
 // passes keep the intermediate in grid order inside the grid buffer: the
 // forward gamma pass overwrites the input grid in place and the inverse alpha
-// pass stages in the output grid.
+// pass stages in the output grid.  With stream the pass writes its output
+// with streaming stores (stream_stores).
 template <typename C>
-hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, hipStream_t s);
+hipError_t launch_fft_gamma_fwd(const PlanView &p, const C *grid, C *t1, bool stream, hipStream_t s);
 template <typename C>
-hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, const C *grid, C *S, bool apply_w, hipStream_t s);
+hipError_t launch_fft_alpha_fwd(const PlanView &p, const C *t1, const C *grid, C *S, bool apply_w, bool stream,
+                                hipStream_t s);
 template <typename C>
-hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, hipStream_t s);
+hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, bool stream, hipStream_t s);
 template <typename C>
-hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, hipStream_t s);
+hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, bool stream, hipStream_t s);
 
 // Plan-time fill of the rescaled recurrence table of one band (rows from
 // goff[g]; rec and rscale are the plan-wide tables).
@@ -202,7 +229,7 @@ hipError_t launch_fill_seeds(const PlanView &p, double *seed, hipStream_t s);
 // sharing one launch shape: nw waves, nsub subsets of 64 beta samples per
 // wave (nw * nsub * 64 >= 2B of every item).  The forward writes the l-major
 // coefficients (symmetry signs, s_l and, when apply_v, V_B applied); the
-// inverse reads them.
+// inverse reads them and writes S, with streaming stores when stream.
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
@@ -210,7 +237,7 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
 template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                          hipStream_t s);
+                          bool stream, hipStream_t s);
 
 // The same inverse DWT by Clenshaw's backward summation (clenshaw.hip): one
 // block of nmax rounded up to 64 lanes per work item, nmax/2 x 128 bytes of
@@ -218,7 +245,7 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
 template <int PR>
 hipError_t launch_idwt_clenshaw(const DwtTables &tab, const WorkItem *items, int nitems, int nmax,
                                 const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                                hipStream_t s);
+                                bool stream, hipStream_t s);
 
 // Rotational-matching head (match.hip).  n pairs of functions on the sphere
 // (B^2 coefficients each): correlation coefficients a(l,M) conj(b(l,M')), the
