@@ -261,7 +261,9 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, ref=None, keep_ref=Fa
 def match_leg(steps, B=128, n=64):
     """Rotational matching of 64 pairs at B = 128: correlation coefficients,
     inverse transform to 64 grids of 256^3, argmax of each.  FP32-split timed;
-    the FP64 path run once for the argmax agreement and the grid error."""
+    the FP64 path run once for the argmax agreement and the grid error.  Each
+    precision also times the head without grids (argmax fused into the last
+    FFT pass), which must give the same indices."""
     import torch
     from paper_1808_00896_amd import inputs, soft
     a_h, b_h = inputs.sh_pair_batch(n, B, seed=6)
@@ -313,6 +315,22 @@ def match_leg(steps, B=128, n=64):
             r["speedup_vs_fp64"] = round(r["value"] / legs[f"match{n}_B{B}_fp64"]["value"], 3)
             del ref
         legs[f"match{n}_B{B}_{prec}"] = r
+        # the same head without grids: the argmax fused into the last FFT pass
+        idx2 = torch.empty_like(idx)
+        k2 = steps if prec == "fp32_split" else 5
+        for _ in range(2):
+            m.match_index(a, b, idx2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k2):
+            m.match_index(a, b, idx2)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t0
+        legs[f"match{n}_B{B}_{prec}_index"] = {
+            "pairs": n, "B": B, "precision": prec, "steps": k2, "value": round(n * k2 / el2, 2),
+            "unit": "pairs/s (coefficients + inverse with the argmax fused into its last pass, no grids)",
+            "ms_per_step": round(el2 / k2 * 1e3, 3), "same_index_as_grid_path": bool(torch.equal(idx2, idx)),
+            "speedup_vs_grid_path": round(n * k2 / el2 / r["value"], 3)}
         m.close()
         del a, b, grid
         torch.cuda.empty_cache()

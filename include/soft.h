@@ -362,7 +362,12 @@ int soft_match_argmax(soft_match_t match, const void *grid, long long *index, hi
  * soft_match -- the whole head: correlation coefficients of every pair (in
  * the head's own buffer), soft_inverse of them into grid, argmax of each
  * grid into index.  a, b: device (read only); grid: device, n grids
- * (written); index: device, n int64 (written).
+ * (written), or NULL; index: device, n int64 (written).
+ * With grid NULL no grid is written: the last FFT pass of the inverse
+ * reduces its values to argmax partial results in the head's buffer, and
+ * index is the same as with a grid (the same values are compared, with the
+ * same tie rule).  That needs the soft_plan's own FFT intermediate:
+ * SOFT_ERR_INVALID for a head made with SOFT_INPLACE_OK.
  */
 int soft_match(soft_match_t match, const void *a, const void *b, void *grid, long long *index, hipStream_t stream);
 

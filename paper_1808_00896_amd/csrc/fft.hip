@@ -321,8 +321,14 @@ __device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int
 // N^3).  In the grid, every gamma block reads and writes only its own T
 // rows, and all its loads are consumed before its first barrier (or, for
 // N <= 16, by the one thread that owns the sequence), so in == out is safe.
-template <int N, int KIND, int SIGN, typename C, bool INGRID>
-__device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int flags) {
+//
+// With ARGMAX (inverse gamma pass only) the pass stores nothing: each block
+// reduces the values it would store to the best (Re, flat index) and writes
+// that to part (see launch_fft_gamma_inv_argmax).
+template <int N, int KIND, int SIGN, typename C, bool INGRID, bool ARGMAX = false>
+__device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int flags,
+                                         ArgBest *part = nullptr) {
+    static_assert(!ARGMAX || (KIND == GAMMA_INV && !INGRID), "argmax is fused into the inverse gamma pass");
     // streaming stores are built for 2B <= 512 only (stream_stores never asks above)
     const bool apply_w = flags & kFlagScale, stream = N <= 512 && (flags & kFlagStream);
     using Sh = Shape<N>;
@@ -353,7 +359,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
         dst = out + u_off;
     } else {
         src = in + u_off;
-        dst = out + fi.grid_off;
+        dst = ARGMAX ? nullptr : out + fi.grid_off;
     }
     const int tid = threadIdx.x;
     const int mp_line = line < B ? line : line - N;  // m' of an alpha-pass block
@@ -419,6 +425,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
         if constexpr (KIND == ALPHA_FWD || KIND == GAMMA_INV) {
             if (apply_w) wj = p.w[KIND == ALPHA_FWD ? row : line];
         }
+        ArgBest best{-__builtin_huge_val(), kNoIndex};
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
 #pragma unroll
@@ -435,9 +442,40 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
                     put_c(&dst[u_index<N, T, INGRID>(row, line, n)], x, stream);
+                } else if constexpr (ARGMAX) {
+                    best = arg_better(best, ArgBest{(double)cscale(x, wj).x, ((long long)row * N + line) * N + n});
                 } else {
                     put_c(&dst[((size_t)row * N + line) * N + n], cscale(x, wj), stream);
                 }
+            }
+        }
+        if constexpr (ARGMAX) {
+            // Block reduction: across each wave by lane exchange, then over the
+            // waves (or, in blocks of fewer than 64 threads, over the threads).
+            constexpr int NT = Tile<N, C>::NT, NR = NT >= 64 ? NT / 64 : NT;
+            __shared__ double rv[NR];
+            __shared__ long long ri[NR];
+            if constexpr (NT >= 64) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    ArgBest q;
+                    q.v = __shfl_xor(best.v, o);
+                    q.i = __shfl_xor(best.i, o);
+                    best = arg_better(best, q);
+                }
+                if ((tid & 63) == 0) {
+                    rv[tid >> 6] = best.v;
+                    ri[tid >> 6] = best.i;
+                }
+            } else {
+                rv[tid] = best.v;
+                ri[tid] = best.i;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                ArgBest r{rv[0], ri[0]};
+                for (int w = 1; w < NR; ++w) r = arg_better(r, ArgBest{rv[w], ri[w]});
+                part[(size_t)bp.batch * ((N / T) * N) + (size_t)line * (N / T) + tile] = r;
             }
         }
     }
@@ -454,6 +492,20 @@ __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *_
 template <int N, int KIND, int SIGN, typename C>
 __global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_ingrid(PlanView p, const C *in, C *out, int flags) {
     fft_pass<N, KIND, SIGN, C, true>(p, in, out, flags);
+}
+
+// The inverse gamma pass fused with the first argmax stage.
+template <int N, typename C>
+__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_gamma_inv_argmax(PlanView p, const C *__restrict__ in,
+                                                                      ArgBest *__restrict__ part) {
+    fft_pass<N, GAMMA_INV, -1, C, false, true>(p, in, nullptr, 0, part);
+}
+
+template <int N, typename C>
+hipError_t launch_argmax_pass(const PlanView &p, const C *in, ArgBest *part, hipStream_t s) {
+    using Ti = Tile<N, C>;
+    hipLaunchKernelGGL((k_fft_gamma_inv_argmax<N, C>), dim3(N / Ti::T, N, p.nfunc), dim3(Ti::NT), 0, s, p, in, part);
+    return hipGetLastError();
 }
 
 template <int N, int KIND, int SIGN, typename C, bool INGRID>
@@ -518,12 +570,52 @@ hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool ap
     return dispatch<GAMMA_INV, -1, C, false>(p, t1, grid, f, s);
 }
 
+template <typename C>
+hipError_t launch_fft_gamma_inv_argmax(const PlanView &p, const C *t1, ArgBest *part, hipStream_t s) {
+    if (!t1 || !part) return hipErrorInvalidValue;
+    switch (p.N) {
+        case 2: return launch_argmax_pass<2, C>(p, t1, part, s);
+        case 4: return launch_argmax_pass<4, C>(p, t1, part, s);
+        case 8: return launch_argmax_pass<8, C>(p, t1, part, s);
+        case 16: return launch_argmax_pass<16, C>(p, t1, part, s);
+        case 32: return launch_argmax_pass<32, C>(p, t1, part, s);
+        case 64: return launch_argmax_pass<64, C>(p, t1, part, s);
+        case 128: return launch_argmax_pass<128, C>(p, t1, part, s);
+        case 256: return launch_argmax_pass<256, C>(p, t1, part, s);
+        case 512: return launch_argmax_pass<512, C>(p, t1, part, s);
+        case 1024: return launch_argmax_pass<1024, C>(p, t1, part, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <typename C>
+int argmax_blocks_of(int N) {
+    switch (N) {
+        case 2: return 2 / Tile<2, C>::T * 2;
+        case 4: return 4 / Tile<4, C>::T * 4;
+        case 8: return 8 / Tile<8, C>::T * 8;
+        case 16: return 16 / Tile<16, C>::T * 16;
+        case 32: return 32 / Tile<32, C>::T * 32;
+        case 64: return 64 / Tile<64, C>::T * 64;
+        case 128: return 128 / Tile<128, C>::T * 128;
+        case 256: return 256 / Tile<256, C>::T * 256;
+        case 512: return 512 / Tile<512, C>::T * 512;
+        case 1024: return 1024 / Tile<1024, C>::T * 1024;
+        default: return 0;
+    }
+}
+}  // namespace
+
+int gamma_argmax_blocks(int N, int csize) { return csize == 16 ? argmax_blocks_of<double2>(N) : argmax_blocks_of<float2>(N); }
+
 #define SOFT_FFT_INSTANTIATE(C)                                                                               \
     template hipError_t launch_fft_gamma_fwd<C>(const PlanView &, const C *, C *, bool, hipStream_t);            \
     template hipError_t launch_fft_alpha_fwd<C>(const PlanView &, const C *, const C *, C *, bool, bool,         \
                                                 hipStream_t);                                                  \
     template hipError_t launch_fft_alpha_inv<C>(const PlanView &, const C *, C *, C *, bool, hipStream_t);       \
-    template hipError_t launch_fft_gamma_inv<C>(const PlanView &, const C *, C *, bool, bool, hipStream_t);
+    template hipError_t launch_fft_gamma_inv<C>(const PlanView &, const C *, C *, bool, bool, hipStream_t);      \
+    template hipError_t launch_fft_gamma_inv_argmax<C>(const PlanView &, const C *, ArgBest *, hipStream_t);
 SOFT_FFT_INSTANTIATE(double2)
 SOFT_FFT_INSTANTIATE(float2)
 

@@ -118,16 +118,6 @@ __global__ __launch_bounds__(256) void k_corr_vjp_b(int B, int n, const C *__res
     gb[cl] = r;
 }
 
-struct ArgBest {
-    double v;
-    long long i;
-};
-
-// Larger value wins; on equal values the smaller index; NaN never wins.
-__device__ __forceinline__ ArgBest arg_better(ArgBest p, ArgBest q) {
-    return (q.v > p.v || (q.v == p.v && q.i < p.i)) ? q : p;
-}
-
 __device__ ArgBest block_best(ArgBest b) {
     __shared__ double sv[4];
     __shared__ long long si[4];
@@ -149,8 +139,6 @@ __device__ ArgBest block_best(ArgBest b) {
     for (int w = 1; w < 4; ++w) r = arg_better(r, ArgBest{sv[w], si[w]});
     return r;
 }
-
-constexpr long long kNoIndex = 0x7fffffffffffffffLL;
 
 // Stage 1: block (c, f) scans chunk c of grid f (elements [c*chunk,
 // (c+1)*chunk) of count) and writes its best (Re, index) to part[f*nblk + c].
@@ -225,6 +213,12 @@ hipError_t launch_argmax_real(const C *x, long long count, int n, void *workspac
     hipLaunchKernelGGL(k_argmax_part<C>, dim3(nblk, n), dim3(256), 0, s, x, count, chunk, nblk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_argmax_final, dim3(n), dim3(256), 0, s, part, nblk, index);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmax_final(const ArgBest *part, int nblk, int n, long long *index, hipStream_t s) {
+    if (n < 1 || nblk < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_argmax_final, dim3(n), dim3(256), 0, s, part, nblk, index);
     return hipGetLastError();
 }

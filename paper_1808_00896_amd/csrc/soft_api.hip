@@ -355,8 +355,13 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
 // Inverse-type transform: the iDWT launches (reading the l-major coefficients,
 // optional V), then per band the alpha then gamma FFT pass (optional W).
 // soft_inverse uses neither factor; soft_adjoint uses both.
+//
+// With part (a one-band plan with its own FFT intermediate) the grid is not
+// written: the last pass reduces each block's values to argmax partials
+// instead (soft::launch_fft_gamma_inv_argmax), and grid may be null.
 template <int PR>
-hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bool scaled) {
+hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_t s, bool scaled,
+                       soft::ArgBest *part = nullptr) {
     using C = typename soft::PrecT<PR>::C;
     const C *cin = static_cast<const C *>(coeffs);
     C *gout = static_cast<C *>(grid);
@@ -378,7 +383,9 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
         if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, band_streams<C>(b), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_INV);
-        if (e == hipSuccess) e = soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, band_streams<C>(b), s);
+        if (e == hipSuccess)
+            e = part ? soft::launch_fft_gamma_inv_argmax<C>(b.view, t1, part, s)
+                     : soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, band_streams<C>(b), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_INV);
     }
     return e;
@@ -413,12 +420,15 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
         e = soft::launch_corr_coeffs<C>(m->B, m->n, static_cast<const C *>(a), static_cast<const C *>(b),
                                         static_cast<C *>(m->coeffs), s);
     if (e == hipSuccess) e = clk.after(SOFT_STAGE_MATCH_COEFFS);
-    if (e == hipSuccess) e = run_inverse<PR>(p, m->coeffs, grid, s, false);
+    // Without a grid the inverse gamma pass reduces straight to argmax partials.
+    soft::ArgBest *fused = grid ? nullptr : static_cast<soft::ArgBest *>(m->part);
+    if (e == hipSuccess) e = run_inverse<PR>(p, m->coeffs, grid, s, false, fused);
     clk.lose_mark();
     if (e == hipSuccess) e = clk.before(SOFT_STAGE_ARGMAX);
     if (e == hipSuccess)
-        e = soft::launch_argmax_real<C>(static_cast<const C *>(grid), 8LL * m->B * m->B * m->B, m->n, m->part, index,
-                                        s);
+        e = fused ? soft::launch_argmax_final(fused, soft::gamma_argmax_blocks(2 * m->B, (int)p->csize), m->n, index, s)
+                  : soft::launch_argmax_real<C>(static_cast<const C *>(grid), 8LL * m->B * m->B * m->B, m->n, m->part,
+                                                index, s);
     if (e == hipSuccess) e = clk.after(SOFT_STAGE_ARGMAX);
     return e;
 }
@@ -919,8 +929,12 @@ int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *o
         return rc;
     }
     const long long N3 = 8LL * B * B * B;
+    // argmax partials: of the grid scan, or of the inverse gamma pass fused with it
+    const size_t part_bytes = std::max(soft::argmax_workspace_bytes(N3, n),
+                                       sizeof(soft::ArgBest) * (size_t)n *
+                                           (size_t)soft::gamma_argmax_blocks(2 * B, (int)m->plan->csize));
     if (hipMalloc(&m->coeffs, m->plan->coeff_total * m->plan->csize) != hipSuccess ||
-        hipMalloc(&m->part, soft::argmax_workspace_bytes(N3, n)) != hipSuccess) {
+        hipMalloc(&m->part, part_bytes) != hipSuccess) {
         (void)hipGetLastError();
         free_match(m);
         return SOFT_ERR_OOM;
@@ -987,7 +1001,10 @@ int soft_match_argmax(soft_match_t m, const void *grid, long long *index, hipStr
 
 int soft_match(soft_match_t m, const void *a, const void *b, void *grid, long long *index, hipStream_t s) {
     if (!m || !a || !b) return SOFT_ERR_INVALID;
-    const int rc = check_call(m->plan, grid, index);
+    // no grid: the argmax is fused into the last FFT pass, which needs the
+    // plan's own FFT intermediate
+    if (!grid && !m->plan->t1) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, grid ? grid : index, index);
     if (rc != SOFT_OK) return rc;
     hipError_t e;
     switch (m->plan->precision) {

@@ -44,6 +44,18 @@ constexpr int kFlagStream = 2;  // write the main output with streaming stores
 // passes of 2B = 1024 never stream.
 inline bool stream_stores(double bytes) { return bytes > 192.0 * (1 << 20) && bytes <= 6.0 * (1 << 30); }
 
+// Running argmax of Re over a grid: the larger value wins, on equal values
+// the smaller flat index; NaN never wins (comparisons with NaN are false), so
+// a scan that sees only NaN keeps kNoIndex.
+struct ArgBest {
+    double v;
+    long long i;
+};
+constexpr long long kNoIndex = 0x7fffffffffffffffLL;
+__device__ __forceinline__ ArgBest arg_better(ArgBest p, ArgBest q) {
+    return (q.v > p.v || (q.v == p.v && q.i < p.i)) ? q : p;
+}
+
 // Store of one complex value, streaming (non-temporal) when asked.
 __device__ __forceinline__ void put_c(double2 *p, double2 x, bool stream) {
     typedef double r2 __attribute__((ext_vector_type(2)));
@@ -217,6 +229,17 @@ hipError_t launch_fft_alpha_inv(const PlanView &p, const C *S, C *t1, C *grid, b
 template <typename C>
 hipError_t launch_fft_gamma_inv(const PlanView &p, const C *t1, C *grid, bool apply_w, bool stream, hipStream_t s);
 
+// The inverse gamma pass of a one-band plan fused with the first stage of
+// the argmax of Re (rotational matching without materialising the grids):
+// block (tile, line) of function f writes the best (Re, flat index
+// (i*2B + j)*2B + k) of the values the pass would store to
+// part[f * gamma_argmax_blocks(N, c) + line * (N / T) + tile], T the pass's
+// tile height, c the complex size in bytes.  launch_argmax_final then
+// reduces the gamma_argmax_blocks partials of each function.
+template <typename C>
+hipError_t launch_fft_gamma_inv_argmax(const PlanView &p, const C *t1, ArgBest *part, hipStream_t s);
+int gamma_argmax_blocks(int N, int csize);
+
 // Plan-time fill of the rescaled recurrence table of one band (rows from
 // goff[g]; rec and rscale are the plan-wide tables).
 hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s);
@@ -256,6 +279,7 @@ hipError_t launch_corr_coeffs(int B, int n, const C *a, const C *b, C *coeffs, h
 template <typename C>
 hipError_t launch_corr_vjp(int B, int n, const C *a, const C *b, const C *g, C *ga, C *gb, hipStream_t s);
 size_t argmax_workspace_bytes(long long count, int n);
+hipError_t launch_argmax_final(const ArgBest *part, int nblk, int n, long long *index, hipStream_t s);
 template <typename C>
 hipError_t launch_argmax_real(const C *x, long long count, int n, void *workspace, long long *index, hipStream_t s);
 

@@ -153,7 +153,7 @@ def soft_plan_sizes(plan):
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(None if t is None else t.data_ptr())
 
 
 def soft_forward(plan, grid, coeffs, stream=None):
@@ -485,6 +485,16 @@ class MatchPlan:
         idx = index if index is not None else torch.empty(self.n, dtype=torch.int64, device=self.device)
         soft_match(self.handle, a, b, g, idx)
         return g, idx
+
+    def match_index(self, a, b, index=None):
+        """The argmax of every pair's correlation grid without the grids: the
+        last FFT pass reduces to the argmax instead of storing (same indices
+        as ``match``; not for ``inplace_ok`` heads)."""
+        a = self._chk(a, self.sh_shape(), "a")
+        b = self._chk(b, self.sh_shape(), "b")
+        idx = index if index is not None else torch.empty(self.n, dtype=torch.int64, device=self.device)
+        soft_match(self.handle, a, b, None, idx)
+        return idx
 
     def close(self):
         if getattr(self, "handle", None):
