@@ -329,7 +329,7 @@ template <int N, int KIND, int SIGN, typename C, bool INGRID, bool ARGMAX = fals
 __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out, int flags,
                                          ArgBest *part = nullptr) {
     static_assert(!ARGMAX || (KIND == GAMMA_INV && !INGRID), "argmax is fused into the inverse gamma pass");
-    // streaming stores are built for 2B <= 512 only (stream_stores never asks above)
+    // streaming stores are built for 2B <= 512 only (stream_stores never asks at 1024)
     const bool apply_w = flags & kFlagScale, stream = N <= 512 && (flags & kFlagStream);
     using Sh = Shape<N>;
     constexpr int T = Tile<N, C>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;

@@ -318,11 +318,11 @@ const WorkItem *items_of(const soft_plan_s *p, const LaunchGroup &lg) {
 template <typename C>
 bool band_streams(const Band &b) {
     const double n = b.view.N;
-    return soft::stream_stores((double)b.view.nfunc * n * n * n * sizeof(C));
+    return soft::stream_stores((double)b.view.nfunc * n * n * n * sizeof(C), b.view.N);
 }
 template <typename C>
 bool group_streams(const LaunchGroup &lg) {
-    return soft::stream_stores((double)lg.nitems * soft::kSlots * lg.nmax * sizeof(C));
+    return soft::stream_stores((double)lg.nitems * soft::kSlots * lg.nmax * sizeof(C), lg.nmax);
 }
 
 template <int PR>

@@ -36,13 +36,13 @@ constexpr int kFlagScale = 1;   // apply w_B(j) (FFT) or V_B (inverse DWT)
 constexpr int kFlagStream = 2;  // write the main output with streaming stores
 
 // Whether a launch writes its main output with streaming (non-temporal)
-// stores.  Measured on MI355X: they speed up the next kernel when the array
-// written exceeds the 256 MB last-level cache, up to a few GB (B = 128 with
-// 1 to 16 functions, B = 256: 2-4 % per step); below that, plain stores
-// leave the array cached for the next kernel, and at B = 512 (8.6 GB a pass
-// in FP32, 17 GB in FP64) streaming stores slow the passes down.  The FFT
-// passes of 2B = 1024 never stream.
-inline bool stream_stores(double bytes) { return bytes > 192.0 * (1 << 20) && bytes <= 6.0 * (1 << 30); }
+// stores: bytes written by the launch, nmax its largest 2B.  Measured on
+// MI355X: they speed up the next kernel when the array written exceeds the
+// 256 MB last-level cache (B = 128 with 1 to 64 functions, B = 256: 2-4 %
+// per step); below that, plain stores leave the array cached for the next
+// kernel.  At 2B = 1024 streaming slowed the FFT passes down (B = 512: 3 %
+// per step), so those launches keep plain stores.
+inline bool stream_stores(double bytes, int nmax) { return nmax < 1024 && bytes > 192.0 * (1 << 20); }
 
 // Running argmax of Re over a grid: the larger value wins, on equal values
 // the smaller flat index; NaN never wins (comparisons with NaN are false), so

@@ -1,6 +1,6 @@
 """Streaming (non-temporal) stores, through the C-ABI.
-A launch whose output array lies between 192 MiB and 6 GiB writes it with
-streaming stores (the FFT passes and the inverse DWT).  A store hint changes
+A launch whose output array exceeds 192 MiB writes it with streaming stores
+(the FFT passes and the inverse DWT), except at 2B = 1024.  A store hint changes
 no value: 16 functions at B = 64 in one plan (537 MB a pass, streamed) must
 equal the same functions transformed one at a time (34 MB a pass, plain
 stores) bit for bit, in every transform, for the matrix-core and the Clenshaw
