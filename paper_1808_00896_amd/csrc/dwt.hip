@@ -229,43 +229,58 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
     const int col = lane & 15, krow = lane >> 4;
     const bool col_present = (mask >> (col >> 1)) & 1;
+    const bool odd = col & 1;
+
+    // Every load of the prologue goes out before any is used, so they are
+    // all in flight at once: the recurrence coefficients of the first panel
+    // (scalar), the S block, cos b_j and seeds, and s_l of the lane's row.
+    double2 c[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
+    // Lanes load whole complex samples: the even lane of a pair (re) that of
+    // step s, the odd lane (im) that of step s + 1; one swap of a half between
+    // the two lanes later leaves each with its part of both steps.  A load
+    // then reads 4 x 2 neighbouring samples, 128 contiguous bytes in FP64, per
+    // slot row.  Samples past N load sample 0 and, like absent slots, are
+    // zeroed: no branches.
+    C raw[NSUB][8];
+    double xv[NSUB], sv[NSUB];
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h) {
+        const int jbase = (wave * NSUB + h) * 64;
+#pragma unroll
+        for (int s = 0; s < 16; s += 2) {
+            const int jl = jbase + 4 * s + krow + (odd ? 4 : 0);
+            raw[h][s / 2] = Sg[(size_t)(col >> 1) * N + (jl < N ? jl : 0)];
+        }
+        const int j = jbase + lane;
+        xv[h] = tab.cosb[it.jbase + (j < N ? j : 0)];
+        sv[h] = tab.seed[it.seed_off + (j < N ? j : 0)];
+    }
+    // s_l of the group's rows (at most one per thread: L <= B <= NW*NSUB*32),
+    // read in the panel epilogues (visible after the first panel's barrier)
+    const double rs = tab.rscale[goff + min((int)threadIdx.x, L - 1)];
+    __builtin_amdgcn_sched_barrier(0);
+
     R xb[NSUB][16];
     double x[NSUB], ecur[NSUB], eprev[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int jbase = (wave * NSUB + h) * 64;
-        // Lanes load whole complex samples: the even lane of a pair (re) that
-        // of step s, the odd lane (im) that of step s + 1; one swap of a half
-        // between the two lanes leaves each with its part of both steps.  A
-        // load then reads 4 x 2 neighbouring samples, 128 contiguous bytes in
-        // FP64, per slot row.  Samples past N load sample 0 and, like absent
-        // slots, are zeroed: no branches.
-        const bool odd = col & 1;
 #pragma unroll
         for (int s = 0; s < 16; s += 2) {
             const int j0 = jbase + 4 * s + krow, j1 = j0 + 4;
-            const int jl = odd ? j1 : j0;
-            const C v = Sg[(size_t)(col >> 1) * N + (jl < N ? jl : 0)];
+            const C v = raw[h][s / 2];
             const R recv = swap_pair_lanes(odd ? v.x : v.y);
             xb[h][s] = col_present && j0 < N ? (odd ? recv : v.x) : (R)0;
             xb[h][s + 1] = col_present && j1 < N ? (odd ? v.y : recv) : (R)0;
         }
-        const int j = jbase + lane;
-        const bool jin = j < N;
-        const double xv = tab.cosb[it.jbase + (jin ? j : 0)];
-        const double sv = tab.seed[it.seed_off + (jin ? j : 0)];
-        x[h] = jin ? xv : 0.0;
-        ecur[h] = jin ? sv : 0.0;
+        const bool jin = jbase + lane < N;
+        x[h] = jin ? xv[h] : 0.0;
+        ecur[h] = jin ? sv[h] : 0.0;
         eprev[h] = 0.0;
     }
-
-    double2 c[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
-
-    // s_l of the group's rows, read in the panel epilogues (visible after the
-    // first panel's barrier).
-    for (int t = threadIdx.x; t < L; t += NW * 64) srow[t] = tab.rscale[goff + t];
+    if ((int)threadIdx.x < L) srow[threadIdx.x] = rs;
     double *pan = panel[wave];
     R *out = reinterpret_cast<R *>(coeffs + it.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
