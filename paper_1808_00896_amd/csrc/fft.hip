@@ -176,14 +176,23 @@ struct Shape {
     static constexpr int RS = N + N / 16 + 1;  // LDS row stride (complex), padded
 };
 
+// The four passes: gamma (over k) and alpha (over i), forward and inverse.
+enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
+
 // T neighbouring sequences per block: the transposed side of a pass moves
 // runs of T elements, so T is chosen for runs of at least 128 bytes (T = 8
 // complex128 or 16 complex64 from 2B = 512 up) within about 140 KB of LDS
 // (one block of 512-1024 threads per CU at 2B = 1024); 32 for N <= 64, 16 up
-// to 256; never more than N.
-template <int N, typename C>
+// to 256; never more than N.  The inverse passes at 2B = 1024 through the
+// plan's intermediate take half that (64-byte runs in FP64, two blocks per
+// CU), which measured faster for both of them (FP64: 7.8 -> 7.5 and 8.0 ->
+// 7.7 ms); the forward passes were slower with it, and so were the inverse
+// passes staging in the grid (INGRID).  The two passes of one direction share
+// T, which fixes the layout of their intermediate.
+template <int N, typename C, int KIND, bool INGRID>
 struct Tile {
-    static constexpr int T0 = N <= 64 ? 32 : (N <= 256 ? 16 : (sizeof(C) == 16 ? 8 : 16));
+    static constexpr int TF = N <= 64 ? 32 : (N <= 256 ? 16 : (sizeof(C) == 16 ? 8 : 16));
+    static constexpr int T0 = N >= 1024 && !INGRID && (KIND == ALPHA_INV || KIND == GAMMA_INV) ? TF / 2 : TF;
     static constexpr int T = T0 < N ? T0 : N;
     static constexpr int NT = T * Shape<N>::P;
     static constexpr int LDS = Shape<N>::P > 1 ? T * Shape<N>::RS : 1;
@@ -276,7 +285,6 @@ __device__ __forceinline__ size_t u_index(int j, int q, int i) {
 }
 
 // Pass kinds: where a block's T sequences come from and go to.
-enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
 
 template <int KIND>
 constexpr bool transposed_in() { return KIND == ALPHA_INV || KIND == GAMMA_INV; }
@@ -332,11 +340,11 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     // streaming stores are built for 2B <= 512 only (stream_stores never asks at 1024)
     const bool apply_w = flags & kFlagScale, stream = N <= 512 && (flags & kFlagStream);
     using Sh = Shape<N>;
-    constexpr int T = Tile<N, C>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
+    constexpr int T = Tile<N, C, KIND, INGRID>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
     constexpr int B = N / 2;
     constexpr int LAST = NSTG - 1;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
-    __shared__ C lds[Tile<N, C>::LDS];
+    __shared__ C lds[Tile<N, C, KIND, INGRID>::LDS];
     const C *tw = twiddles<C>(p, SIGN);
 
     // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
@@ -452,7 +460,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
         if constexpr (ARGMAX) {
             // Block reduction: across each wave by lane exchange, then over the
             // waves (or, in blocks of fewer than 64 threads, over the threads).
-            constexpr int NT = Tile<N, C>::NT, NR = NT >= 64 ? NT / 64 : NT;
+            constexpr int NT = Tile<N, C, KIND, INGRID>::NT, NR = NT >= 64 ? NT / 64 : NT;
             __shared__ double rv[NR];
             __shared__ long long ri[NR];
             if constexpr (NT >= 64) {
@@ -483,34 +491,34 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
 
 // Intermediate in the plan's t1: input and output never alias.
 template <int N, int KIND, int SIGN, typename C>
-__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
+__global__ __launch_bounds__((Tile<N, C, KIND, false>::NT)) void k_fft(PlanView p, const C *__restrict__ in, C *__restrict__ out,
                                                      int flags) {
     fft_pass<N, KIND, SIGN, C, false>(p, in, out, flags);
 }
 
 // Intermediate in the grid buffer: the gamma passes run in place (in == out).
 template <int N, int KIND, int SIGN, typename C>
-__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_ingrid(PlanView p, const C *in, C *out, int flags) {
+__global__ __launch_bounds__((Tile<N, C, KIND, true>::NT)) void k_fft_ingrid(PlanView p, const C *in, C *out, int flags) {
     fft_pass<N, KIND, SIGN, C, true>(p, in, out, flags);
 }
 
 // The inverse gamma pass fused with the first argmax stage.
 template <int N, typename C>
-__global__ __launch_bounds__((Tile<N, C>::NT)) void k_fft_gamma_inv_argmax(PlanView p, const C *__restrict__ in,
+__global__ __launch_bounds__((Tile<N, C, GAMMA_INV, false>::NT)) void k_fft_gamma_inv_argmax(PlanView p, const C *__restrict__ in,
                                                                       ArgBest *__restrict__ part) {
     fft_pass<N, GAMMA_INV, -1, C, false, true>(p, in, nullptr, 0, part);
 }
 
 template <int N, typename C>
 hipError_t launch_argmax_pass(const PlanView &p, const C *in, ArgBest *part, hipStream_t s) {
-    using Ti = Tile<N, C>;
+    using Ti = Tile<N, C, GAMMA_INV, false>;
     hipLaunchKernelGGL((k_fft_gamma_inv_argmax<N, C>), dim3(N / Ti::T, N, p.nfunc), dim3(Ti::NT), 0, s, p, in, part);
     return hipGetLastError();
 }
 
 template <int N, int KIND, int SIGN, typename C, bool INGRID>
 hipError_t launch_kind(const PlanView &p, const C *in, C *out, int flags, hipStream_t s) {
-    using Ti = Tile<N, C>;
+    using Ti = Tile<N, C, KIND, INGRID>;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
     const int nline = ALPHA ? N - 1 : N;
     // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
@@ -592,16 +600,16 @@ namespace {
 template <typename C>
 int argmax_blocks_of(int N) {
     switch (N) {
-        case 2: return 2 / Tile<2, C>::T * 2;
-        case 4: return 4 / Tile<4, C>::T * 4;
-        case 8: return 8 / Tile<8, C>::T * 8;
-        case 16: return 16 / Tile<16, C>::T * 16;
-        case 32: return 32 / Tile<32, C>::T * 32;
-        case 64: return 64 / Tile<64, C>::T * 64;
-        case 128: return 128 / Tile<128, C>::T * 128;
-        case 256: return 256 / Tile<256, C>::T * 256;
-        case 512: return 512 / Tile<512, C>::T * 512;
-        case 1024: return 1024 / Tile<1024, C>::T * 1024;
+        case 2: return 2 / Tile<2, C, GAMMA_INV, false>::T * 2;
+        case 4: return 4 / Tile<4, C, GAMMA_INV, false>::T * 4;
+        case 8: return 8 / Tile<8, C, GAMMA_INV, false>::T * 8;
+        case 16: return 16 / Tile<16, C, GAMMA_INV, false>::T * 16;
+        case 32: return 32 / Tile<32, C, GAMMA_INV, false>::T * 32;
+        case 64: return 64 / Tile<64, C, GAMMA_INV, false>::T * 64;
+        case 128: return 128 / Tile<128, C, GAMMA_INV, false>::T * 128;
+        case 256: return 256 / Tile<256, C, GAMMA_INV, false>::T * 256;
+        case 512: return 512 / Tile<512, C, GAMMA_INV, false>::T * 512;
+        case 1024: return 1024 / Tile<1024, C, GAMMA_INV, false>::T * 1024;
         default: return 0;
     }
 }
