@@ -174,7 +174,7 @@ int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
  *   launch     index of the DWT launch (0 <= launch < number of launches).
  *   direction  0 = forward DWT, 1 = inverse DWT.
  *   waves, subsets  one of the built shapes (waves x subsets of 64 beta
- *              samples per wave): 1x1, 2x1, 4x1, 8x1, 1x2, 2x2, 4x2, 8x2, 16x1,
+ *              samples per wave): 1x1, 2x1, 4x1, 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4,
  *              covering the launch: waves * subsets * 64 >= its largest 2B;
  *              or, for the inverse (direction 1), 0x0: the inverse DWT by
  *              Clenshaw's backward summation over degrees (FP64 vector

@@ -257,9 +257,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         xv[h] = tab.cosb[it.jbase + (j < N ? j : 0)];
         sv[h] = tab.seed[it.seed_off + (j < N ? j : 0)];
     }
-    // s_l of the group's rows (at most one per thread: L <= B <= NW*NSUB*32),
-    // read in the panel epilogues (visible after the first panel's barrier)
-    const double rs = tab.rscale[goff + min((int)threadIdx.x, L - 1)];
+    // s_l of the group's rows (L <= B <= NW*NSUB*32, so at most RSN per
+    // thread), read in the panel epilogues (visible after the first panel's
+    // barrier)
+    constexpr int RSN = (NSUB + 1) / 2;
+    double rs[RSN];
+#pragma unroll
+    for (int q = 0; q < RSN; ++q) rs[q] = tab.rscale[goff + min((int)threadIdx.x + q * NW * 64, L - 1)];
     __builtin_amdgcn_sched_barrier(0);
 
     R xb[NSUB][16];
@@ -280,7 +284,9 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         ecur[h] = jin ? sv[h] : 0.0;
         eprev[h] = 0.0;
     }
-    if ((int)threadIdx.x < L) srow[threadIdx.x] = rs;
+#pragma unroll
+    for (int q = 0; q < RSN; ++q)
+        if ((int)threadIdx.x + q * NW * 64 < L) srow[threadIdx.x + q * NW * 64] = rs[q];
     double *pan = panel[wave];
     R *out = reinterpret_cast<R *>(coeffs + it.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
@@ -330,7 +336,10 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 #pragma unroll
             for (int r = 0; r < 4; ++r) tot[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
         } else {
+            // FP32 head chains of at most two subsets (32 samples), added in FP64
             v4f acc[4], acl[1];  // acl: the split mode's tail products
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[r] = 0.0;
             acl[0] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int a = 0; a < 4; ++a) acc[a] = (v4f){0.f, 0.f, 0.f, 0.f};
@@ -367,13 +376,21 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
                             bf4(a[4 * t].y, a[4 * t + 1].y, a[4 * t + 2].y, a[4 * t + 3].y),
                             bf4(xb[h][4 * t], xb[h][4 * t + 1], xb[h][4 * t + 2], xb[h][4 * t + 3]), acl[0], 0, 0, 0);
                 }
-            }
+                // the head's chains go to FP64 every two subsets; the tail
+                // (about 2^-24 of the value) keeps one chain and joins last
+                if (h % 2 == 1 || h == NSUB - 1) {
+                    if (h != NSUB - 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double t = PR == P32S ? (double)acl[0][r] : 0.0;
+                    for (int r = 0; r < 4; ++r) {
+                        double t = PR == P32S && h == NSUB - 1 ? (double)acl[0][r] : 0.0;
 #pragma unroll
-                for (int a = 0; a < 4; ++a) t += (double)acc[a][r];
-                tot[r] = t;
+                        for (int a = 0; a < 4; ++a) t += (double)acc[a][r];
+                        tot[r] += t;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) acc[a] = (v4f){0.f, 0.f, 0.f, 0.f};
+                    if (h != NSUB - 1) __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
         // The wave's panel is free once its A operands are in registers: park
@@ -658,7 +675,8 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
 }
 
 // Launch shapes (waves x subsets of 64 beta samples per wave): 1x1, 2x1, 4x1,
-// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1; a shape covers items with 2B <= waves*subsets*64.
+// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4; a shape covers items with
+// 2B <= waves*subsets*64.
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
@@ -680,6 +698,7 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_FWD(2, 2)
     SOFT_DWT_FWD(4, 2)
     SOFT_DWT_FWD(8, 2)
+    SOFT_DWT_FWD(4, 4)
     SOFT_DWT_FWD(16, 1)
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
@@ -706,6 +725,7 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_INV(2, 2)
     SOFT_DWT_INV(4, 2)
     SOFT_DWT_INV(8, 2)
+    SOFT_DWT_INV(4, 4)
     SOFT_DWT_INV(16, 1)
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;

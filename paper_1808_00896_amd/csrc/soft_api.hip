@@ -234,13 +234,17 @@ int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double 
 // Default DWT launch shape (waves per block, subsets of 64 beta samples per
 // wave) of length N = 2B, forward and inverse: the fastest shape measured per
 // length on MI355X (SOFT_PLAN_TUNE re-measures on the plan itself).
-std::pair<int, int> shape_for(int N, bool forward) {
+std::pair<int, int> shape_for(int N, bool forward, int precision) {
     if (N <= 32) return {1, 1};
     if (N == 64) return forward ? std::make_pair(1, 1) : std::make_pair(2, 1);
     if (N == 128) return {2, 1};
     if (N == 256) return forward ? std::make_pair(2, 2) : std::make_pair(4, 1);
     if (N == 512) return {4, 2};
-    return {8, 2};
+    // 2B = 1024: four waves of four subsets, two blocks per CU, except for the
+    // FP32 inverses (FP32: 8x2; FP32-split, whose four-subset inverse needs
+    // more registers than two blocks leave: 16x1)
+    if (forward || precision == SOFT_FP64) return {4, 4};
+    return precision == SOFT_FP32 ? std::make_pair(8, 2) : std::make_pair(16, 1);
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SOFT_OK : SOFT_ERR_HIP; }
@@ -435,7 +439,7 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
 
 // DWT launch shapes the library instantiates (waves, subsets of 64 beta
 // samples per wave).
-constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}};
+constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}, {4, 4}};
 
 // Autotuner: for every DWT launch group and direction, time each shape that
 // covers the group's largest 2B (and is at most twice that), and for the
@@ -650,8 +654,8 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             }
             LaunchGroup lg;
             const int len = keys[gi] ? keys[gi] : 256;
-            std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true);
-            std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false);
+            std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision);
+            std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision);
             lg.bands = group_bands[gi];
             for (int bi : group_bands[gi]) lg.nmax = std::max(lg.nmax, p->bands[bi].N);
             lg.nitems = (int)lists[gi].size();

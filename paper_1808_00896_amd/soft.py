@@ -135,7 +135,7 @@ def soft_plan_describe(plan):
     return json.loads(buf.value.decode())
 
 
-DWT_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (8, 2), (16, 1))
+DWT_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (8, 2), (16, 1), (4, 4))
 CLENSHAW = (0, 0)  # inverse-DWT "shape" of the Clenshaw kernel (soft_plan_set_dwt_shape)
 
 
