@@ -584,14 +584,16 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             for (const Band &b : p->bands)
                 p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
 
-        // DWT launch groups: in a plan of several bands, all bands with
-        // 2B <= 256 share one launch (with the 2B = 256 shapes); every other
-        // length has its own.
+        // DWT launch groups: in a plan of several bands, the bands with
+        // 2B <= 64 share one launch (with the 2B = 64 shapes); every other
+        // length has its own (sharing one launch down from 2B = 256 left the
+        // lanes of the shorter bands idle: 2-3 % slower on the 256-function
+        // batch of B = 16 ... 128).
         const bool merged = p->bands.size() > 1;
         std::vector<int> keys;  // 0 for the shared launch, else 2B
         std::vector<std::vector<int>> group_bands;
         for (size_t bi = 0; bi < p->bands.size(); ++bi) {
-            const int key = merged && p->bands[bi].N <= 256 ? 0 : p->bands[bi].N;
+            const int key = merged && p->bands[bi].N <= 64 ? 0 : p->bands[bi].N;
             size_t gi = std::find(keys.begin(), keys.end(), key) - keys.begin();
             if (gi == keys.size()) {
                 keys.push_back(key);
@@ -653,7 +655,7 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
                 return SOFT_ERR_UNSUPPORTED;
             }
             LaunchGroup lg;
-            const int len = keys[gi] ? keys[gi] : 256;
+            const int len = keys[gi] ? keys[gi] : 64;
             std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision);
             std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision);
             lg.bands = group_bands[gi];
