@@ -106,6 +106,33 @@ __device__ __forceinline__ C twc(C a) {
     }
 }
 
+// Load of one complex input.  The stage-0 loads of a pass read every element
+// once; for 128 <= 2B <= 512 they are non-temporal, which measured faster for
+// the pass and the kernels after it (B = 128 step 0.652 -> 0.630 ms, FP32-split
+// 0.433 -> 0.403 ms; B = 256 5.58 -> 5.51 ms); at 2B = 1024 they slowed the
+// passes down (B = 512: 62.0 -> 63.8 ms per step) and below 128 they gave
+// nothing.
+template <int N>
+__device__ __forceinline__ double2 ld_in(const double2 *p) {
+    if constexpr (N >= 128 && N <= 512) {
+        typedef double r2 __attribute__((ext_vector_type(2)));
+        const r2 v = __builtin_nontemporal_load(reinterpret_cast<const r2 *>(p));
+        return make_double2(v[0], v[1]);
+    } else {
+        return *p;
+    }
+}
+template <int N>
+__device__ __forceinline__ float2 ld_in(const float2 *p) {
+    if constexpr (N >= 128 && N <= 512) {
+        typedef float r2 __attribute__((ext_vector_type(2)));
+        const r2 v = __builtin_nontemporal_load(reinterpret_cast<const r2 *>(p));
+        return make_float2(v[0], v[1]);
+    } else {
+        return *p;
+    }
+}
+
 // In-register DFT of R points: X[k] = sum_n x[n] e^{SIGN 2 pi i n k / R}.
 template <int R, int SIGN, typename C>
 __device__ __forceinline__ void dft(C *v) {
@@ -386,19 +413,19 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                 const int n = p_in + k * P + r * (N / R);
                 C x;
                 if constexpr (KIND == GAMMA_FWD) {
-                    x = src[((size_t)row * N + line) * N + n];
+                    x = ld_in<N>(&src[((size_t)row * N + line) * N + n]);
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    x = src[u_index<N, T, INGRID>(row, line, n)];
+                    x = ld_in<N>(&src[u_index<N, T, INGRID>(row, line, n)]);
                 } else if constexpr (KIND == ALPHA_INV) {
                     if (n == B) {
                         x = mk<C>(0.0, 0.0);
                     } else {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
-                        x = src[(size_t)(sl >> 1) * N + jj];
+                        x = ld_in<N>(&src[(size_t)(sl >> 1) * N + jj]);
                     }
                 } else {
-                    x = n == B ? mk<C>(0.0, 0.0) : src[u_index<N, T, INGRID>(line, n, row)];
+                    x = n == B ? mk<C>(0.0, 0.0) : ld_in<N>(&src[u_index<N, T, INGRID>(line, n, row)]);
                 }
                 v[k * R + r] = x;
             }
