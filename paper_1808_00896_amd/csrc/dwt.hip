@@ -233,7 +233,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 
     // Every load of the prologue goes out before any is used, so they are
     // all in flight at once: the recurrence coefficients of the first panel
-    // (scalar), the S block, cos b_j and seeds, and s_l of the lane's row.
+    // (scalar), the S block (read once: non-temporal loads, about 1 % off the
+    // B = 128 step), cos b_j and seeds, and s_l of the lane's row.
     double2 c[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
@@ -251,7 +252,11 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 #pragma unroll
         for (int s = 0; s < 16; s += 2) {
             const int jl = jbase + 4 * s + krow + (odd ? 4 : 0);
-            raw[h][s / 2] = Sg[(size_t)(col >> 1) * N + (jl < N ? jl : 0)];
+            typedef R r2 __attribute__((ext_vector_type(2)));
+            const r2 v = __builtin_nontemporal_load(
+                reinterpret_cast<const r2 *>(Sg + (size_t)(col >> 1) * N + (jl < N ? jl : 0)));
+            raw[h][s / 2].x = v[0];
+            raw[h][s / 2].y = v[1];
         }
         const int j = jbase + lane;
         xv[h] = tab.cosb[it.jbase + (j < N ? j : 0)];
