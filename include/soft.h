@@ -89,7 +89,7 @@ typedef enum {
  *                   plan's own work list with zeroed data, and keep the
  *                   fastest.  Costs a few
  *                   DWT launches per candidate at plan creation; without it
- *                   a fixed shape per 2B is used.
+ *                   a fixed shape per 2B, direction and precision is used.
  *   SOFT_INPLACE_OK the plan may use the grid buffers as scratch, and holds
  *                   no FFT intermediate of its own (that saves (2B)^3 complex
  *                   elements per function of the largest band: 16 GiB at
