@@ -139,10 +139,11 @@ def test_uneven_offsets_and_sizes(dev):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_split"])
 def test_uneven_large_bands_match_single_plans(dev, prec):
-    """B = 256 and 512 inside an uneven plan keep their own DWT launches and
-    FFT passes: bit-identical to one-bandwidth plans.  The small bands share
-    the merged launch and agree to the precision's bar."""
-    Bs = [256, 8, 512, 2] if prec == "fp32_split" else [256, 8, 2]
+    """Bands of 2B >= 128 (here B = 64, 256 and 512) inside an uneven plan
+    keep their own DWT launches and FFT passes: bit-identical to
+    one-bandwidth plans.  The bands of 2B <= 64 share one launch and agree to
+    the precision's bar."""
+    Bs = [256, 8, 512, 64, 2] if prec == "fp32_split" else [256, 8, 64, 2]
     cs = [inputs.coeffs_decay(B, 100 + i) for i, B in enumerate(Bs)]
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     with soft.UnevenPlan(Bs, precision=prec) as p:
@@ -156,7 +157,7 @@ def test_uneven_large_bands_match_single_plans(dev, prec):
                 gs = q.inverse(to_dev(cs[f], dev, prec))
                 cs2 = q.forward(gs)
                 torch.cuda.synchronize()
-                if B >= 256:
+                if B >= 64:
                     assert torch.equal(grids[f], gs), B
                     assert torch.equal(coefs[f], cs2), B
                 else:
