@@ -214,13 +214,20 @@ enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
 // plan's intermediate take half that (64-byte runs in FP64, two blocks per
 // CU), which measured faster for both of them (FP64: 7.8 -> 7.5 and 8.0 ->
 // 7.7 ms); the forward passes were slower with it, and so were the inverse
-// passes staging in the grid (INGRID).  The two passes of one direction share
-// T, which fixes the layout of their intermediate.
+// passes staging in the grid (INGRID).  The intermediate of a direction is
+// laid out by its gamma pass's T (TL); the complex64 forward alpha pass at
+// 2B = 1024 reads it with half-height blocks (two blocks of 8 rows per
+// 16-row layout tile, each still one contiguous run of 8N elements): 5.2 ->
+// 4.8 ms at B = 512, where the gamma pass is faster with the full tile.
 template <int N, typename C, int KIND, bool INGRID>
 struct Tile {
     static constexpr int TF = N <= 64 ? 32 : (N <= 256 ? 16 : (sizeof(C) == 16 ? 8 : 16));
-    static constexpr int T0 = N >= 1024 && !INGRID && (KIND == ALPHA_INV || KIND == GAMMA_INV) ? TF / 2 : TF;
+    static constexpr bool INV = KIND == ALPHA_INV || KIND == GAMMA_INV;
+    static constexpr int TL0 = N >= 1024 && !INGRID && INV ? TF / 2 : TF;
+    static constexpr int T0 =
+        N >= 1024 && !INGRID && (INV || (KIND == ALPHA_FWD && sizeof(C) == 8)) ? TF / 2 : TF;
     static constexpr int T = T0 < N ? T0 : N;
+    static constexpr int TL = TL0 < N ? TL0 : N;
     static constexpr int NT = T * Shape<N>::P;
     static constexpr int LDS = Shape<N>::P > 1 ? T * Shape<N>::RS : 1;
 };
@@ -368,6 +375,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     const bool apply_w = flags & kFlagScale, stream = N <= 512 && (flags & kFlagStream);
     using Sh = Shape<N>;
     constexpr int T = Tile<N, C, KIND, INGRID>::T, P = Sh::P, E = Sh::E, NSTG = Sh::NSTAGE;
+    constexpr int TL = Tile<N, C, KIND, INGRID>::TL;  // layout of the intermediate
     constexpr int B = N / 2;
     constexpr int LAST = NSTG - 1;
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
@@ -415,7 +423,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                 if constexpr (KIND == GAMMA_FWD) {
                     x = ld_in<N>(&src[((size_t)row * N + line) * N + n]);
                 } else if constexpr (KIND == ALPHA_FWD) {
-                    x = ld_in<N>(&src[u_index<N, T, INGRID>(row, line, n)]);
+                    x = ld_in<N>(&src[u_index<N, TL, INGRID>(row, line, n)]);
                 } else if constexpr (KIND == ALPHA_INV) {
                     if (n == B) {
                         x = mk<C>(0.0, 0.0);
@@ -425,7 +433,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                         x = ld_in<N>(&src[(size_t)(sl >> 1) * N + jj]);
                     }
                 } else {
-                    x = n == B ? mk<C>(0.0, 0.0) : ld_in<N>(&src[u_index<N, T, INGRID>(line, n, row)]);
+                    x = n == B ? mk<C>(0.0, 0.0) : ld_in<N>(&src[u_index<N, TL, INGRID>(line, n, row)]);
                 }
                 v[k * R + r] = x;
             }
@@ -468,7 +476,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                 const int n = p_out + k * P + r * (N / R);
                 const C x = v[k * R + r];
                 if constexpr (KIND == GAMMA_FWD) {
-                    if (n != B) put_c(&dst[u_index<N, T, INGRID>(line, n, row)], x, stream);
+                    if (n != B) put_c(&dst[u_index<N, TL, INGRID>(line, n, row)], x, stream);
                 } else if constexpr (KIND == ALPHA_FWD) {
                     if (n != B) {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
@@ -476,7 +484,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                         put_c(&dst[(size_t)(sl >> 1) * N + jj], cscale(x, wj), stream);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
-                    put_c(&dst[u_index<N, T, INGRID>(row, line, n)], x, stream);
+                    put_c(&dst[u_index<N, TL, INGRID>(row, line, n)], x, stream);
                 } else if constexpr (ARGMAX) {
                     best = arg_better(best, ArgBest{(double)cscale(x, wj).x, ((long long)row * N + line) * N + n});
                 } else {
