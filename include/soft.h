@@ -283,9 +283,11 @@ int soft_plan_set_timing_stages(soft_plan_t plan, unsigned mask);
 int soft_plan_stage_times(soft_plan_t plan, double *ms, long long *launches, int reset);
 
 /*
- * soft_plan_destroy -- release the plan's device memory.  Synchronises the
- * device first so no enqueued work still uses the workspace.  NULL is
- * accepted and ignored.  Returns SOFT_OK or SOFT_ERR_HIP.
+ * soft_plan_destroy -- release the plan's device memory.  Waits first for
+ * the work of the plan's last transform call (an event recorded on that
+ * call's stream), so no enqueued work still uses the workspace; other streams
+ * and other work on the device are not waited for.  NULL is accepted and
+ * ignored.  Returns SOFT_OK or SOFT_ERR_HIP.
  */
 int soft_plan_destroy(soft_plan_t plan);
 
@@ -371,7 +373,8 @@ int soft_match_argmax(soft_match_t match, const void *grid, long long *index, hi
  */
 int soft_match(soft_match_t match, const void *a, const void *b, void *grid, long long *index, hipStream_t stream);
 
-/* soft_match_destroy -- release the head and its soft_plan (synchronises the device; NULL ignored). */
+/* soft_match_destroy -- release the head and its soft_plan, after waiting for the
+ * work of its last call as soft_plan_destroy does (NULL ignored). */
 int soft_match_destroy(soft_match_t match);
 
 /* soft_status_string -- static text for a status code (never NULL). */

@@ -82,6 +82,10 @@ struct soft_plan_s {
     std::vector<Pending> pending;
     double stage_ms[SOFT_NUM_STAGES] = {};
     long long stage_n[SOFT_NUM_STAGES] = {};
+    // End of the last call's work, recorded on its stream: destroy waits for
+    // it instead of for the whole device.
+    hipEvent_t done = nullptr;
+    bool done_recorded = false;
 };
 
 // Rotational-matching head: n pairs of functions on the sphere at bandwidth
@@ -108,6 +112,7 @@ void free_plan(soft_plan_s *p) {
     if (!p) return;
     for (hipEvent_t e : p->free_events) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->used_events) (void)hipEventDestroy(e);
+    if (p->done) (void)hipEventDestroy(p->done);
     if (p->tables) (void)hipFree(p->tables);
     if (p->S) (void)hipFree(p->S);
     if (p->t1) (void)hipFree(p->t1);
@@ -248,6 +253,16 @@ std::pair<int, int> shape_for(int N, bool forward, int precision) {
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SOFT_OK : SOFT_ERR_HIP; }
+
+// Marks the end of a call's work on its stream (what soft_plan_destroy waits for).
+hipError_t mark_done(soft_plan_s *p, hipStream_t s) {
+    const hipError_t e = hipEventRecord(p->done, s);
+    p->done_recorded = p->done_recorded || e == hipSuccess;
+    return e;
+}
+
+// Waits for the last call's work on the plan (a no-op before the first call).
+hipError_t wait_done(soft_plan_s *p) { return p->done_recorded ? hipEventSynchronize(p->done) : hipSuccess; }
 
 int check_call(soft_plan_t plan, const void *a, const void *b) {
     if (!plan || !a || !b) return SOFT_ERR_INVALID;
@@ -411,6 +426,7 @@ int dispatch(soft_plan_t p, const void *in, void *out, hipStream_t s, bool forwa
                         : run_inverse<soft::P32S>(p, in, out, s, scaled);
             break;
     }
+    if (e == hipSuccess) e = mark_done(p, s);
     return hip_status(e);
 }
 
@@ -518,7 +534,7 @@ int tune_dwt(soft_plan_s *p) {
             default: e = tune_dwt_prec<soft::P32S>(p, coeffs); break;
         }
     }
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     (void)hipFree(coeffs);
     return hip_status(e);
 }
@@ -707,7 +723,8 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             (p->t1_elems && hipMalloc(&p->t1, p->t1_elems * p->csize) != hipSuccess) ||
             hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
             hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess ||
-            hipMalloc(&p->seed, p->seed_total * sizeof(double)) != hipSuccess) {
+            hipMalloc(&p->seed, p->seed_total * sizeof(double)) != hipSuccess ||
+            hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
             free_plan(p);
             return SOFT_ERR_OOM;
@@ -755,7 +772,7 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             if (e == hipSuccess) e = soft::launch_fill_recurrence(b.view, p->rec, p->rscale, 0);
             if (e == hipSuccess) e = soft::launch_fill_seeds(b.view, p->seed + b.seed_base, 0);
         }
-        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e == hipSuccess && (flags & SOFT_PLAN_TUNE)) {
             const int rc = tune_dwt(p);
             if (rc != SOFT_OK) {
@@ -917,7 +934,7 @@ int soft_plan_stage_times(soft_plan_t p, double *ms, long long *launches, int re
 
 int soft_plan_destroy(soft_plan_t p) {
     if (!p) return SOFT_OK;
-    const hipError_t e = hipDeviceSynchronize();
+    const hipError_t e = wait_done(p);
     free_plan(p);
     return hip_status(e);
 }
@@ -1002,6 +1019,7 @@ int soft_match_argmax(soft_match_t m, const void *grid, long long *index, hipStr
         e = soft::launch_argmax_real<double2>(static_cast<const double2 *>(grid), N3, m->n, m->part, index, s);
     else
         e = soft::launch_argmax_real<float2>(static_cast<const float2 *>(grid), N3, m->n, m->part, index, s);
+    if (e == hipSuccess) e = mark_done(m->plan, s);
     return hip_status(e);
 }
 
@@ -1018,12 +1036,13 @@ int soft_match(soft_match_t m, const void *a, const void *b, void *grid, long lo
         case SOFT_FP32: e = run_match<soft::P32>(m, a, b, grid, index, s); break;
         default: e = run_match<soft::P32S>(m, a, b, grid, index, s); break;
     }
+    if (e == hipSuccess) e = mark_done(m->plan, s);
     return hip_status(e);
 }
 
 int soft_match_destroy(soft_match_t m) {
     if (!m) return SOFT_OK;
-    const hipError_t e = hipDeviceSynchronize();
+    const hipError_t e = wait_done(m->plan);
     free_match(m);
     return hip_status(e);
 }

@@ -224,6 +224,40 @@ def test_adjoints_match_brute_force(oracle, B):
     np.testing.assert_allclose(oracle.adjoint_inverse(B, g), want_adji, atol=1e-13 * np.abs(want_adji).max())
 
 
+@pytest.mark.parametrize("B", [1, 2, 3, 4])
+def test_idwt_matches_explicit_sum(oracle, B):
+    """S'(j; m, m') = sum_l d(l,m,m';b_j) f°(l,m,m') (the T_B^T step of the
+    matrix form, Sect. 2.4), element by element against d from the explicit
+    Jacobi form, in the [m+B-1][m'+B-1][j] layout."""
+    c = inputs.coeffs_uniform(B, 1100 + B)
+    N = 2 * B
+    beta = (2 * np.arange(N) + 1) * np.pi / (4 * B)
+    want = np.zeros((2 * B - 1, 2 * B - 1, N), np.complex128)
+    for (l, m, mp) in _lmm(B):
+        want[m + B - 1, mp + B - 1, :] += d_any(l, m, mp, beta) * c[l * (4 * l * l - 1) // 3 + (m + l) * (2 * l + 1) + (mp + l)]
+    for prec in ("f64", "f80"):
+        got = oracle.idwt(B, c, prec)
+        assert got.shape == want.shape
+        assert np.abs(got - want).max() <= 1e-14 * max(1.0, np.abs(want).max()), prec
+
+
+@pytest.mark.parametrize("B", [5, 8])
+def test_idwt_is_the_grid_frequency_content(oracle, B):
+    """The unnormalised e^{+i} 2-D DFT of each beta-slice of the inverse grid
+    recovers (2B)^2 S'(j; m, m') for |m|, |m'| < B (eq.
+    "fourier_representation" with the +-B bin empty), checked with numpy's
+    FFT on a grid from the brute-force inverse."""
+    c = inputs.coeffs_decay(B, 1200 + B)
+    g = inverse_brute(B, c)
+    S = oracle.idwt(B, c)
+    N = 2 * B
+    for j in range(N):
+        F = np.fft.ifft2(g[:, j, :]) * N * N
+        for m in range(1 - B, B):
+            for mp in range(1 - B, B):
+                assert abs(F[m % N, mp % N] - N * N * S[m + B - 1, mp + B - 1, j]) < 1e-11 * N * N
+
+
 # --------------------------------------------------------------------------
 # Invariants at larger B
 # --------------------------------------------------------------------------
