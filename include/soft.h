@@ -373,6 +373,28 @@ int soft_match_argmax(soft_match_t match, const void *grid, long long *index, hi
  */
 int soft_match(soft_match_t match, const void *a, const void *b, void *grid, long long *index, hipStream_t stream);
 
+/*
+ * soft_match_argmax_noalloc -- soft_match_argmax without a head, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that forbid hipMalloc): the same result for n grids of bandwidth B,
+ * with the partial results in a 1 MiB array that the library holds in static
+ * device memory on every GPU it runs on until the process ends.  Calls no
+ * allocating routine; its first call on a device looks up that device's copy
+ * of the array.
+ *   B          bandwidth of the grids, a power of two <= 512.
+ *   n          number of grids, 1 <= n <= 65535 (every such n fits the array).
+ *   precision  a soft_precision: complex128 grids for SOFT_FP64, complex64
+ *              otherwise.
+ *   grid       device, n grids of (2B)^3 elements back to back (read only).
+ *   index      device, n int64 (written), as soft_match_argmax.
+ * Every call on one GPU shares that GPU's array, so calls that overlap in
+ * time on one GPU (two streams, two host threads) race: serialise them.
+ * Returns SOFT_OK, SOFT_ERR_INVALID (NULL pointer, B < 1, n < 1, unknown
+ * precision), SOFT_ERR_UNSUPPORTED (B not a power of two or > 512, n > 65535)
+ * or SOFT_ERR_HIP.
+ */
+int soft_match_argmax_noalloc(int B, int n, int precision, const void *grid, long long *index, hipStream_t stream);
+
 /* soft_match_destroy -- release the head and its soft_plan, after waiting for the
  * work of its last call as soft_plan_destroy does (NULL ignored). */
 int soft_match_destroy(soft_match_t match);

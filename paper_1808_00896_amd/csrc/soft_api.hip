@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -792,6 +793,39 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
     return SOFT_OK;
 }
 
+// Allocation-free argmax: its partial results live in this file-scope device
+// array (1 MiB on every GPU the library runs on, held until the process ends)
+// instead of a plan's buffer.  argmax_blocks() deals about 4096 blocks over all
+// grids and at least one per grid, so n <= kArgmaxScratchEntries grids always
+// fit.  In host code `scratch` only names the symbol: kernels get its device
+// address, looked up once per device with that device current.
+constexpr int kArgmaxScratchEntries = 65536;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) soft::ArgBest scratch[kArgmaxScratchEntries];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).
+int scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SOFT_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return SOFT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return SOFT_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SOFT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1020,6 +1054,23 @@ int soft_match_argmax(soft_match_t m, const void *grid, long long *index, hipStr
     else
         e = soft::launch_argmax_real<float2>(static_cast<const float2 *>(grid), N3, m->n, m->part, index, s);
     if (e == hipSuccess) e = mark_done(m->plan, s);
+    return hip_status(e);
+}
+
+int soft_match_argmax_noalloc(int B, int n, int precision, const void *grid, long long *index, hipStream_t s) {
+    if (B < 1 || n < 1 || !grid || !index || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!is_pow2(B) || B > 512 || n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
+    const long long N3 = 8LL * B * B * B;
+    if (soft::argmax_workspace_bytes(N3, n) > sizeof(soft::ArgBest) * (size_t)kArgmaxScratchEntries)
+        return SOFT_ERR_UNSUPPORTED;
+    void *part = nullptr;
+    const int rc = scratch_address(&part);
+    if (rc != SOFT_OK) return rc;
+    hipError_t e;
+    if (precision == SOFT_FP64)
+        e = soft::launch_argmax_real<double2>(static_cast<const double2 *>(grid), N3, n, part, index, s);
+    else
+        e = soft::launch_argmax_real<float2>(static_cast<const float2 *>(grid), N3, n, part, index, s);
     return hip_status(e);
 }
 

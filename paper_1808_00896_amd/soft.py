@@ -69,10 +69,12 @@ def lib():
         L.soft_match_coeffs.argtypes = [vp, vp, vp, vp, vp]
         L.soft_match_coeffs_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.soft_match_argmax.argtypes = [vp, vp, vp, vp]
+        L.soft_match_argmax_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.soft_match.argtypes = [vp, vp, vp, vp, vp, vp]
         L.soft_match_destroy.argtypes = [vp]
         for name in ("soft_match_plan", "soft_match_sizes", "soft_match_plan_soft", "soft_match_coeffs",
-                     "soft_match_coeffs_vjp", "soft_match_argmax", "soft_match", "soft_match_destroy"):
+                     "soft_match_coeffs_vjp", "soft_match_argmax", "soft_match_argmax_noalloc", "soft_match",
+                     "soft_match_destroy"):
             getattr(L, name).restype = ctypes.c_int
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
@@ -234,6 +236,12 @@ def soft_match_coeffs_vjp(match, a, b, g, ga, gb, stream=None):
 def soft_match_argmax(match, grid, index, stream=None):
     _check(lib().soft_match_argmax(ctypes.c_void_p(match), _ptr(grid), _ptr(index), _stream(stream)),
            "soft_match_argmax")
+
+
+def soft_match_argmax_noalloc(B, n, precision, grid, index, stream=None):
+    """Argmax of Re over n grids of bandwidth B without a head (no allocation)."""
+    _check(lib().soft_match_argmax_noalloc(int(B), int(n), int(precision), _ptr(grid), _ptr(index),
+                                           _stream(stream)), "soft_match_argmax_noalloc")
 
 
 def soft_match(match, a, b, grid, index, stream=None):

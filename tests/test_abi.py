@@ -99,6 +99,15 @@ def test_match_argument_errors_need_no_gpu(L):
     assert L.soft_match_coeffs(None, None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_coeffs_vjp(None, None, None, None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_argmax(None, None, None, None) == soft.SOFT_ERR_INVALID
+    one = ctypes.c_void_p(16)  # never dereferenced: the arguments are rejected first
+    assert L.soft_match_argmax_noalloc(8, 2, 0, None, one, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_argmax_noalloc(8, 2, 0, one, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_argmax_noalloc(0, 2, 0, one, one, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_argmax_noalloc(8, 0, 0, one, one, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_argmax_noalloc(8, 2, 3, one, one, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_argmax_noalloc(12, 2, 0, one, one, None) == soft.SOFT_ERR_UNSUPPORTED
+    assert L.soft_match_argmax_noalloc(1024, 2, 0, one, one, None) == soft.SOFT_ERR_UNSUPPORTED
+    assert L.soft_match_argmax_noalloc(8, 65536, 0, one, one, None) == soft.SOFT_ERR_UNSUPPORTED
     assert L.soft_match_sizes(None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan_soft(None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_destroy(None) == soft.SOFT_OK
