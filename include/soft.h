@@ -84,8 +84,8 @@ typedef enum {
  * Plan flags (bitwise or).
  *   SOFT_PLAN_TUNE  at plan time, time every DWT launch shape (waves per
  *                   block, beta samples per lane) that fits each DWT launch,
- *                   forward and inverse separately, and for the inverse also
- *                   the Clenshaw form (see soft_plan_set_dwt_shape), on the
+ *                   forward and inverse separately, and also the Clenshaw
+ *                   form of each direction (see soft_plan_set_dwt_shape), on the
  *                   plan's own work list with zeroed data, and keep the
  *                   fastest.  Costs a few
  *                   DWT launches per candidate at plan creation; without it
@@ -99,8 +99,18 @@ typedef enum {
  *                   soft_adjoint stage in their output grid.  Results are
  *                   bit-identical to a plan without the flag; the FFT passes
  *                   move shorter runs and are somewhat slower.
+ *   SOFT_PLAN_GRAPH each transform call (soft_forward, soft_inverse,
+ *                   soft_adjoint, soft_adjoint_inverse) launches a HIP graph
+ *                   of its kernels, captured on a plan-owned stream at the
+ *                   first call of that kind and captured again (the
+ *                   executable graph updated) when the call's input or output
+ *                   pointer differs from the last capture; a replay with the
+ *                   same pointers costs one graph launch instead of one
+ *                   launch per kernel.  Results are bit-identical to calls
+ *                   without the flag.  Calls made while stage timing is
+ *                   enabled run without the graph.
  */
-enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u };
+enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u, SOFT_PLAN_GRAPH = 4u };
 
 typedef enum {
     SOFT_OK = 0,
@@ -117,8 +127,8 @@ typedef enum {
  *   B          bandwidth, a power of two with 1 <= B <= 512.
  *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
- *   flags      0, SOFT_PLAN_TUNE, SOFT_INPLACE_OK or both; other bits are
- *              SOFT_ERR_INVALID.
+ *   flags      any of SOFT_PLAN_TUNE, SOFT_INPLACE_OK and SOFT_PLAN_GRAPH;
+ *              other bits are SOFT_ERR_INVALID.
  *   out        receives the plan handle; unchanged on error.
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
@@ -149,6 +159,19 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
 int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, soft_plan_t *out);
 
 /*
+ * soft_plan_check -- build the host side of a plan for the bandwidths
+ * B_list[0..n) (its tables of Sect. 2.2-2.4 and its DWT work lists) without
+ * touching a device, check it, and release it: every (function, symmetry
+ * group) in exactly one work item, every order pair of every function in
+ * exactly one group slot (eq. "Wigner_symmetries"), every offset inside its
+ * buffer, every launch shape covering its launch.  For testing the plan logic
+ * on hosts without a GPU.  Arguments as for soft_plan_uneven.  Returns
+ * SOFT_OK, SOFT_ERR_INVALID (bad arguments, or a check failed),
+ * SOFT_ERR_UNSUPPORTED or SOFT_ERR_OOM.
+ */
+int soft_plan_check(const int *B_list, int n, int precision, unsigned flags);
+
+/*
  * soft_plan_sizes -- element counts of one call's buffers.
  *   grid_elems   complex elements of all grids of the plan (sum of (2B)^3).
  *   coeff_elems  complex elements of all coefficient vectors (sum of B(4B^2-1)/3).
@@ -176,10 +199,13 @@ int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
  *   waves, subsets  one of the built shapes (waves x subsets of 64 beta
  *              samples per wave): 1x1, 2x1, 4x1, 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4,
  *              covering the launch: waves * subsets * 64 >= its largest 2B;
- *              or, for the inverse (direction 1), 0x0: the inverse DWT by
- *              Clenshaw's backward summation over degrees (FP64 vector
- *              arithmetic, one beta sample per lane) instead of the matrix
- *              contraction.  soft_plan_describe reports it as [0, 0].
+ *              or 0x0: the DWT by Clenshaw-type recurrences on the FP64
+ *              vector unit instead of the matrix contraction (Sect. 2.4),
+ *              one beta sample per lane: the inverse by Clenshaw's backward
+ *              summation over degrees, the forward by its transpose (the
+ *              adjoint-Clenshaw evaluation: each lane runs the three-term
+ *              recurrence forward and the sums over beta are reduced across
+ *              lanes).  soft_plan_describe reports it as [0, 0].
  * Takes effect for later calls.  Returns SOFT_OK or SOFT_ERR_INVALID.
  */
 int soft_plan_set_dwt_shape(soft_plan_t plan, int launch, int direction, int waves, int subsets);
@@ -398,6 +424,30 @@ int soft_match_argmax_noalloc(int B, int n, int precision, const void *grid, lon
 /* soft_match_destroy -- release the head and its soft_plan, after waiting for the
  * work of its last call as soft_plan_destroy does (NULL ignored). */
 int soft_match_destroy(soft_match_t match);
+
+/*
+ * Device ceilings (measurement support, not part of the transform): kernels
+ * of this library that measure what the GPU sustains, so that the roofline
+ * fractions of the transform kernels can be read against measured rates as
+ * well as the published peaks.
+ *
+ * soft_probe_copy -- copy `bytes` (a multiple of 16) from src to dst, both
+ *   device pointers, with non-temporal loads and stores (every byte read
+ *   once and written once: 2 * bytes of HBM traffic).  Returns SOFT_OK,
+ *   SOFT_ERR_INVALID (NULL pointer, bytes 0 or not a multiple of 16) or
+ *   SOFT_ERR_HIP.
+ * soft_probe_flops -- run a dependent-chain arithmetic loop on `blocks`
+ *   blocks of four waves for `iters` iterations: kind 0 FP64 vector FMA,
+ *   1 FP64 matrix core (16x16x4 MFMA), 2 FP32 matrix core (16x16x4 MFMA).
+ *   sink: device, blocks * 256 doubles (kept as an output so the loop is not
+ *   removed; not written in practice).  Returns SOFT_OK, SOFT_ERR_INVALID or
+ *   SOFT_ERR_HIP.
+ * soft_probe_flop_count -- the flops one soft_probe_flops launch performs
+ *   (FMA = 2 flops); 0 for invalid arguments.
+ */
+int soft_probe_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
+int soft_probe_flops(int kind, int blocks, int iters, double *sink, hipStream_t stream);
+double soft_probe_flop_count(int kind, int blocks, int iters);
 
 /* soft_status_string -- static text for a status code (never NULL). */
 const char *soft_status_string(int status);

@@ -161,6 +161,17 @@ __device__ __forceinline__ void lds_wait_all() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Block barrier that orders LDS only: each wave's LDS operations complete
+// (lgkmcnt(0)) before it arrives, while its global loads, stores and LDS DMA
+// stay in flight.  A __syncthreads (or a fence on LDS alone, which must also
+// cover the LDS DMA) would wait for all of those with vmcnt(0).  The barrier
+// is an asm statement with a memory clobber, so the compiler keeps every
+// memory access on its side.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    asm volatile("s_barrier" ::: "memory");
+}
+
 // Value of the neighbouring lane (lane ^ 1): DPP quad_perm [1, 0, 3, 2].
 __device__ __forceinline__ int swap_pair_lanes(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
 __device__ __forceinline__ float swap_pair_lanes(float v) { return __int_as_float(swap_pair_lanes(__float_as_int(v))); }
@@ -193,105 +204,23 @@ __device__ __forceinline__ int out_row(int krow, int r) {
 // ---------------------------------------------------------------------------
 // Forward DWT: panel x X on MFMA.
 // ---------------------------------------------------------------------------
-// Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
-// into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds the
-// recurrence value at degree l0 + lp + r for j-local jl in the wave's own LDS
-// region.  Panel rows past the group's last degree hold values of the
-// continued recurrence; they only reach output rows that are never written.
-// A wave's LDS operations complete in order, so filling and reading its own
-// panel needs no block barrier.  Once its A operands are in registers, each
-// wave parks its 16 x 16 partial sums in its own panel; one barrier before
-// and one after the cross-wave FP64 sum (no separate reduction buffer, which
-// keeps four 4-wave blocks within a CU's LDS).  The recurrence
-// coefficients of a panel (16 x (alpha, gamma)) sit in scalar registers; the
-// next panel's are loaded after this panel's LDS reads, behind the MFMAs.
-// Four accumulators keep four MFMA chains in flight (in the FP32 modes each
-// covers 16 beta samples; the split mode keeps the lo products apart).
+// The panel loop of one forward work item: recurrence, panels, MFMA
+// contraction and the fused reorder epilogue (shared by both forward kernels).
+// On entry x, ecur and eprev hold each lane's cos b_j and first two
+// recurrence values, xb the B operand, c the first panel's recurrence
+// coefficients, and srow the item's s_l (visible after the first barrier).
 template <int NW, int NSUB, int PR>
-__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double2 *__restrict__ rec,
-                                                    const WorkItem *__restrict__ items, int nitems,
-                                                    const typename PrecT<PR>::C *__restrict__ S,
-                                                    typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
-    using C = typename PrecT<PR>::C;
+__device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd], const double *srow,
+                                                const WorkItem &it, const double2 *__restrict__ Rr,
+                                                double2 (&c)[16], typename PrecT<PR>::R (&xb)[NSUB][16],
+                                                double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
+                                                typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
     using R = typename PrecT<PR>::R;
-    // s_l of the group's degrees: at most B = NW*NSUB*32 for this shape.
-    __shared__ double panel[NW][16 * kRowFwd];
-    __shared__ double srow[NW * NSUB * 32];
-    const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
-    const int B = it.B, N = 2 * B;
+    const int B = it.B;
     const int m = it.m, mp = it.mp, mask = it.mask;
     const int L = B - m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long goff = it.goff;
-    const double2 *__restrict__ Rr = rec + goff;
-
-    const C *Sg = S + it.s_off;
-    // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
     const int col = lane & 15, krow = lane >> 4;
-    const bool col_present = (mask >> (col >> 1)) & 1;
-    const bool odd = col & 1;
-
-    // Every load of the prologue goes out before any is used, so they are
-    // all in flight at once: the recurrence coefficients of the first panel
-    // (scalar), the S block (read once: non-temporal loads, about 1 % off the
-    // B = 128 step), cos b_j and seeds, and s_l of the lane's row.
-    double2 c[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
-    // Lanes load whole complex samples: the even lane of a pair (re) that of
-    // step s, the odd lane (im) that of step s + 1; one swap of a half between
-    // the two lanes later leaves each with its part of both steps.  A load
-    // then reads 4 x 2 neighbouring samples, 128 contiguous bytes in FP64, per
-    // slot row.  Samples past N load sample 0 and, like absent slots, are
-    // zeroed: no branches.
-    C raw[NSUB][8];
-    double xv[NSUB], sv[NSUB];
-#pragma unroll
-    for (int h = 0; h < NSUB; ++h) {
-        const int jbase = (wave * NSUB + h) * 64;
-#pragma unroll
-        for (int s = 0; s < 16; s += 2) {
-            const int jl = jbase + 4 * s + krow + (odd ? 4 : 0);
-            typedef R r2 __attribute__((ext_vector_type(2)));
-            const r2 v = __builtin_nontemporal_load(
-                reinterpret_cast<const r2 *>(Sg + (size_t)(col >> 1) * N + (jl < N ? jl : 0)));
-            raw[h][s / 2].x = v[0];
-            raw[h][s / 2].y = v[1];
-        }
-        const int j = jbase + lane;
-        xv[h] = tab.cosb[it.jbase + (j < N ? j : 0)];
-        sv[h] = tab.seed[it.seed_off + (j < N ? j : 0)];
-    }
-    // s_l of the group's rows (L <= B <= NW*NSUB*32, so at most RSN per
-    // thread), read in the panel epilogues (visible after the first panel's
-    // barrier)
-    constexpr int RSN = (NSUB + 1) / 2;
-    double rs[RSN];
-#pragma unroll
-    for (int q = 0; q < RSN; ++q) rs[q] = tab.rscale[goff + min((int)threadIdx.x + q * NW * 64, L - 1)];
-    __builtin_amdgcn_sched_barrier(0);
-
-    R xb[NSUB][16];
-    double x[NSUB], ecur[NSUB], eprev[NSUB];
-#pragma unroll
-    for (int h = 0; h < NSUB; ++h) {
-        const int jbase = (wave * NSUB + h) * 64;
-#pragma unroll
-        for (int s = 0; s < 16; s += 2) {
-            const int j0 = jbase + 4 * s + krow, j1 = j0 + 4;
-            const C v = raw[h][s / 2];
-            const R recv = swap_pair_lanes(odd ? v.x : v.y);
-            xb[h][s] = col_present && j0 < N ? (odd ? recv : v.x) : (R)0;
-            xb[h][s + 1] = col_present && j1 < N ? (odd ? v.y : recv) : (R)0;
-        }
-        const bool jin = jbase + lane < N;
-        x[h] = jin ? xv[h] : 0.0;
-        ecur[h] = jin ? sv[h] : 0.0;
-        eprev[h] = 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < RSN; ++q)
-        if ((int)threadIdx.x + q * NW * 64 < L) srow[threadIdx.x + q * NW * 64] = rs[q];
     double *pan = panel[wave];
     R *out = reinterpret_cast<R *>(coeffs + it.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
@@ -402,7 +331,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         // the wave's 16 x 16 partial sums there for the cross-wave sum.
 #pragma unroll
         for (int r = 0; r < 4; ++r) pan[out_row<PR>(krow, r) * 16 + col] = tot[r];
-        __syncthreads();
+        lds_sync();
         // Epilogue (the reorder): column c = 2 slot + part of row lp + r is
         // f°(l, member of slot) up to the slot's symmetry sign, s_l and V_B.
 #pragma unroll
@@ -419,8 +348,110 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
             }
         }
         // every wave has read the partial sums before any panel is refilled
-        __syncthreads();
+        lds_sync();
     }
+}
+
+// Block = NW waves; wave w owns the j-range [w*NSUB*64, (w+1)*NSUB*64), split
+// into NSUB subsets of 64 (one j per lane each).  Panel slot (jl, r) holds the
+// recurrence value at degree l0 + lp + r for j-local jl in the wave's own LDS
+// region.  Panel rows past the group's last degree hold values of the
+// continued recurrence; they only reach output rows that are never written.
+// A wave's LDS operations complete in order, so filling and reading its own
+// panel needs no block barrier.  Once its A operands are in registers, each
+// wave parks its 16 x 16 partial sums in its own panel; one barrier before
+// and one after the cross-wave FP64 sum (no separate reduction buffer, which
+// keeps four 4-wave blocks within a CU's LDS).  The recurrence
+// coefficients of a panel (16 x (alpha, gamma)) sit in scalar registers; the
+// next panel's are loaded after this panel's LDS reads, behind the MFMAs.
+// Four accumulators keep four MFMA chains in flight (in the FP32 modes each
+// covers 16 beta samples; the split mode keeps the lo products apart).
+template <int NW, int NSUB, int PR>
+__global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double2 *__restrict__ rec,
+                                                    const WorkItem *__restrict__ items, int nitems,
+                                                    const typename PrecT<PR>::C *__restrict__ S,
+                                                    typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
+    using C = typename PrecT<PR>::C;
+    using R = typename PrecT<PR>::R;
+    // s_l of the group's degrees: at most B = NW*NSUB*32 for this shape.
+    __shared__ double panel[NW][16 * kRowFwd];
+    __shared__ double srow[NW * NSUB * 32];
+    const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
+    const int B = it.B, N = 2 * B;
+    const int m = it.m, mp = it.mp, mask = it.mask;
+    const int L = B - m;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long goff = it.goff;
+    const double2 *__restrict__ Rr = rec + goff;
+
+    const C *Sg = S + it.s_off;
+    // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
+    const int col = lane & 15, krow = lane >> 4;
+    const bool col_present = (mask >> (col >> 1)) & 1;
+    const bool odd = col & 1;
+
+    // Every load of the prologue goes out before any is used, so they are
+    // all in flight at once: the recurrence coefficients of the first panel
+    // (scalar), the S block (read once: non-temporal loads, about 1 % off the
+    // B = 128 step), cos b_j and seeds, and s_l of the lane's row.
+    double2 c[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
+    // Lanes load whole complex samples: the even lane of a pair (re) that of
+    // step s, the odd lane (im) that of step s + 1; one swap of a half between
+    // the two lanes later leaves each with its part of both steps.  A load
+    // then reads 4 x 2 neighbouring samples, 128 contiguous bytes in FP64, per
+    // slot row.  Samples past N load sample 0 and, like absent slots, are
+    // zeroed: no branches.
+    C raw[NSUB][8];
+    double xv[NSUB], sv[NSUB];
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h) {
+        const int jbase = (wave * NSUB + h) * 64;
+#pragma unroll
+        for (int s = 0; s < 16; s += 2) {
+            const int jl = jbase + 4 * s + krow + (odd ? 4 : 0);
+            typedef R r2 __attribute__((ext_vector_type(2)));
+            const r2 v = __builtin_nontemporal_load(
+                reinterpret_cast<const r2 *>(Sg + (size_t)(col >> 1) * N + (jl < N ? jl : 0)));
+            raw[h][s / 2].x = v[0];
+            raw[h][s / 2].y = v[1];
+        }
+        const int j = jbase + lane;
+        xv[h] = tab.cosb[it.jbase + (j < N ? j : 0)];
+        sv[h] = tab.seed[it.seed_off + (j < N ? j : 0)];
+    }
+    // s_l of the group's rows (L <= B <= NW*NSUB*32, so at most RSN per
+    // thread), read in the panel epilogues (visible after the first panel's
+    // barrier)
+    constexpr int RSN = (NSUB + 1) / 2;
+    double rs[RSN];
+#pragma unroll
+    for (int q = 0; q < RSN; ++q) rs[q] = tab.rscale[goff + min((int)threadIdx.x + q * NW * 64, L - 1)];
+    __builtin_amdgcn_sched_barrier(0);
+
+    R xb[NSUB][16];
+    double x[NSUB], ecur[NSUB], eprev[NSUB];
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h) {
+        const int jbase = (wave * NSUB + h) * 64;
+#pragma unroll
+        for (int s = 0; s < 16; s += 2) {
+            const int j0 = jbase + 4 * s + krow, j1 = j0 + 4;
+            const C v = raw[h][s / 2];
+            const R recv = swap_pair_lanes(odd ? v.x : v.y);
+            xb[h][s] = col_present && j0 < N ? (odd ? recv : v.x) : (R)0;
+            xb[h][s + 1] = col_present && j1 < N ? (odd ? v.y : recv) : (R)0;
+        }
+        const bool jin = jbase + lane < N;
+        x[h] = jin ? xv[h] : 0.0;
+        ecur[h] = jin ? sv[h] : 0.0;
+        eprev[h] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RSN; ++q)
+        if ((int)threadIdx.x + q * NW * 64 < L) srow[threadIdx.x + q * NW * 64] = rs[q];
+    fwd_item_panels<NW, NSUB, PR>(panel, srow, it, Rr, c, xb, x, ecur, eprev, coeffs, apply_v);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,6 +544,114 @@ __device__ __forceinline__ void inv_put(const InvGather<NT, KC, R> &st, R *buf, 
     }
 }
 
+// One 16-degree panel of an inverse work item (degrees lp .. lp+15): the
+// recurrence fills the wave's panel and advances, and the panel (A) times
+// bop (B, this lane's four coefficient values of the panel) accumulates into
+// acc on matrix cores.  Loads the next panel's recurrence coefficients into c.
+template <int NW, int NSUB, int PR>
+__device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], const typename PrecT<PR>::R (&bop)[4],
+                                          double2 (&c)[16], const double2 *__restrict__ Rr, int lp,
+                                          const double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
+                                          v4d (&acc)[NSUB][4]) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, krow = lane >> 4;
+    double *pan = panel[threadIdx.x >> 6];
+    v4bf bopb;
+    if constexpr (PR == P32S) bopb = bf4((float)bop[0], (float)bop[1], (float)bop[2], (float)bop[3]);
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            panel_put<PR>(&pan[r * kRowInv + lane], ecur[h]);
+            const double u = fma(c[r].x, x[h], -c[r].y);
+            const double en = fma(u, ecur[h], -eprev[h]);
+            eprev[h] = ecur[h];
+            ecur[h] = en;
+        }
+        if constexpr (PR == P64) {
+            double a[4][4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a[t][s] = pan[(s + 4 * krow) * kRowInv + 16 * t + col];
+            if (h == NSUB - 1) {
+                lds_wait_all();
+#pragma unroll
+                for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], bop[s], acc[h][t], 0, 0, 0);
+        } else {
+            float2 a[4][4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    a[t][s] = *reinterpret_cast<const float2 *>(&pan[(s + 4 * krow) * kRowInv + 16 * t + col]);
+            if (h == NSUB - 1) {
+                lds_wait_all();
+#pragma unroll
+                for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                v4f ap = {0.f, 0.f, 0.f, 0.f}, al = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    ap = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s].x, bop[s], ap, 0, 0, 0);
+                // the tail: the panel's four k steps in one bf16 MFMA
+                // (element s of the lane is step s, as above)
+                if constexpr (PR == P32S)
+                    al = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        bf4(a[t][0].y, a[t][1].y, a[t][2].y, a[t][3].y), bopb, al, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[h][t][r] += (double)ap[r] + (PR == P32S ? (double)al[r] : 0.0);
+            }
+        }
+    }
+}
+
+// The end of an inverse work item: acc (Y[j][c] for this wave's beta samples)
+// goes through the wave's panel to each slot's row of S, beta contiguous.
+template <int NSUB, int PR>
+__device__ __forceinline__ void inv_store(double *pan, const v4d (&acc)[NSUB][4], const WorkItem &it,
+                                          typename PrecT<PR>::C *__restrict__ S, bool stream) {
+    using C = typename PrecT<PR>::C;
+    using R = typename PrecT<PR>::R;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, krow = lane >> 4;
+    const int N = 2 * it.B;
+    // Register r of lane holds Y[j = 16 t + out_row(krow, r)][c = col] of tile t.
+    // Transpose through the wave's panel (pairs (re, im) swizzled by j) and
+    // store each slot's beta samples contiguously.
+    C *Sg = S + it.s_off;
+    const int slot = col >> 1, part = col & 1;
+#pragma unroll
+    for (int h = 0; h < NSUB; ++h) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int jl = 16 * t + out_row<PR>(krow, r);
+                pan[jl * 16 + 2 * (slot ^ (jl & 7)) + part] = acc[h][t][r];
+            }
+        const int j = (wave * NSUB + h) * 64 + lane;
+#pragma unroll
+        for (int s2 = 0; s2 < kSlots; ++s2) {
+            const double2 v = *reinterpret_cast<const double2 *>(pan + lane * 16 + 2 * (s2 ^ (lane & 7)));
+            C o;
+            o.x = (R)v.x;
+            o.y = (R)v.y;
+            if (j < N && ((it.mask >> s2) & 1)) put_c(&Sg[(size_t)s2 * N + j], o, stream);
+        }
+    }
+}
+
 template <int NW, int NSUB, int PR>
 __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
@@ -572,64 +711,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
-        v4bf bopb;
-        if constexpr (PR == P32S) bopb = bf4((float)bop[0], (float)bop[1], (float)bop[2], (float)bop[3]);
-#pragma unroll
-        for (int h = 0; h < NSUB; ++h) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                panel_put<PR>(&pan[r * kRowInv + lane], ecur[h]);
-                const double u = fma(c[r].x, x[h], -c[r].y);
-                const double en = fma(u, ecur[h], -eprev[h]);
-                eprev[h] = ecur[h];
-                ecur[h] = en;
-            }
-            if constexpr (PR == P64) {
-                double a[4][4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) a[t][s] = pan[(s + 4 * krow) * kRowInv + 16 * t + col];
-                if (h == NSUB - 1) {
-                    lds_wait_all();
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], bop[s], acc[h][t], 0, 0, 0);
-            } else {
-                float2 a[4][4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        a[t][s] = *reinterpret_cast<const float2 *>(&pan[(s + 4 * krow) * kRowInv + 16 * t + col]);
-                if (h == NSUB - 1) {
-                    lds_wait_all();
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    v4f ap = {0.f, 0.f, 0.f, 0.f}, al = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        ap = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s].x, bop[s], ap, 0, 0, 0);
-                    // the tail: the panel's four k steps in one bf16 MFMA
-                    // (element s of the lane is step s, as above)
-                    if constexpr (PR == P32S)
-                        al = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                            bf4(a[t][0].y, a[t][1].y, a[t][2].y, a[t][3].y), bopb, al, 0, 0, 0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[h][t][r] += (double)ap[r] + (PR == P32S ? (double)al[r] : 0.0);
-                }
-            }
-        }
+        inv_panel<NW, NSUB, PR>(panel, bop, c, Rr, lp, x, ecur, eprev, acc);
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
         if (lp + 16 - ch * KC == KC || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
@@ -640,30 +722,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         }
     }
 
-    // Register r of lane holds Y[j = 16 t + out_row(krow, r)][c = col] of tile t.
-    // Transpose through the wave's panel (pairs (re, im) swizzled by j) and
-    // store each slot's beta samples contiguously.
-    C *Sg = S + it.s_off;
-    const int slot = col >> 1, part = col & 1;
-#pragma unroll
-    for (int h = 0; h < NSUB; ++h) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int jl = 16 * t + out_row<PR>(krow, r);
-                pan[jl * 16 + 2 * (slot ^ (jl & 7)) + part] = acc[h][t][r];
-            }
-        const int j = (wave * NSUB + h) * 64 + lane;
-#pragma unroll
-        for (int s2 = 0; s2 < kSlots; ++s2) {
-            const double2 v = *reinterpret_cast<const double2 *>(pan + lane * 16 + 2 * (s2 ^ (lane & 7)));
-            C o;
-            o.x = (R)v.x;
-            o.y = (R)v.y;
-            if (j < N && ((it.mask >> s2) & 1)) put_c(&Sg[(size_t)s2 * N + j], o, stream);
-        }
-    }
+    inv_store<NSUB, PR>(pan, acc, it, S, stream);
 }
 
 }  // namespace

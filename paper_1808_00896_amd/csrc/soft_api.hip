@@ -87,6 +87,16 @@ struct soft_plan_s {
     // it instead of for the whole device.
     hipEvent_t done = nullptr;
     bool done_recorded = false;
+    // SOFT_PLAN_GRAPH: per call kind (forward, inverse, adjoint, adjoint
+    // inverse) the executable graph of its kernels and the pointers it was
+    // captured with; capture runs on a plan-owned stream.
+    struct GraphSlot {
+        hipGraphExec_t exec = nullptr;
+        const void *in = nullptr;
+        void *out = nullptr;
+    };
+    GraphSlot graphs[4];
+    hipStream_t capture = nullptr;
 };
 
 // Rotational-matching head: n pairs of functions on the sphere at bandwidth
@@ -107,13 +117,16 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // the pairs (matching head) in a 16-bit grid dimension.
 constexpr int kMaxFunctions = 65535;
 
-constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE | SOFT_INPLACE_OK;
+constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE | SOFT_INPLACE_OK | SOFT_PLAN_GRAPH;
 
 void free_plan(soft_plan_s *p) {
     if (!p) return;
     for (hipEvent_t e : p->free_events) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->used_events) (void)hipEventDestroy(e);
     if (p->done) (void)hipEventDestroy(p->done);
+    for (auto &g : p->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (p->capture) (void)hipStreamDestroy(p->capture);
     if (p->tables) (void)hipFree(p->tables);
     if (p->S) (void)hipFree(p->S);
     if (p->t1) (void)hipFree(p->t1);
@@ -365,8 +378,10 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     for (const LaunchGroup &lg : p->groups) {
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_FWD);
         if (e == hipSuccess)
-            e = soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S, cout_, scaled,
-                                         s);
+            e = lg.nw_f == 0
+                    ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, S, cout_, scaled, s)
+                    : soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S, cout_,
+                                               scaled, s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_FWD);
     }
     return e;
@@ -411,23 +426,68 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     return e;
 }
 
+// Enqueues the kernels of one call on stream s.
+hipError_t enqueue_call(soft_plan_t p, const void *in, void *out, hipStream_t s, bool forward, bool scaled) {
+    switch (p->precision) {
+        case SOFT_FP64:
+            return forward ? run_forward<soft::P64>(p, in, out, s, scaled)
+                           : run_inverse<soft::P64>(p, in, out, s, scaled);
+        case SOFT_FP32:
+            return forward ? run_forward<soft::P32>(p, in, out, s, scaled)
+                           : run_inverse<soft::P32>(p, in, out, s, scaled);
+        default:
+            return forward ? run_forward<soft::P32S>(p, in, out, s, scaled)
+                           : run_inverse<soft::P32S>(p, in, out, s, scaled);
+    }
+}
+
+// SOFT_PLAN_GRAPH: launches the call's graph on s, capturing its kernels on
+// the plan's own stream first when the call kind has no graph yet or its
+// pointers changed (then the executable graph is updated in place, or made
+// anew when the update is refused).  The kernels take their buffers as
+// arguments, so a graph is valid only for the pointers it was captured with.
+hipError_t graph_call(soft_plan_t p, const void *in, void *out, hipStream_t s, bool forward, bool scaled) {
+    soft_plan_s::GraphSlot &g = p->graphs[(forward ? 0 : 1) + (scaled ? 2 : 0)];
+    hipError_t e = hipSuccess;
+    if (!g.exec || g.in != in || g.out != out) {
+        if (!p->capture) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+        hipGraph_t graph = nullptr;
+        if (e == hipSuccess) e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t ek = enqueue_call(p, in, out, p->capture, forward, scaled);
+            e = hipStreamEndCapture(p->capture, &graph);
+            if (ek != hipSuccess) e = ek;
+        }
+        if (e == hipSuccess && g.exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult how;
+            if (hipGraphExecUpdate(g.exec, graph, &bad, &how) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(g.exec);
+                g.exec = nullptr;
+            }
+        }
+        if (e == hipSuccess && !g.exec) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.in = nullptr;
+            g.out = nullptr;
+            return e;
+        }
+        g.in = in;
+        g.out = out;
+    }
+    return hipGraphLaunch(g.exec, s);
+}
+
 int dispatch(soft_plan_t p, const void *in, void *out, hipStream_t s, bool forward, bool scaled) {
     const int rc = check_call(p, in, out);
     if (rc != SOFT_OK) return rc;
-    hipError_t e;
-    switch (p->precision) {
-        case SOFT_FP64:
-            e = forward ? run_forward<soft::P64>(p, in, out, s, scaled) : run_inverse<soft::P64>(p, in, out, s, scaled);
-            break;
-        case SOFT_FP32:
-            e = forward ? run_forward<soft::P32>(p, in, out, s, scaled) : run_inverse<soft::P32>(p, in, out, s, scaled);
-            break;
-        default:
-            e = forward ? run_forward<soft::P32S>(p, in, out, s, scaled)
-                        : run_inverse<soft::P32S>(p, in, out, s, scaled);
-            break;
-    }
-    if (e == hipSuccess) e = mark_done(p, s);
+    // stage timing records events between the kernels: such calls run eagerly
+    const hipError_t e0 = (p->flags & SOFT_PLAN_GRAPH) && !p->timing_mask
+                              ? graph_call(p, in, out, s, forward, scaled)
+                              : enqueue_call(p, in, out, s, forward, scaled);
+    const hipError_t e = e0 == hipSuccess ? mark_done(p, s) : e0;
     return hip_status(e);
 }
 
@@ -459,8 +519,8 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
 constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}, {4, 4}};
 
 // Autotuner: for every DWT launch group and direction, time each shape that
-// covers the group's largest 2B (and is at most twice that), and for the
-// inverse also the Clenshaw kernel, on the plan's own work list and
+// covers the group's largest 2B (and is at most twice that), and also the
+// Clenshaw kernel of the direction, on the plan's own work list and
 // workspace, with zeroed data, and keep the fastest.  Every
 // candidate runs once untimed (which also brings the clocks up), then
 // kTuneRounds rounds launch each candidate once in turn, each launch between
@@ -477,18 +537,21 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
     C *S = static_cast<C *>(p->S), *cf = static_cast<C *>(coeffs);
     for (LaunchGroup &lg : p->groups) {
         for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-            // candidate c: index into kDwtShapes, or -1 for the Clenshaw inverse
-            std::vector<int> cand;
-            for (int c = 0; c < (int)(sizeof(kDwtShapes) / sizeof(kDwtShapes[0])); ++c) {
-                const int cover = kDwtShapes[c][0] * kDwtShapes[c][1] * 64;
-                if (cover >= lg.nmax && cover <= 2 * lg.nmax) cand.push_back(c);
+            // candidates (waves, subsets): the covering matrix-core shapes and
+            // the Clenshaw form (0, 0)
+            std::vector<std::pair<int, int>> cand;
+            for (const auto &sh : kDwtShapes) {
+                const int cover = sh[0] * sh[1] * 64;
+                if (cover >= lg.nmax && cover <= 2 * lg.nmax) cand.emplace_back(sh[0], sh[1]);
             }
-            if (dir == 1) cand.push_back(-1);
-            auto launch = [&](int c) {
-                if (c < 0)
-                    return soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cf, S, false,
-                                                          group_streams<C>(lg), 0);
-                const int nw = kDwtShapes[c][0], ns = kDwtShapes[c][1];
+            cand.emplace_back(0, 0);
+            auto launch = [&](std::pair<int, int> c) {
+                if (c.first == 0)
+                    return dir == 0 ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax,
+                                                                        S, cf, true, 0)
+                                    : soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax,
+                                                                     cf, S, false, group_streams<C>(lg), 0);
+                const int nw = c.first, ns = c.second;
                 return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true, 0)
                                 : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false,
                                                            group_streams<C>(lg), 0);
@@ -510,8 +573,8 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
             size_t bi = 0;
             for (size_t i = 1; i < cand.size(); ++i)
                 if (best[i] < best[bi]) bi = i;
-            (dir == 0 ? lg.nw_f : lg.nw_i) = cand[bi] < 0 ? 0 : kDwtShapes[cand[bi]][0];
-            (dir == 0 ? lg.nsub_f : lg.nsub_i) = cand[bi] < 0 ? 0 : kDwtShapes[cand[bi]][1];
+            (dir == 0 ? lg.nw_f : lg.nw_i) = cand[bi].first;
+            (dir == 0 ? lg.nsub_f : lg.nsub_i) = cand[bi].second;
         }
         lg.tuned = e == hipSuccess;
     }
@@ -544,8 +607,217 @@ bool valid_precision(int precision) {
     return precision == SOFT_FP64 || precision == SOFT_FP32 || precision == SOFT_FP32_SPLIT;
 }
 
+// Host side of a plan: its tables, function table and DWT work lists in
+// one block laid out as on the device, plus the offsets of its parts.
+struct HostTables {
+    std::vector<unsigned char> host;
+    size_t funcs_off = 0, cosb_off = 0, lcs_off = 0, lbin_off = 0, total = 0;
+    std::vector<BandLayout> lays;
+    std::vector<std::vector<WorkItem>> lists;
+};
+
 // Builds bands, the function table and the DWT work lists of a plan for the
-// bandwidths Bs[0..n) (validated by the caller).
+// bandwidths Bs[0..n) (validated by the caller) into p and ht, without
+// touching a device.
+int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned flags, HostTables &ht) {
+    // Bands in increasing B; functions keep the caller's order.
+    std::vector<int> distinct(Bs, Bs + n);
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    int jtot = 0, gtot = 0;
+    for (int B : distinct) {
+        Band b;
+        b.B = B;
+        b.N = 2 * B;
+        b.G = B * (B + 1) / 2;
+        b.jbase = jtot;
+        b.gbase = gtot;
+        b.seed_base = p->seed_total;
+        p->seed_total += (long long)b.G * b.N;
+        jtot += b.N;
+        gtot += b.G;
+        b.Nc = (long long)B * (4LL * B * B - 1) / 3;
+        for (int m = 0; m < B; ++m) b.rows += (long long)(m + 1) * (B - m);
+        b.row_base = p->rows_total;
+        p->rows_total += b.rows;
+        p->bands.push_back(b);
+    }
+    p->funcs.resize(n);
+    for (int f = 0; f < n; ++f) {
+        const int bi = (int)(std::lower_bound(distinct.begin(), distinct.end(), Bs[f]) - distinct.begin());
+        Band &b = p->bands[bi];
+        FuncInfo &fi = p->funcs[f];
+        fi.band = bi;
+        fi.pad = 0;
+        fi.grid_off = (long long)p->grid_total;
+        fi.coeff_off = (long long)p->coeff_total;
+        fi.s_off = (long long)p->s_total;
+        p->grid_total += (size_t)b.N * b.N * b.N;
+        p->coeff_total += (size_t)b.Nc;
+        p->s_total += (size_t)b.G * kSlots * b.N;
+        b.funcs.push_back(f);
+    }
+    // The tile-blocked FFT intermediate; a SOFT_INPLACE_OK plan has none
+    // and stages the intermediate in the grid buffer instead.
+    if (!(flags & SOFT_INPLACE_OK))
+        for (const Band &b : p->bands)
+            p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
+
+    // DWT launch groups: in a plan of several bands, the bands with
+    // 2B <= 64 share one launch (with the 2B = 64 shapes); every other
+    // length has its own (sharing one launch down from 2B = 256 left the
+    // lanes of the shorter bands idle: 2-3 % slower on the 256-function
+    // batch of B = 16 ... 128).
+    const bool merged = p->bands.size() > 1;
+    std::vector<int> keys;  // 0 for the shared launch, else 2B
+    std::vector<std::vector<int>> group_bands;
+    for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+        const int key = merged && p->bands[bi].N <= 64 ? 0 : p->bands[bi].N;
+        size_t gi = std::find(keys.begin(), keys.end(), key) - keys.begin();
+        if (gi == keys.size()) {
+            keys.push_back(key);
+            group_bands.emplace_back();
+        }
+        group_bands[gi].push_back((int)bi);
+    }
+    // Per band and group g (ordered by m, then m'): m and the first row.
+    std::vector<std::vector<int>> gm(p->bands.size());
+    std::vector<std::vector<long long>> grow(p->bands.size());
+    for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+        const Band &b = p->bands[bi];
+        long long row = b.row_base;
+        for (int m = 0; m < b.B; ++m)
+            for (int mp = 0; mp <= m; ++mp) {
+                gm[bi].push_back(m);
+                grow[bi].push_back(row);
+                row += b.B - m;
+            }
+    }
+    // Work lists: runs of 8 consecutive groups of one function (the XCD
+    // remap hands each run to one XCD), ordered by the cost (B - m) 2B of
+    // their first group, largest first, so the long recurrences start
+    // early and the short ones fill the tail.
+    std::vector<std::vector<WorkItem>> &lists = ht.lists;
+    lists.assign(keys.size(), {});
+    for (size_t gi = 0; gi < keys.size(); ++gi) {
+        struct Run {
+            long long cost;
+            int band, func, g0, g1;
+        };
+        std::vector<Run> runs;
+        for (int bi : group_bands[gi]) {
+            const Band &b = p->bands[bi];
+            for (int f : b.funcs)
+                for (int g0 = 0; g0 < b.G; g0 += 8)
+                    runs.push_back({(long long)(b.B - gm[bi][g0]) * b.N, bi, f, g0, std::min(b.G, g0 + 8)});
+        }
+        std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.cost > c.cost; });
+        for (const Run &r : runs) {
+            const Band &b = p->bands[r.band];
+            const FuncInfo &fi = p->funcs[r.func];
+            for (int g = r.g0; g < r.g1; ++g) {
+                const int m = gm[r.band][g], mp = g - m * (m + 1) / 2;
+                WorkItem w{};
+                w.goff = grow[r.band][g];
+                w.s_off = fi.s_off + (long long)g * kSlots * b.N;
+                w.coeff_off = fi.coeff_off;
+                w.B = b.B;
+                w.jbase = b.jbase;
+                w.seed_off = b.seed_base + (long long)g * b.N;
+                w.m = m;
+                w.mp = mp;
+                w.mask = group_mask(m, mp);
+                lists[gi].push_back(w);
+            }
+        }
+        if (lists[gi].size() > (size_t)0x7fffffff) return SOFT_ERR_UNSUPPORTED;
+        LaunchGroup lg;
+        const int len = keys[gi] ? keys[gi] : 64;
+        std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision);
+        std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision);
+        lg.bands = group_bands[gi];
+        for (int bi : group_bands[gi]) lg.nmax = std::max(lg.nmax, p->bands[bi].N);
+        lg.nitems = (int)lists[gi].size();
+        p->groups.push_back(lg);
+    }
+
+    // Table block: band tables, function table, band views, work lists.
+    size_t off = 0;
+    std::vector<BandLayout> &lays = ht.lays;
+    for (Band &b : p->bands) {
+        b.tab_off = off;
+        lays.push_back(band_layout(b));
+        off = align256(off + lays.back().total);
+    }
+    const size_t funcs_off = ht.funcs_off = off;
+    off = align256(off + sizeof(FuncInfo) * n);
+    const size_t cosb_off = ht.cosb_off = off;
+    off = align256(off + sizeof(double) * jtot);
+    const size_t lcs_off = ht.lcs_off = off;
+    off = align256(off + sizeof(double4) * jtot);
+    const size_t lbin_off = ht.lbin_off = off;
+    off = align256(off + sizeof(double2) * gtot);
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        p->groups[gi].items_off = off;
+        off = align256(off + sizeof(WorkItem) * lists[gi].size());
+    }
+    const size_t total = ht.total = off;
+    std::vector<unsigned char> &host = ht.host;
+    host.assign(total, 0);
+    double *cosb_h = reinterpret_cast<double *>(host.data() + cosb_off);
+    double4 *lcs_h = reinterpret_cast<double4 *>(host.data() + lcs_off);
+    double2 *lbin_h = reinterpret_cast<double2 *>(host.data() + lbin_off);
+    for (size_t bi = 0; bi < p->bands.size(); ++bi) {
+        const Band &b = p->bands[bi];
+        const int rc = fill_band(b, lays[bi], host.data() + b.tab_off, cosb_h + b.jbase, lcs_h + b.jbase,
+                                 lbin_h + b.gbase);
+        if (rc != SOFT_OK) return rc;
+    }
+    std::memcpy(host.data() + funcs_off, p->funcs.data(), sizeof(FuncInfo) * n);
+    for (size_t gi = 0; gi < p->groups.size(); ++gi)
+        std::memcpy(host.data() + p->groups[gi].items_off, lists[gi].data(), sizeof(WorkItem) * lists[gi].size());
+    return SOFT_OK;
+}
+
+// Checks a plan's host tables: every (function, symmetry group) appears in
+// exactly one work item, each item's offsets lie inside its function's S
+// block, coefficient vector, seed and recurrence rows, and every launch
+// shape covers its launch.  (fill_band has checked that the groups' member
+// slots cover every order pair exactly once.)
+int check_host(const soft_plan_s *p, const HostTables &ht) {
+    std::vector<std::vector<unsigned char>> seen(p->n);
+    for (int f = 0; f < p->n; ++f) seen[f].assign(p->bands[p->funcs[f].band].G, 0);
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const LaunchGroup &lg = p->groups[gi];
+        if ((size_t)lg.nitems != ht.lists[gi].size()) return SOFT_ERR_INVALID;
+        if (lg.nw_f * lg.nsub_f * 64 < lg.nmax || lg.nw_i * lg.nsub_i * 64 < lg.nmax) return SOFT_ERR_INVALID;
+        for (const WorkItem &w : ht.lists[gi]) {
+            int f = -1;
+            for (int q = 0; q < p->n && f < 0; ++q)
+                if (p->funcs[q].coeff_off == w.coeff_off) f = q;
+            if (f < 0) return SOFT_ERR_INVALID;
+            const Band &b = p->bands[p->funcs[f].band];
+            const long long N = b.N;
+            if (w.B != b.B || w.jbase != b.jbase || w.m < 0 || w.m >= b.B || w.mp < 0 || w.mp > w.m)
+                return SOFT_ERR_INVALID;
+            const int g = w.m * (w.m + 1) / 2 + w.mp;
+            if (seen[f][g]++) return SOFT_ERR_INVALID;
+            if (w.mask != group_mask(w.m, w.mp) || b.N > lg.nmax) return SOFT_ERR_INVALID;
+            if (w.s_off != p->funcs[f].s_off + (long long)g * kSlots * N ||
+                w.s_off + kSlots * N > (long long)p->s_total)
+                return SOFT_ERR_INVALID;
+            if (w.seed_off != b.seed_base + (long long)g * N || w.seed_off + N > p->seed_total) return SOFT_ERR_INVALID;
+            if (w.goff < b.row_base || w.goff + (b.B - w.m) > b.row_base + b.rows) return SOFT_ERR_INVALID;
+            if (w.coeff_off + b.Nc > (long long)p->coeff_total) return SOFT_ERR_INVALID;
+        }
+    }
+    for (int f = 0; f < p->n; ++f)
+        for (unsigned char c : seen[f])
+            if (c != 1) return SOFT_ERR_INVALID;
+    if (ht.host.size() != ht.total) return SOFT_ERR_INVALID;
+    return SOFT_OK;
+}
+
 int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *out) {
     soft_plan_s *p = new (std::nothrow) soft_plan_s;
     if (!p) return SOFT_ERR_OOM;
@@ -558,166 +830,17 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             delete p;
             return SOFT_ERR_HIP;
         }
-        // Bands in increasing B; functions keep the caller's order.
-        std::vector<int> distinct(Bs, Bs + n);
-        std::sort(distinct.begin(), distinct.end());
-        distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
-        int jtot = 0, gtot = 0;
-        for (int B : distinct) {
-            Band b;
-            b.B = B;
-            b.N = 2 * B;
-            b.G = B * (B + 1) / 2;
-            b.jbase = jtot;
-            b.gbase = gtot;
-            b.seed_base = p->seed_total;
-            p->seed_total += (long long)b.G * b.N;
-            jtot += b.N;
-            gtot += b.G;
-            b.Nc = (long long)B * (4LL * B * B - 1) / 3;
-            for (int m = 0; m < B; ++m) b.rows += (long long)(m + 1) * (B - m);
-            b.row_base = p->rows_total;
-            p->rows_total += b.rows;
-            p->bands.push_back(b);
+        HostTables ht;
+        const int rc = build_host(p, Bs, n, precision, flags, ht);
+        if (rc != SOFT_OK) {
+            delete p;
+            return rc;
         }
-        p->funcs.resize(n);
-        for (int f = 0; f < n; ++f) {
-            const int bi = (int)(std::lower_bound(distinct.begin(), distinct.end(), Bs[f]) - distinct.begin());
-            Band &b = p->bands[bi];
-            FuncInfo &fi = p->funcs[f];
-            fi.band = bi;
-            fi.pad = 0;
-            fi.grid_off = (long long)p->grid_total;
-            fi.coeff_off = (long long)p->coeff_total;
-            fi.s_off = (long long)p->s_total;
-            p->grid_total += (size_t)b.N * b.N * b.N;
-            p->coeff_total += (size_t)b.Nc;
-            p->s_total += (size_t)b.G * kSlots * b.N;
-            b.funcs.push_back(f);
-        }
-        // The tile-blocked FFT intermediate; a SOFT_INPLACE_OK plan has none
-        // and stages the intermediate in the grid buffer instead.
-        if (!(flags & SOFT_INPLACE_OK))
-            for (const Band &b : p->bands)
-                p->t1_elems = std::max(p->t1_elems, b.funcs.size() * (size_t)b.N * b.N * b.N);
-
-        // DWT launch groups: in a plan of several bands, the bands with
-        // 2B <= 64 share one launch (with the 2B = 64 shapes); every other
-        // length has its own (sharing one launch down from 2B = 256 left the
-        // lanes of the shorter bands idle: 2-3 % slower on the 256-function
-        // batch of B = 16 ... 128).
-        const bool merged = p->bands.size() > 1;
-        std::vector<int> keys;  // 0 for the shared launch, else 2B
-        std::vector<std::vector<int>> group_bands;
-        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
-            const int key = merged && p->bands[bi].N <= 64 ? 0 : p->bands[bi].N;
-            size_t gi = std::find(keys.begin(), keys.end(), key) - keys.begin();
-            if (gi == keys.size()) {
-                keys.push_back(key);
-                group_bands.emplace_back();
-            }
-            group_bands[gi].push_back((int)bi);
-        }
-        // Per band and group g (ordered by m, then m'): m and the first row.
-        std::vector<std::vector<int>> gm(p->bands.size());
-        std::vector<std::vector<long long>> grow(p->bands.size());
-        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
-            const Band &b = p->bands[bi];
-            long long row = b.row_base;
-            for (int m = 0; m < b.B; ++m)
-                for (int mp = 0; mp <= m; ++mp) {
-                    gm[bi].push_back(m);
-                    grow[bi].push_back(row);
-                    row += b.B - m;
-                }
-        }
-        // Work lists: runs of 8 consecutive groups of one function (the XCD
-        // remap hands each run to one XCD), ordered by the cost (B - m) 2B of
-        // their first group, largest first, so the long recurrences start
-        // early and the short ones fill the tail.
-        std::vector<std::vector<WorkItem>> lists(keys.size());
-        for (size_t gi = 0; gi < keys.size(); ++gi) {
-            struct Run {
-                long long cost;
-                int band, func, g0, g1;
-            };
-            std::vector<Run> runs;
-            for (int bi : group_bands[gi]) {
-                const Band &b = p->bands[bi];
-                for (int f : b.funcs)
-                    for (int g0 = 0; g0 < b.G; g0 += 8)
-                        runs.push_back({(long long)(b.B - gm[bi][g0]) * b.N, bi, f, g0, std::min(b.G, g0 + 8)});
-            }
-            std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.cost > c.cost; });
-            for (const Run &r : runs) {
-                const Band &b = p->bands[r.band];
-                const FuncInfo &fi = p->funcs[r.func];
-                for (int g = r.g0; g < r.g1; ++g) {
-                    const int m = gm[r.band][g], mp = g - m * (m + 1) / 2;
-                    WorkItem w{};
-                    w.goff = grow[r.band][g];
-                    w.s_off = fi.s_off + (long long)g * kSlots * b.N;
-                    w.coeff_off = fi.coeff_off;
-                    w.B = b.B;
-                    w.jbase = b.jbase;
-                    w.seed_off = b.seed_base + (long long)g * b.N;
-                    w.m = m;
-                    w.mp = mp;
-                    w.mask = group_mask(m, mp);
-                    lists[gi].push_back(w);
-                }
-            }
-            if (lists[gi].size() > (size_t)0x7fffffff) {
-                delete p;
-                return SOFT_ERR_UNSUPPORTED;
-            }
-            LaunchGroup lg;
-            const int len = keys[gi] ? keys[gi] : 64;
-            std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision);
-            std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision);
-            lg.bands = group_bands[gi];
-            for (int bi : group_bands[gi]) lg.nmax = std::max(lg.nmax, p->bands[bi].N);
-            lg.nitems = (int)lists[gi].size();
-            p->groups.push_back(lg);
-        }
-
-        // Table block: band tables, function table, band views, work lists.
-        size_t off = 0;
-        std::vector<BandLayout> lays;
-        for (Band &b : p->bands) {
-            b.tab_off = off;
-            lays.push_back(band_layout(b));
-            off = align256(off + lays.back().total);
-        }
-        const size_t funcs_off = off;
-        off = align256(off + sizeof(FuncInfo) * n);
-        const size_t cosb_off = off;
-        off = align256(off + sizeof(double) * jtot);
-        const size_t lcs_off = off;
-        off = align256(off + sizeof(double4) * jtot);
-        const size_t lbin_off = off;
-        off = align256(off + sizeof(double2) * gtot);
-        for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-            p->groups[gi].items_off = off;
-            off = align256(off + sizeof(WorkItem) * lists[gi].size());
-        }
-        const size_t total = off;
-        std::vector<unsigned char> host(total, 0);
-        double *cosb_h = reinterpret_cast<double *>(host.data() + cosb_off);
-        double4 *lcs_h = reinterpret_cast<double4 *>(host.data() + lcs_off);
-        double2 *lbin_h = reinterpret_cast<double2 *>(host.data() + lbin_off);
-        for (size_t bi = 0; bi < p->bands.size(); ++bi) {
-            const Band &b = p->bands[bi];
-            const int rc = fill_band(b, lays[bi], host.data() + b.tab_off, cosb_h + b.jbase, lcs_h + b.jbase,
-                                     lbin_h + b.gbase);
-            if (rc != SOFT_OK) {
-                delete p;
-                return rc;
-            }
-        }
-        std::memcpy(host.data() + funcs_off, p->funcs.data(), sizeof(FuncInfo) * n);
-        for (size_t gi = 0; gi < p->groups.size(); ++gi)
-            std::memcpy(host.data() + p->groups[gi].items_off, lists[gi].data(), sizeof(WorkItem) * lists[gi].size());
+        const size_t total = ht.total;
+        const std::vector<unsigned char> &host = ht.host;
+        const size_t funcs_off = ht.funcs_off, cosb_off = ht.cosb_off, lcs_off = ht.lcs_off,
+                     lbin_off = ht.lbin_off;
+        const std::vector<BandLayout> &lays = ht.lays;
 
         const size_t rec_rows = (size_t)p->rows_total + soft::kPadRows;
         if (hipMalloc(&p->tables, total) != hipSuccess || hipMalloc(&p->S, p->s_total * p->csize) != hipSuccess ||
@@ -852,6 +975,31 @@ int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, so
     return make_plan(B_list, n, precision, flags, out);
 }
 
+int soft_plan_check(const int *B_list, int n, int precision, unsigned flags) {
+    if (!B_list || n < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    for (int i = 0; i < n; ++i)
+        if (B_list[i] < 1) return SOFT_ERR_INVALID;
+    if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
+    for (int i = 0; i < n; ++i)
+        if (!is_pow2(B_list[i]) || B_list[i] > 512) return SOFT_ERR_UNSUPPORTED;
+    soft_plan_s *p = new (std::nothrow) soft_plan_s;
+    if (!p) return SOFT_ERR_OOM;
+    int rc;
+    try {
+        p->precision = precision;
+        p->n = n;
+        p->flags = flags;
+        p->csize = precision == SOFT_FP64 ? sizeof(double2) : sizeof(float2);
+        HostTables ht;
+        rc = build_host(p, B_list, n, precision, flags, ht);
+        if (rc == SOFT_OK) rc = check_host(p, ht);
+    } catch (const std::bad_alloc &) {
+        rc = SOFT_ERR_OOM;
+    }
+    delete p;
+    return rc;
+}
+
 int soft_plan_sizes(soft_plan_t p, size_t *grid_elems, size_t *coeff_elems, size_t *workspace_bytes) {
     if (!p) return SOFT_ERR_INVALID;
     if (grid_elems) *grid_elems = p->grid_total;
@@ -887,8 +1035,9 @@ int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves,
     if (!p || launch < 0 || launch >= (int)p->groups.size() || (direction != 0 && direction != 1))
         return SOFT_ERR_INVALID;
     LaunchGroup &lg = p->groups[launch];
-    if (direction == 1 && waves == 0 && subsets == 0) {  // the Clenshaw inverse
-        lg.nw_i = lg.nsub_i = 0;
+    if (waves == 0 && subsets == 0) {  // the Clenshaw forms
+        (direction == 0 ? lg.nw_f : lg.nw_i) = 0;
+        (direction == 0 ? lg.nsub_f : lg.nsub_i) = 0;
         return SOFT_OK;
     }
     bool known = false;
@@ -1096,6 +1245,21 @@ int soft_match_destroy(soft_match_t m) {
     const hipError_t e = wait_done(m->plan);
     free_match(m);
     return hip_status(e);
+}
+
+int soft_probe_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    if (!src || !dst || bytes == 0 || bytes % 16 != 0) return SOFT_ERR_INVALID;
+    return hip_status(soft::launch_probe_copy(src, dst, (long long)(bytes / 16), s));
+}
+
+int soft_probe_flops(int kind, int blocks, int iters, double *sink, hipStream_t s) {
+    if (kind < 0 || kind > 2 || blocks < 1 || iters < 1 || !sink) return SOFT_ERR_INVALID;
+    return hip_status(soft::launch_probe_flops(kind, blocks, iters, sink, s));
+}
+
+double soft_probe_flop_count(int kind, int blocks, int iters) {
+    if (kind < 0 || kind > 2 || blocks < 1 || iters < 1) return 0.0;
+    return soft::probe_flop_count(kind, blocks, iters);
 }
 
 const char *soft_status_string(int status) {

@@ -270,6 +270,15 @@ hipError_t launch_idwt_clenshaw(const DwtTables &tab, const WorkItem *items, int
                                 const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
                                 bool stream, hipStream_t s);
 
+// The forward DWT by the transposed (adjoint) Clenshaw evaluation
+// (clenshaw.hip): one block of nmax rounded up to 64 lanes per work item, one
+// beta sample per lane, the sums over beta reduced across lanes; nmax is the
+// largest 2B of the items (2 .. 1024).
+template <int PR>
+hipError_t launch_dwt_fwd_clenshaw(const DwtTables &tab, const WorkItem *items, int nitems, int nmax,
+                                   const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
+                                   hipStream_t s);
+
 // Rotational-matching head (match.hip).  n pairs of functions on the sphere
 // (B^2 coefficients each): correlation coefficients a(l,M) conj(b(l,M')), the
 // vector-Jacobian product of that map, and the per-grid argmax of Re over n
@@ -282,5 +291,14 @@ size_t argmax_workspace_bytes(long long count, int n);
 hipError_t launch_argmax_final(const ArgBest *part, int nblk, int n, long long *index, hipStream_t s);
 template <typename C>
 hipError_t launch_argmax_real(const C *x, long long count, int n, void *workspace, long long *index, hipStream_t s);
+
+// Device ceilings (probe.hip): a streaming copy of `words` 16-byte words,
+// and dependent-chain loops (kind 0: FP64 vector FMA, 1: FP64 MFMA 16x16x4,
+// 2: FP32 MFMA 16x16x4) over `blocks` blocks of 4 waves; probe_flop_count is
+// the flops one such launch performs.  sink: blocks * 256 doubles, never
+// written in practice.
+hipError_t launch_probe_copy(const void *src, void *dst, long long words, hipStream_t s);
+hipError_t launch_probe_flops(int kind, int blocks, int iters, double *sink, hipStream_t s);
+double probe_flop_count(int kind, int blocks, int iters);
 
 }  // namespace soft

@@ -26,6 +26,7 @@ SOFT_FP32_SPLIT = 2
 PRECISIONS = {"fp64": SOFT_FP64, "fp32": SOFT_FP32, "fp32_split": SOFT_FP32_SPLIT}
 SOFT_PLAN_TUNE = 1
 SOFT_INPLACE_OK = 2
+SOFT_PLAN_GRAPH = 4
 SOFT_OK = 0
 SOFT_ERR_INVALID = -1
 SOFT_ERR_UNSUPPORTED = -2
@@ -53,6 +54,8 @@ def lib():
         L.soft_plan_uneven.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                                        ctypes.POINTER(vp)]
         L.soft_plan_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.soft_plan_check.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_uint]
+        L.soft_plan_check.restype = ctypes.c_int
         L.soft_plan_offsets.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.soft_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
         L.soft_plan_set_dwt_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -76,6 +79,12 @@ def lib():
                      "soft_match_coeffs_vjp", "soft_match_argmax", "soft_match_argmax_noalloc", "soft_match",
                      "soft_match_destroy"):
             getattr(L, name).restype = ctypes.c_int
+        L.soft_probe_copy.argtypes = [vp, vp, sz, vp]
+        L.soft_probe_copy.restype = ctypes.c_int
+        L.soft_probe_flops.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.soft_probe_flops.restype = ctypes.c_int
+        L.soft_probe_flop_count.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.soft_probe_flop_count.restype = ctypes.c_double
         L.soft_status_string.argtypes = [ctypes.c_int]
         L.soft_status_string.restype = ctypes.c_char_p
         for name in ("soft_plan", "soft_plan_uneven", "soft_plan_sizes", "soft_plan_offsets", "soft_plan_describe", "soft_plan_set_dwt_shape", "soft_forward", "soft_inverse", "soft_adjoint",
@@ -119,6 +128,14 @@ def soft_plan_uneven(B_list, precision=SOFT_FP64, flags=0):
     h = ctypes.c_void_p()
     _check(lib().soft_plan_uneven(arr, len(Bs), int(precision), int(flags), ctypes.byref(h)), "soft_plan_uneven")
     return h.value
+
+
+def soft_plan_check(B_list, precision=SOFT_FP64, flags=0):
+    """Build and check a plan's host side for the bandwidths B_list without a
+    device; returns the status code (SOFT_OK when every check holds)."""
+    Bs = [int(b) for b in B_list]
+    arr = (ctypes.c_int * max(1, len(Bs)))(*Bs)
+    return lib().soft_plan_check(arr, len(Bs), int(precision), int(flags))
 
 
 def soft_plan_offsets(plan, n):
@@ -244,6 +261,23 @@ def soft_match_argmax_noalloc(B, n, precision, grid, index, stream=None):
                                            _stream(stream)), "soft_match_argmax_noalloc")
 
 
+PROBE_FMA64, PROBE_MFMA64, PROBE_MFMA32 = 0, 1, 2
+
+
+def soft_probe_copy(src, dst, stream=None):
+    """Streaming copy of src into dst (device tensors of equal byte size)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().soft_probe_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "soft_probe_copy")
+
+
+def soft_probe_flops(kind, blocks, iters, sink, stream=None):
+    """Arithmetic loop of `kind` (PROBE_*) on `blocks` blocks; returns its flop count."""
+    _check(lib().soft_probe_flops(int(kind), int(blocks), int(iters), _ptr(sink), _stream(stream)),
+           "soft_probe_flops")
+    return lib().soft_probe_flop_count(int(kind), int(blocks), int(iters))
+
+
 def soft_match(match, a, b, grid, index, stream=None):
     _check(lib().soft_match(ctypes.c_void_p(match), _ptr(a), _ptr(b), _ptr(grid), _ptr(index), _stream(stream)),
            "soft_match")
@@ -269,8 +303,9 @@ def _precision(precision):
     return int(precision)
 
 
-def _flags(tune, inplace_ok):
-    return (SOFT_PLAN_TUNE if tune else 0) | (SOFT_INPLACE_OK if inplace_ok else 0)
+def _flags(tune, inplace_ok, graph=False):
+    return (SOFT_PLAN_TUNE if tune else 0) | (SOFT_INPLACE_OK if inplace_ok else 0) | \
+        (SOFT_PLAN_GRAPH if graph else 0)
 
 
 class _PlanBase:
@@ -385,15 +420,16 @@ class Plan(_PlanBase):
     ``precision`` is "fp64" (complex128), "fp32" or "fp32_split" (complex64).
     ``tune`` times the DWT launch shapes at plan time; ``inplace_ok`` drops
     the plan's FFT intermediate and stages it in the grid tensors instead
-    (forward and adjoint_inverse then overwrite their input grid).
+    (forward and adjoint_inverse then overwrite their input grid); ``graph``
+    replays each call kind as a captured HIP graph (SOFT_PLAN_GRAPH).
     Calls are asynchronous on the current torch stream.
     """
 
-    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False, inplace_ok=False):
+    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False):
         self._init_device(device, precision)
         self.inplace_ok = bool(inplace_ok)
         with torch.cuda.device(self.device):
-            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok))
+            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok, graph))
         self.B, self.batch, self.N = B, batch, 2 * B
         self.nc = num_coeffs(B)
 
@@ -413,12 +449,12 @@ class UnevenPlan(_PlanBase):
     where each starts, and ``split_grids`` / ``split_coeffs`` return views.
     """
 
-    def __init__(self, Bs, device=None, precision="fp64", tune=False, inplace_ok=False):
+    def __init__(self, Bs, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False):
         self._init_device(device, precision)
         self.inplace_ok = bool(inplace_ok)
         self.Bs = [int(b) for b in Bs]
         with torch.cuda.device(self.device):
-            self.handle = soft_plan_uneven(self.Bs, self.precision, _flags(tune, inplace_ok))
+            self.handle = soft_plan_uneven(self.Bs, self.precision, _flags(tune, inplace_ok, graph))
         self.grid_offsets, self.coeff_offsets = soft_plan_offsets(self.handle, len(self.Bs))
 
     def grid_shape(self):

@@ -47,7 +47,7 @@ def test_argument_errors_need_no_gpu(L):
     h = ctypes.c_void_p()
     assert L.soft_plan(0, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
-    assert L.soft_plan(8, 1, 0, 4, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 1, 0, 8, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 1, 0, 0x80000000, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_describe(None, None, 0) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 1, 7, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
@@ -70,7 +70,7 @@ def test_uneven_argument_errors_need_no_gpu(L):
     assert L.soft_plan_uneven(None, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_uneven(arr, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_uneven(arr, 3, 3, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
-    assert L.soft_plan_uneven(arr, 3, 0, 6, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_uneven(arr, 3, 0, 8, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_uneven(arr, 3, 0, 0, None) == soft.SOFT_ERR_INVALID
     bad = (ctypes.c_int * 3)(8, 0, 4)
     assert L.soft_plan_uneven(bad, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
@@ -91,7 +91,7 @@ def test_match_argument_errors_need_no_gpu(L):
     assert L.soft_match_plan(0, 4, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(8, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(8, 4, 5, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
-    assert L.soft_match_plan(8, 4, 0, 4, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(8, 4, 0, 8, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(8, 4, 0, 0, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(24, 4, 2, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert h.value is None
@@ -113,10 +113,28 @@ def test_match_argument_errors_need_no_gpu(L):
     assert L.soft_match_destroy(None) == soft.SOFT_OK
 
 
+def test_probe_argument_errors_need_no_gpu(L):
+    from paper_1808_00896_amd import soft
+    one = ctypes.c_void_p(16)  # never dereferenced: the arguments are rejected first
+    assert L.soft_probe_copy(None, one, 16, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_probe_copy(one, one, 0, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_probe_copy(one, one, 24, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_probe_flops(3, 1, 1, one, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_probe_flops(0, 0, 1, one, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_probe_flops(1, 1, 1, None, None) == soft.SOFT_ERR_INVALID
+    # flops per launch: 8 FMAs x 64 lanes x 2 (vector), 8 MFMAs x 2*16*16*4 (matrix), 4 waves a block
+    assert L.soft_probe_flop_count(0, 3, 5) == 8 * 64 * 2 * 4 * 3 * 5
+    assert L.soft_probe_flop_count(1, 3, 5) == 8 * 2048 * 4 * 3 * 5
+    assert L.soft_probe_flop_count(2, 1, 1) == 8 * 2048 * 4
+    assert L.soft_probe_flop_count(5, 1, 1) == 0.0
+
+
 def test_flag_constants_match_header():
     """The binding's flag values are the header's."""
     import re
     from paper_1808_00896_amd import soft
     text = open(os.path.join(ROOT, "include", "soft.h")).read()
-    vals = dict((k, int(v)) for k, v in re.findall(r"\b(SOFT_PLAN_TUNE|SOFT_INPLACE_OK)\s*=\s*(\d+)u", text))
-    assert vals == {"SOFT_PLAN_TUNE": soft.SOFT_PLAN_TUNE, "SOFT_INPLACE_OK": soft.SOFT_INPLACE_OK}
+    vals = dict((k, int(v)) for k, v in
+                re.findall(r"\b(SOFT_PLAN_TUNE|SOFT_INPLACE_OK|SOFT_PLAN_GRAPH)\s*=\s*(\d+)u", text))
+    assert vals == {"SOFT_PLAN_TUNE": soft.SOFT_PLAN_TUNE, "SOFT_INPLACE_OK": soft.SOFT_INPLACE_OK,
+                    "SOFT_PLAN_GRAPH": soft.SOFT_PLAN_GRAPH}

@@ -79,3 +79,60 @@ def test_oracle_child_leg_runs_on_cpu():
         assert r.returncode == 0, r.stderr
         out = json.loads(r.stdout.strip().splitlines()[-1])
         assert out["seconds"] > 0 and out["threads"] == 1
+
+
+def test_traffic_lookup_signature():
+    assert bench.measured_traffic("fp64_B3_n1", "dwt_inv") is None
+
+
+def test_err_report_per_degree():
+    """deg_rel[l] = max |dx| / max |ref| over degree l's (2l+1)^2 entries, with
+    a planted error in one degree only."""
+    B = 6
+    rng = np.random.default_rng(0)
+    ref = rng.standard_normal(bench.num_coeffs(B)) + 1j * rng.standard_normal(bench.num_coeffs(B))
+    x = ref.copy()
+    l = 4
+    start = l * (4 * l * l - 1) // 3
+    x[start + 3] += 1e-3
+    r = bench.err_report(x, ref, B)
+    blk = np.abs(ref[start:start + (2 * l + 1) ** 2]).max()
+    assert r["deg_rel"][l] == bench.sig(1e-3 / blk, 2)
+    assert all(v == 0.0 for k, v in enumerate(r["deg_rel"]) if k != l)
+    assert r["max_rel"] == bench.sig(1e-3 / np.abs(ref).max())
+    assert r["l2_rel"] == bench.sig(1e-3 / np.linalg.norm(ref))
+
+
+def test_coeff_indices_and_pairs_report():
+    """The sampled-pair indices are the l-major positions of f°(l, m, m'),
+    and entries below a pair's lowest degree are ignored."""
+    B = 8
+    pairs = bench.sample_pairs(B)
+    idx = bench.coeff_indices(B, pairs)
+    for p, (m, mp) in enumerate(pairs):
+        for l in range(max(abs(m), abs(mp)), B):
+            assert idx[p, l] == l * (4 * l * l - 1) // 3 + (m + l) * (2 * l + 1) + (mp + l)
+    ref = np.ones((len(pairs), B), dtype=complex)
+    x = ref.copy()
+    x[:, 0] += 5.0      # degree 0: below the lowest degree of every pair but (0, 0)
+    x[0, 0] = ref[0, 0]
+    r = bench.pairs_report(x, ref, pairs)
+    assert r["max_rel"] == 0.0
+
+
+def test_stage_of_kernel_names():
+    assert bench.stage_of("k_fft<256, 0, 1, double2>") == "fft_gamma_fwd"
+    assert bench.stage_of("k_fft_ingrid<1024, 2, -1, float2>") == "fft_alpha_inv"
+    assert bench.stage_of("k_fft<64, 3, -1, double2>") == "fft_gamma_inv"
+    assert bench.stage_of("k_dwt_fwd<4, 1, 0>") == "dwt_fwd"
+    assert bench.stage_of("k_idwt_clenshaw<0, 1>") == "dwt_inv"
+    assert bench.stage_of("k_probe_copy") is None
+
+
+def test_workload_bands():
+    assert bench._workload_bands("fp32_split_B128_n16") == ([128] * 16, "fp32_split")
+    Bs, prec = bench._workload_bands("fp64_uneven256")
+    assert prec == "fp64" and len(Bs) == 256 and set(Bs) == {16, 32, 64, 128}
+    assert bench.calls_per_step("fp64_uneven256", "fft_alpha_fwd") == 4
+    assert bench.calls_per_step("fp64_uneven256", "dwt_fwd") == 3
+    assert bench.calls_per_step("fp64_B512_n1", "dwt_fwd") == 1

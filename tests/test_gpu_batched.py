@@ -250,7 +250,8 @@ def test_every_dwt_shape_B256_agrees(dev, prec):
 
 def test_set_dwt_shape_rejects_bad_shapes(dev):
     with soft.Plan(64) as p:
-        for args in ((1, 0, 2, 1), (0, 2, 2, 1), (0, 0, 1, 1), (0, 0, 3, 1), (0, 0, 16, 2)):
+        for args in ((1, 0, 2, 1), (0, 2, 2, 1), (0, 0, 1, 1), (0, 0, 3, 1), (0, 0, 16, 2), (0, 0, 2, 0),
+                     (0, 1, 0, 1)):
             with pytest.raises(soft.SoftError):
                 p.set_dwt_shape(*args)
 
@@ -267,7 +268,7 @@ def test_tuned_plans_match_oracle(oracle, dev, prec):
         for key in ("forward", "inverse"):
             nw, ns = d["dwt_launches"][0][key]
             assert ((nw, ns) in soft.DWT_SHAPES and nw * ns * 64 >= 2 * B) or \
-                (key == "inverse" and (nw, ns) == soft.CLENSHAW)
+                (nw, ns) == soft.CLENSHAW
         g = to_host(p.inverse(to_dev(c, dev, prec)))
         assert relerr(g, oracle.inverse(B, c)) <= TOL[prec]
     Bs, cs = inputs.uneven_batch(10, [4, 16, 64, 256], seed=9)

@@ -1,5 +1,7 @@
-"""The inverse DWT by Clenshaw's backward summation (inverse "shape" 0x0),
-through the C-ABI, against the oracle and against the matrix-core inverse.
+"""The DWT pair by Clenshaw-type recurrences ("shape" 0x0): the inverse by
+Clenshaw's backward summation and the forward by its transpose (the
+adjoint-Clenshaw evaluation, sums over beta reduced across lanes), through the
+C-ABI, against the oracle and against the matrix-core DWTs.
 
 Bars as for the other inverse paths: FP64 1e-11 relative to the oracle
 (max-norm), FP32 4e-6 and FP32-split 1e-6 against the FP64 oracle on the same
@@ -43,9 +45,10 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def clenshaw(plan):
+def clenshaw(plan, directions=(1,)):
     for i in range(len(plan.describe()["dwt_launches"])):
-        plan.set_dwt_shape(i, 1, *soft.CLENSHAW)
+        for d in directions:
+            plan.set_dwt_shape(i, d, *soft.CLENSHAW)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_split"])
@@ -86,16 +89,75 @@ def test_clenshaw_uneven_matches_oracle(oracle, dev):
         assert relerr(gf, oracle.inverse(B, cs[f])) <= 1e-11, (f, B)
 
 
-def test_clenshaw_only_for_the_inverse(dev):
-    with soft.Plan(8) as p:
-        with pytest.raises(soft.SoftError):
-            p.set_dwt_shape(0, 0, *soft.CLENSHAW)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_split"])
+@pytest.mark.parametrize("B", [1, 2, 4, 8, 16, 32, 64, 128])
+def test_clenshaw_forward_matches_oracle(oracle, dev, prec, B):
+    """The adjoint-Clenshaw forward on random (not band-limited) grids: the
+    quadrature sum itself."""
+    g = rounded(inputs.grid_random(B, 200 + B), prec)
+    with soft.Plan(B, precision=prec) as p:
+        clenshaw(p, (0,))
+        assert p.describe()["dwt_launches"][0]["forward"] == list(soft.CLENSHAW)
+        c = host(p.forward(to_dev(g, dev, prec)))
+    err = relerr(c, oracle.forward(B, g))
+    print(f"forward B={B} {prec}: {err:.2e}")
+    assert err <= TOL[prec]
+
+
+def test_clenshaw_forward_adjoint_batch_uneven(oracle, dev):
+    """soft_adjoint_inverse (unweighted, no V) and a batch of three against the
+    matrix-core forward of the same plan; an uneven plan against the oracle."""
+    B, n = 16, 3
+    g = to_dev(np.stack([inputs.grid_random(B, 210 + f) for f in range(n)]), dev)
+    with soft.Plan(B, n) as p:
+        want_f, want_a = p.forward(g).clone(), p.adjoint_inverse(g).clone()
+        clenshaw(p, (0,))
+        got_f, got_a = p.forward(g), p.adjoint_inverse(g)
+        torch.cuda.synchronize()
+        for got, want in ((got_f, want_f), (got_a, want_a)):
+            assert float((got - want).abs().max() / want.abs().max()) <= 1e-13
+    Bs, _ = inputs.uneven_batch(8, [2, 8, 32, 64], seed=21)
+    gs = [inputs.grid_random(B, 220 + f) for f, B in enumerate(Bs)]
+    with soft.UnevenPlan(Bs) as p:
+        clenshaw(p, (0, 1))
+        c = host(p.forward(to_dev(np.concatenate([x.reshape(-1) for x in gs]), dev)))
+    for f, B in enumerate(Bs):
+        cf = c[p.coeff_offsets[f]:p.coeff_offsets[f + 1]]
+        assert relerr(cf, oracle.forward(B, gs[f])) <= 1e-11, (f, B)
+
+
+@pytest.mark.parametrize("B", [256, 512])
+def test_clenshaw_large_against_oracle(oracle, dev, B):
+    """2B = 512 and 1024: both Clenshaw directions against the oracle on
+    sampled beta slices (inverse; the long-double oracle at B = 512) and
+    sampled order pairs (forward of the band-limited grid)."""
+    c = inputs.coeffs_decay(B, 230 + B)
+    with soft.Plan(B) as p:
+        clenshaw(p, (0, 1))
+        gd = p.inverse(to_dev(c, dev))
+        cd = host(p.forward(gd))
+        g = host(gd)
+        del gd
+    torch.cuda.empty_cache()
+    prec = "f80" if B == 512 else "f64"
+    for j in (0, B + 3, 2 * B - 1):
+        err = relerr(g[:, j, :], oracle.inverse_slice(B, c, j, prec=prec))
+        print(f"B={B} inverse slice {j}: {err:.2e}")
+        assert err <= (1e-9 if B == 512 else 1e-11), j
+    pairs = [(0, 0), (B - 1, 1 - B), (-(B // 2), 7), (B // 4, B // 4 - 1)]
+    want = oracle.forward_pairs(B, g, pairs)
+    for k, (m, mp) in enumerate(pairs):
+        l0 = max(abs(m), abs(mp))
+        got = np.array([cd[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
+        err = np.abs(got - want[k, l0:]).max() / np.abs(c).max()
+        print(f"B={B} forward pair {(m, mp)}: {err:.2e}")
+        assert err <= (1e-9 if B == 512 else 1e-11), (m, mp)
 
 
 @pytest.mark.parametrize("B", [256, 512])
 def test_clenshaw_large_agrees_with_mfma(dev, B):
-    """2B = 512 and 1024: the Clenshaw inverse against the matrix-core inverse
-    of the same plan (itself pinned to the oracle by the parity tests)."""
+    """2B = 512 and 1024: the Clenshaw inverse and forward against the
+    matrix-core DWTs of the same plan (same sums, another order)."""
     c = to_dev(inputs.coeffs_decay(B, 190 + B), dev)
     with soft.Plan(B) as p:
         want = p.inverse(c)
@@ -105,5 +167,12 @@ def test_clenshaw_large_agrees_with_mfma(dev, B):
         err = float((got - want).abs().max() / want.abs().max())
         print(f"B={B}: {err:.2e}")
         assert err <= 1e-12
-        del got, want
+        want_c = p.forward(got).clone()
+        clenshaw(p, (0,))
+        got_c = p.forward(got)
+        torch.cuda.synchronize()
+        err = float((got_c - want_c).abs().max() / want_c.abs().max())
+        print(f"B={B} forward: {err:.2e}")
+        assert err <= 1e-12
+        del got, want, got_c, want_c
     torch.cuda.empty_cache()
