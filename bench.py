@@ -1215,7 +1215,37 @@ def main():
         out["ceilings"] = ceilings(16 * (2 * B) ** 3)
     if args.calibrate_copy:
         out["copy_calibration_bytes"] = calibrate_copy()
+    out["summary"] = summary(out, legs)
     print(json.dumps(out))
+
+
+def summary(out, legs):
+    """One compact entry per leg, last in the line (so a tail of it shows
+    every leg): v = throughput, ms = median inverse and forward ms, rf = the
+    dominant kernel's roofline fraction, inv / fwd = the worst error against
+    the oracle over the leg's samples as [max-norm, L2] (inverse) and
+    [max-norm, L2, largest per-degree] (forward), x = speedup over the leg's
+    FP64 (or eager) counterpart; 3 significant digits."""
+    def worst(rep, key, n):
+        return [sig(max(r[key].get(k, 0.0) for r in rep), 2) for k in ("max_rel", "l2_rel", "deg_rel_max")[:n]]
+
+    res = {}
+    for name, r in legs.items():
+        rf = r.get("roofline") or {}
+        rep = r.get("err_vs_oracle")
+        e = {"v": sig(r["value"]) if r.get("value") is not None else None}
+        if r.get("inverse_ms"):
+            e["ms"] = [sig(r["inverse_ms"]["median"]), sig(r["forward_ms"]["median"])]
+        if rf:
+            e["rf"] = sig(rf["frac"], 2)
+        if rep:
+            e["inv"] = worst(rep, "inverse", 2)
+            e["fwd"] = worst(rep, "forward", 3)
+        for k in ("speedup_vs_fp64", "speedup_vs_eager"):
+            if k in r:
+                e["x"] = r[k]
+        res[name] = e
+    return res
 
 
 if __name__ == "__main__":

@@ -72,7 +72,7 @@ typedef struct soft_plan_s *soft_plan_t;
  *                    (about 2^-24 of d) on bf16 matrix cores, which keeps d
  *                    to about 2^-32 relative, so the DWT error is that of
  *                    FP32 data rather than of FP32 d; relative error about
- *                    1e-6 or below at B <= 512 for data of unit scale.
+ *                    1e-6 or below at B <= 1024 for data of unit scale.
  */
 typedef enum {
     SOFT_FP64 = 0,
@@ -115,8 +115,9 @@ enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u, SOFT_PLAN_GRAPH = 4u };
 typedef enum {
     SOFT_OK = 0,
     SOFT_ERR_INVALID = -1,     /* null pointer, B < 1, batch < 1, unknown precision or flag, wrong device */
-    SOFT_ERR_UNSUPPORTED = -2, /* valid for the paper but not built here: B not a power of two or B > 512,
-                                  more than 65535 functions in one plan */
+    SOFT_ERR_UNSUPPORTED = -2, /* valid for the paper but not built here: B not a power of two, B > 1024
+                                  (B > 512 for the matching entry points), more than 65535 functions in
+                                  one plan */
     SOFT_ERR_OOM = -3,         /* device or host allocation failed at plan time */
     SOFT_ERR_HIP = -4          /* a HIP runtime call or kernel launch failed */
 } soft_status;
@@ -124,7 +125,17 @@ typedef enum {
 /*
  * soft_plan -- plan `batch` transforms of bandwidth B (Sect. 2.3: a function
  * of bandwidth B lives in H_B, degrees l < B).
- *   B          bandwidth, a power of two with 1 <= B <= 512.
+ *   B          bandwidth, a power of two with 1 <= B <= 1024.  At B = 1024
+ *              (2B = 2048) the seeds d(l0, l0, m'; b_j) that the recurrence
+ *              needs reach about 2^-1240, below double precision's range:
+ *              that band keeps such seeds scaled by 2^1000 and the DWT runs
+ *              those recurrences scaled until they pass 2^-200 (Sect. 5
+ *              names B = 512 as the size where double precision alone falls
+ *              short on its CPU design).  An FP64 plan at B = 1024 needs
+ *              about 310 GB with the caller's grid and coefficients and
+ *              fails with SOFT_ERR_OOM on one 288 GB GPU; an FP32 or
+ *              FP32-split plan with SOFT_INPLACE_OK holds about 82 GB (162 GB
+ *              with the caller's buffers).
  *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
  *   flags      any of SOFT_PLAN_TUNE, SOFT_INPLACE_OK and SOFT_PLAN_GRAPH;
@@ -147,7 +158,7 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
  * soft_plan_uneven -- plan one call over n functions of mixed bandwidths
  * (the batched transform over uneven bandwidths: each function keeps its own
  * B, grid and coefficient count).
- *   B_list     host array of n bandwidths, each a power of two <= 512, in
+ *   B_list     host array of n bandwidths, each a power of two <= 1024, in
  *              the order the functions are stored; read during the call only.
  *   n          number of functions, 1 <= n <= 65535.
  *   precision, flags, out   as for soft_plan.
@@ -420,6 +431,46 @@ int soft_match(soft_match_t match, const void *a, const void *b, void *grid, lon
  * or SOFT_ERR_HIP.
  */
 int soft_match_argmax_noalloc(int B, int n, int precision, const void *grid, long long *index, hipStream_t stream);
+
+/*
+ * soft_sh_forward -- spherical-harmonic coefficients of n functions on the
+ * sphere (the inputs of rotational matching, Sect. 1), by the sampling
+ * theorem of Sect. 2.3 at m' = 0:
+ *   a(l, m) = sum_{j,k} w_B(j) f(theta_j, phi_k) conj(Y_l^m(theta_j, phi_k)),
+ *   Y_l^m(theta, phi) = sqrt((2l+1)/(4 pi)) e^{i m phi} d(l, 0, m; theta),
+ * the orthonormal spherical harmonics with the Condon-Shortley phase (d(l, 0, m)
+ * of Sect. 2.2 is the textbook d^l_{m0}); exact for functions of degree < B.
+ *   B          bandwidth, a power of two <= 512; n >= 1 functions (<= 65535).
+ *   precision  a soft_precision (complex128 data for SOFT_FP64, complex64
+ *              otherwise; the arithmetic is FP64 in every precision).
+ *   f          device, n sample grids [2B][2B], f(theta_j, phi_k) at
+ *              j * 2B + k with theta_j = (2j+1) pi/(4B), phi_k = k pi/B (read only).
+ *   a          device, n x B^2 coefficients, (l, m) at l^2 + m + l (written).
+ * Allocates nothing.  Returns SOFT_OK, SOFT_ERR_INVALID, SOFT_ERR_UNSUPPORTED
+ * or SOFT_ERR_HIP.
+ */
+int soft_sh_forward(int B, int n, int precision, const void *f, void *a, hipStream_t stream);
+
+/*
+ * soft_match_refine -- the rotation of each pair read off its correlation
+ * grid (as written by soft_match) at its maximum index (from soft_match or
+ * soft_match_argmax), refined below the grid spacing: along each axis a
+ * parabola through Re C at the maximum and its two neighbours (periodic in
+ * alpha and gamma; none at the first and last beta sample) moves the grid
+ * coordinate by (c- - c+) / (2 (c- - 2 c0 + c+)) when the three values bend
+ * down, clamped to half a step.  With a = coefficients of f and b of g
+ * (f°(l, M, M') = a(l, M) conj(b(l, M'))), the result is the rotation R with
+ * g(w) = f(R^-1 w), R = Rz(alpha) Ry(beta) Rz(gamma): (alpha, beta, gamma)
+ * = (gamma_k, beta_j, alpha_i) at the refined grid coordinates (i, j, k)
+ * (the outer angles swap because d(l, m, m') of Sect. 2.2 is the transpose of
+ * the textbook d^l_{m m'}).
+ *   grid    device, the head's n grids (read only).
+ *   index   device, n int64 grid maxima; an index of -1 gives NaN angles.
+ *   angles  device, n x 3 doubles (alpha, beta, gamma) (written).
+ * Returns SOFT_OK, SOFT_ERR_INVALID or SOFT_ERR_HIP.
+ */
+int soft_match_refine(soft_match_t match, const void *grid, const long long *index, double *angles,
+                      hipStream_t stream);
 
 /* soft_match_destroy -- release the head and its soft_plan, after waiting for the
  * work of its last call as soft_plan_destroy does (NULL ignored). */

@@ -248,3 +248,69 @@ def correlation_coeffs_vjp(B, a, b, g):
 def argmax_real(grid):
     """Flat index of the largest real part (the first one on exact ties)."""
     return int(np.argmax(np.asarray(grid).real.reshape(-1)))
+
+
+# ---------------------------------------------------------------------------
+# Functions on the sphere (the rotational-matching application of Sect. 1)
+# ---------------------------------------------------------------------------
+
+def sh_forward(B, f):
+    """Spherical-harmonic coefficients of a function on the sphere sampled at
+    (theta_j, phi_k) = ((2j+1) pi/(4B), k pi/B), j, k < 2B (the beta and
+    alpha samples of the sampling theorem, Sect. 2.3, at m' = 0):
+        a(l, m) = sum_{j,k} w_B(j) f[j, k] conj(Y(l, m; theta_j, phi_k)),
+        Y(l, m; theta, phi) = sqrt((2l+1)/(4 pi)) e^{i m phi} d(l, 0, m; theta),
+    d as defined in Sect. 2.2 (d(l, 0, m) is the textbook d^l_{m0}, so Y is
+    the orthonormal spherical harmonic with the Condon-Shortley phase).  The
+    quadrature is exact for functions of degree < B.  Returns B^2 complex
+    values, (l, m) at l^2 + m + l."""
+    f = _c128(f)
+    N = 2 * B
+    assert f.shape == (N, N)
+    w = weights(B)
+    phi = np.arange(N) * np.pi / B
+    a = np.zeros(B * B, np.complex128)
+    for m in range(1 - B, B):
+        F = (f * np.exp(-1j * m * phi)[None, :]).sum(axis=1)
+        for j in range(N):
+            d = wigner_d_grid(B, 0, m, j)
+            for l in range(abs(m), B):
+                a[sh_index(l, m)] += np.sqrt((2 * l + 1) / (4 * np.pi)) * w[j] * d[l] * F[j]
+    return a
+
+
+def rotation_of_index(B, idx):
+    """Euler angles (alpha, beta, gamma) of the rotation R = Rz(alpha) Ry(beta)
+    Rz(gamma) read off the correlation grid of a = coefficients of f and
+    b = coefficients of g: the grid point (alpha_i, beta_j, gamma_k) of flat
+    index (i*2B + j)*2B + k is the rotation with g(w) = f(R^-1 w) at
+    (alpha, beta, gamma) = (gamma_k, beta_j, alpha_i) (the roles of the
+    outer angles swap because d(l, m, m') of Sect. 2.2 is the transpose of
+    the textbook d^l_{m m'})."""
+    N = 2 * B
+    i, j, k = idx // (N * N), (idx // N) % N, idx % N
+    return (k * np.pi / B, (2 * j + 1) * np.pi / (4 * B), i * np.pi / B)
+
+
+def refine_quadratic(B, grid, idx):
+    """Sub-grid refinement of a correlation maximum: along each grid axis a
+    parabola through Re C at the maximum and its two neighbours (periodic in
+    alpha and gamma; none at the first and last beta sample) moves the grid
+    coordinate by (c- - c+) / (2 (c- - 2 c0 + c+)), clamped to [-1/2, 1/2],
+    and the moved coordinates are read as in ``rotation_of_index``.  Returns
+    (alpha, beta, gamma)."""
+    N = 2 * B
+    g = np.asarray(grid).reshape(N, N, N).real
+    i, j, k = idx // (N * N), (idx // N) % N, idx % N
+    c0 = g[i, j, k]
+
+    def step(cm, cp):
+        den = cm - 2.0 * c0 + cp
+        if not den < 0.0:
+            return 0.0
+        return min(0.5, max(-0.5, (cm - cp) / (2.0 * den)))
+
+    di = step(g[(i - 1) % N, j, k], g[(i + 1) % N, j, k])
+    dk = step(g[i, j, (k - 1) % N], g[i, j, (k + 1) % N])
+    dj = step(g[i, j - 1, k], g[i, j + 1, k]) if 0 < j < N - 1 else 0.0
+    return ((k + dk) * np.pi / B, (2 * (j + dj) + 1) * np.pi / (4 * B), (i + di) * np.pi / B)

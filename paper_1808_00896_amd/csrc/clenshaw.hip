@@ -48,8 +48,8 @@
 namespace soft {
 namespace {
 
-__device__ __forceinline__ int coeff_flat(int l, int m, int mp) {
-    return l * (4 * l * l - 1) / 3 + (m + l) * (2 * l + 1) + (mp + l);
+__device__ __forceinline__ long long coeff_flat(int l, int m, int mp) {
+    return (long long)l * (4 * l * l - 1) / 3 + (m + l) * (2 * l + 1) + (mp + l);
 }
 
 template <int PR, int NB>
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(1024 / NB) void k_idwt_clenshaw(DwtTables tab, cons
         const int j = threadIdx.x + h * NT;
         const bool jin = j < N;
         x[h] = tab.cosb[it.jbase + (jin ? j : 0)];
-        seed[h] = tab.seed[it.seed_off + (jin ? j : 0)];
+        seed[h] = tab.seed[it.seed_off + (jin ? j : 0)];  // 2B <= 1024: never an extended-range seed
     }
     __syncthreads();
 

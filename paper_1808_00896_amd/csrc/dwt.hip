@@ -71,7 +71,18 @@ __device__ __forceinline__ DD two_sum(double a, double b) {
 // Seed d(l0, l0, m'; b_j) = sqrt((2 l0)!/((l0+m')!(l0-m')!)) cos^{l0+m'}(b/2)
 // sin^{l0-m'}(b/2) for the representative (l0 = m >= m' >= 0), Sect. 2.2.
 // The exponent is summed in double-double so only the final exp rounds.
-__device__ __forceinline__ double seed_d(double2 lb, double4 t, int m, int mp) {
+//
+// Extended range (xr, the bands of 2B = 2048).  Up to B = 512 every seed
+// whose recurrence reaches 1e-20 before degree B is above 2^-700, but at
+// B = 1024 such seeds go down to about 2^-1240 (for instance m = m' = 375
+// near b = 2.39, whose d(l) reach 0.04 by l = 1023): below double
+// precision's range.  There a seed under e^-700 is stored as -(seed * 2^1000)
+// (seeds are never negative otherwise) and the kernels run that lane's
+// recurrence scaled (panel_fill); seeds under 2^-2000 are 0.
+constexpr double kXrScale = 0x1p1000, kXrUnscale = 0x1p-1000;
+constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;  // ln 2 = hi + lo
+
+__device__ __forceinline__ double seed_d(double2 lb, double4 t, int m, int mp, bool xr) {
     const double P = (double)(m + mp), Q = (double)(m - mp);
     DD a = two_prod(P, t.x);
     a.lo = fma(P, t.y, a.lo);
@@ -80,8 +91,17 @@ __device__ __forceinline__ double seed_d(double2 lb, double4 t, int m, int mp) {
     const DD s1 = two_sum(lb.x, a.hi);
     const DD s2 = two_sum(s1.hi, c.hi);
     const double lo = lb.y + a.lo + c.lo + s1.lo + s2.lo;
-    if (s2.hi < -745.0) return 0.0;
-    return exp(s2.hi) * (1.0 + lo);  // exp(hi + lo) to O(lo^2), |lo| < 1e-12
+    if (!xr || s2.hi >= -700.0) {
+        if (s2.hi < -745.0) return 0.0;
+        return exp(s2.hi) * (1.0 + lo);  // exp(hi + lo) to O(lo^2), |lo| < 1e-12
+    }
+    // exp(hi + lo) 2^1000 = exp(r) 2^(q + 1000) with r = hi + lo - q ln 2 in double-double
+    const double q = rint(s2.hi * M_LOG2E);
+    if (q < -2000.0) return 0.0;
+    const DD qa = two_prod(q, kLn2Hi);
+    const DD r = two_sum(s2.hi, -qa.hi);
+    const double rlo = ((r.lo - qa.lo) - q * kLn2Lo) + lo;
+    return -ldexp(exp(r.hi) * (1.0 + rlo), (int)q + 1000);
 }
 
 // Rescaled three-term recurrence.  Eq. "Wigner_d_recurrence" reads, for the
@@ -129,7 +149,7 @@ __global__ __launch_bounds__(256) void k_fill_seeds(PlanView p, double *__restri
     if (e >= (long long)p.G * p.N) return;
     const int g = (int)(e / p.N), j = (int)(e - (long long)g * p.N);
     const GroupInfo gi = p.grp[g];
-    seed[e] = seed_d(p.lbin[g], p.lcs[j], gi.m, gi.mp);
+    seed[e] = seed_d(p.lbin[g], p.lcs[j], gi.m, gi.mp, p.N >= 2048);
 }
 
 // ---------------------------------------------------------------------------
@@ -148,9 +168,10 @@ __global__ __launch_bounds__(256) void k_fill_seeds(PlanView p, double *__restri
 constexpr int kRowFwd = 66;
 constexpr int kRowInv = 68;
 
-// 32-bit flat index of f°(l, m, m') (fits for l < 512: l(4l^2-1)/3 < 2^31).
-__device__ __forceinline__ int coeff_index32(int l, int m, int mp) {
-    return l * (4 * l * l - 1) / 3 + (m + l) * (2 * l + 1) + (mp + l);
+// Flat index of f°(l, m, m') (64-bit: at B = 1024 twice the index of the
+// real part passes 2^31).
+__device__ __forceinline__ long long coeff_index64(int l, int m, int mp) {
+    return (long long)l * (4 * l * l - 1) / 3 + (m + l) * (2 * l + 1) + (mp + l);
 }
 
 // s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), fenced so the
@@ -194,6 +215,51 @@ __device__ __forceinline__ void panel_put(double *slotp, double e) {
     }
 }
 
+// A lane's seed as stored (seed_d): e(l0) and its scale xs (1, or 2^-1000
+// for an extended-range seed).
+__device__ __forceinline__ void seed_load(double sd, bool in, double &e, double &xs) {
+    e = in ? fabs(sd) : 0.0;
+    xs = sd < 0.0 ? kXrUnscale : 1.0;
+}
+
+// One panel of a lane's recurrence: rows r = 0..15 (pan[r * RS], pan offset
+// by the lane) get e(l0 + lp + r), and (ecur, eprev) advance 16 degrees with
+// the panel's coefficients c.  With XR (the launch shapes that cover
+// 2B = 2048), a lane whose seed was stored scaled runs e = d 2^1000 / s_l
+// and writes e * xs; once |e| passes 2^800 the scale is folded back (d grows
+// by at most about 2^116 over 16 degrees, so e stays far below the double
+// range in between).  A wave without a scaled lane takes the plain loop.
+template <int PR, int RS, bool XR>
+__device__ __forceinline__ void panel_fill(double *pan, const double2 (&c)[16], double x, double &ecur,
+                                           double &eprev, double &xs) {
+    if constexpr (XR) {
+        if (__builtin_amdgcn_ballot_w64(xs != 1.0) != 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                panel_put<PR>(&pan[r * RS], ecur * xs);
+                const double u = fma(c[r].x, x, -c[r].y);
+                const double en = fma(u, ecur, -eprev);
+                eprev = ecur;
+                ecur = en;
+            }
+            if (xs != 1.0 && fabs(ecur) >= 0x1p800) {
+                ecur *= kXrUnscale;
+                eprev *= kXrUnscale;
+                xs = 1.0;
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        panel_put<PR>(&pan[r * RS], ecur);
+        const double u = fma(c[r].x, x, -c[r].y);
+        const double en = fma(u, ecur, -eprev);
+        eprev = ecur;
+        ecur = en;
+    }
+}
+
 // MFMA output rows: FP64 16x16x4 puts C[lane/16 + 4 r] in register r, FP32
 // 16x16x4 puts C[4 (lane/16) + r].
 template <int PR>
@@ -204,17 +270,22 @@ __device__ __forceinline__ int out_row(int krow, int r) {
 // ---------------------------------------------------------------------------
 // Forward DWT: panel x X on MFMA.
 // ---------------------------------------------------------------------------
+// The launch shapes that cover 2B = 2048 run extended-range seeds.
+template <int NW, int NSUB>
+constexpr bool xr_of() { return NW * NSUB * 64 >= 2048; }
+
 // The panel loop of one forward work item: recurrence, panels, MFMA
-// contraction and the fused reorder epilogue (shared by both forward kernels).
-// On entry x, ecur and eprev hold each lane's cos b_j and first two
-// recurrence values, xb the B operand, c the first panel's recurrence
-// coefficients, and srow the item's s_l (visible after the first barrier).
+// contraction and the fused reorder epilogue.  On entry x, ecur, eprev and
+// xs hold each lane's cos b_j, first two recurrence values and seed scale,
+// xb the B operand, c the first panel's recurrence coefficients, and srow
+// the item's s_l (visible after the first barrier).
 template <int NW, int NSUB, int PR>
 __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd], const double *srow,
                                                 const WorkItem &it, const double2 *__restrict__ Rr,
                                                 double2 (&c)[16], typename PrecT<PR>::R (&xb)[NSUB][16],
                                                 double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
-                                                typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
+                                                double (&xs)[NSUB], typename PrecT<PR>::C *__restrict__ coeffs,
+                                                int apply_v) {
     using R = typename PrecT<PR>::R;
     const int B = it.B;
     const int m = it.m, mp = it.mp, mask = it.mask;
@@ -246,14 +317,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
             for (int a = 0; a < 4; ++a) acc[a] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    panel_put<PR>(&pan[r * kRowFwd + lane], ecur[h]);
-                    const double u = fma(c[r].x, x[h], -c[r].y);
-                    const double en = fma(u, ecur[h], -eprev[h]);
-                    eprev[h] = ecur[h];
-                    ecur[h] = en;
-                }
+                panel_fill<PR, kRowFwd, xr_of<NW, NSUB>()>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
                 double a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s) a[s] = pan[col * kRowFwd + 4 * s + krow];
@@ -279,14 +343,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
             for (int a = 0; a < 4; ++a) acc[a] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    panel_put<PR>(&pan[r * kRowFwd + lane], ecur[h]);
-                    const double u = fma(c[r].x, x[h], -c[r].y);
-                    const double en = fma(u, ecur[h], -eprev[h]);
-                    eprev[h] = ecur[h];
-                    ecur[h] = en;
-                }
+                panel_fill<PR, kRowFwd, xr_of<NW, NSUB>()>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
                 float2 a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s)
@@ -344,7 +401,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
                 for (int w = 0; w < NW; ++w) sum += panel[w][t];
                 const int l = m + li;
                 const double f = e_sign[q] * srow[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
-                out[2 * coeff_index32(l, e_mm[q], e_mmp[q]) + (t & 1)] = (R)(sum * f);
+                out[2 * coeff_index64(l, e_mm[q], e_mmp[q]) + (t & 1)] = (R)(sum * f);
             }
         }
         // every wave has read the partial sums before any panel is refilled
@@ -431,7 +488,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     __builtin_amdgcn_sched_barrier(0);
 
     R xb[NSUB][16];
-    double x[NSUB], ecur[NSUB], eprev[NSUB];
+    double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int jbase = (wave * NSUB + h) * 64;
@@ -445,13 +502,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         }
         const bool jin = jbase + lane < N;
         x[h] = jin ? xv[h] : 0.0;
-        ecur[h] = jin ? sv[h] : 0.0;
+        seed_load(sv[h], jin, ecur[h], xs[h]);
         eprev[h] = 0.0;
     }
 #pragma unroll
     for (int q = 0; q < RSN; ++q)
         if ((int)threadIdx.x + q * NW * 64 < L) srow[threadIdx.x + q * NW * 64] = rs[q];
-    fwd_item_panels<NW, NSUB, PR>(panel, srow, it, Rr, c, xb, x, ecur, eprev, coeffs, apply_v);
+    fwd_item_panels<NW, NSUB, PR>(panel, srow, it, Rr, c, xb, x, ecur, eprev, xs, coeffs, apply_v);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,7 +570,7 @@ __device__ __forceinline__ void inv_gather(InvGather<NT, KC, R> &st, const doubl
         const int e = threadIdx.x + k * NT;
         if (e < KC * 16) {
             const int li = min(c * KC + (e >> 4), L - 1);
-            st.raw[k] = cin[2 * coeff_index32(it.m + li, st.mm[k], st.mmp[k]) + (e & 1)];
+            st.raw[k] = cin[2 * coeff_index64(it.m + li, st.mm[k], st.mmp[k]) + (e & 1)];
             st.rs[k] = rscale[it.goff + li];
         }
     }
@@ -552,7 +609,7 @@ template <int NW, int NSUB, int PR>
 __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], const typename PrecT<PR>::R (&bop)[4],
                                           double2 (&c)[16], const double2 *__restrict__ Rr, int lp,
                                           const double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
-                                          v4d (&acc)[NSUB][4]) {
+                                          double (&xs)[NSUB], v4d (&acc)[NSUB][4]) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, krow = lane >> 4;
     double *pan = panel[threadIdx.x >> 6];
@@ -560,14 +617,7 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
     if constexpr (PR == P32S) bopb = bf4((float)bop[0], (float)bop[1], (float)bop[2], (float)bop[3]);
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            panel_put<PR>(&pan[r * kRowInv + lane], ecur[h]);
-            const double u = fma(c[r].x, x[h], -c[r].y);
-            const double en = fma(u, ecur[h], -eprev[h]);
-            eprev[h] = ecur[h];
-            ecur[h] = en;
-        }
+        panel_fill<PR, kRowInv, xr_of<NW, NSUB>()>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
         if constexpr (PR == P64) {
             double a[4][4];
 #pragma unroll
@@ -679,7 +729,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     inv_gather_init<NT, KC, R>(st, it);
     inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 0);
 
-    double x[NSUB], ecur[NSUB], eprev[NSUB];
+    double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int j = (wave * NSUB + h) * 64 + lane;
@@ -687,7 +737,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         const double xv = tab.cosb[it.jbase + (jin ? j : 0)];
         const double sv = tab.seed[it.seed_off + (jin ? j : 0)];
         x[h] = jin ? xv : 0.0;
-        ecur[h] = jin ? sv : 0.0;
+        seed_load(sv, jin, ecur[h], xs[h]);
         eprev[h] = 0.0;
     }
     v4d acc[NSUB][4];
@@ -711,7 +761,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
-        inv_panel<NW, NSUB, PR>(panel, bop, c, Rr, lp, x, ecur, eprev, acc);
+        inv_panel<NW, NSUB, PR>(panel, bop, c, Rr, lp, x, ecur, eprev, xs, acc);
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
         if (lp + 16 - ch * KC == KC || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
@@ -739,7 +789,7 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
 }
 
 // Launch shapes (waves x subsets of 64 beta samples per wave): 1x1, 2x1, 4x1,
-// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4; a shape covers items with
+// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4, 8x4; a shape covers items with
 // 2B <= waves*subsets*64.
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
@@ -763,6 +813,7 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_FWD(4, 2)
     SOFT_DWT_FWD(8, 2)
     SOFT_DWT_FWD(4, 4)
+    SOFT_DWT_FWD(8, 4)
     SOFT_DWT_FWD(16, 1)
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
@@ -790,6 +841,7 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
     SOFT_DWT_INV(4, 2)
     SOFT_DWT_INV(8, 2)
     SOFT_DWT_INV(4, 4)
+    SOFT_DWT_INV(8, 4)
     SOFT_DWT_INV(16, 1)
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;

@@ -221,11 +221,14 @@ enum Kind { GAMMA_FWD = 0, ALPHA_FWD = 1, ALPHA_INV = 2, GAMMA_INV = 3 };
 // 4.8 ms at B = 512, where the gamma pass is faster with the full tile.
 template <int N, typename C, int KIND, bool INGRID>
 struct Tile {
-    static constexpr int TF = N <= 64 ? 32 : (N <= 256 ? 16 : (sizeof(C) == 16 ? 8 : 16));
+    // At 2B = 2048 a tile of T sequences takes T * 34 KB (complex128) or
+    // T * 17 KB (complex64) of LDS: T = 4 or 8 keeps it within a CU's 160 KB.
+    static constexpr int TF = N <= 64 ? 32 : (N <= 256 ? 16 : (N <= 1024 ? (sizeof(C) == 16 ? 8 : 16)
+                                                                          : (sizeof(C) == 16 ? 4 : 8)));
     static constexpr bool INV = KIND == ALPHA_INV || KIND == GAMMA_INV;
-    static constexpr int TL0 = N >= 1024 && !INGRID && INV ? TF / 2 : TF;
-    static constexpr int T0 =
-        N >= 1024 && !INGRID && (INV || (KIND == ALPHA_FWD && sizeof(C) == 8)) ? TF / 2 : TF;
+    static constexpr bool HALF = N == 1024 && !INGRID;
+    static constexpr int TL0 = HALF && INV ? TF / 2 : TF;
+    static constexpr int T0 = HALF && (INV || (KIND == ALPHA_FWD && sizeof(C) == 8)) ? TF / 2 : TF;
     static constexpr int T = T0 < N ? T0 : N;
     static constexpr int TL = TL0 < N ? TL0 : N;
     static constexpr int NT = T * Shape<N>::P;
@@ -578,6 +581,7 @@ hipError_t dispatch(const PlanView &p, const C *in, C *out, int flags, hipStream
         case 256: return launch_kind<256, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
         case 512: return launch_kind<512, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
         case 1024: return launch_kind<1024, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
+        case 2048: return launch_kind<2048, KIND, SIGN, C, INGRID>(p, in, out, flags, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -627,6 +631,7 @@ hipError_t launch_fft_gamma_inv_argmax(const PlanView &p, const C *t1, ArgBest *
         case 256: return launch_argmax_pass<256, C>(p, t1, part, s);
         case 512: return launch_argmax_pass<512, C>(p, t1, part, s);
         case 1024: return launch_argmax_pass<1024, C>(p, t1, part, s);
+        case 2048: return launch_argmax_pass<2048, C>(p, t1, part, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -645,6 +650,7 @@ int argmax_blocks_of(int N) {
         case 256: return 256 / Tile<256, C, GAMMA_INV, false>::T * 256;
         case 512: return 512 / Tile<512, C, GAMMA_INV, false>::T * 512;
         case 1024: return 1024 / Tile<1024, C, GAMMA_INV, false>::T * 1024;
+        case 2048: return 2048 / Tile<2048, C, GAMMA_INV, false>::T * 2048;
         default: return 0;
     }
 }

@@ -262,6 +262,7 @@ std::pair<int, int> shape_for(int N, bool forward, int precision) {
     // 2B = 1024: four waves of four subsets, two blocks per CU, except for the
     // FP32 inverses (FP32: 8x2; FP32-split, whose four-subset inverse needs
     // more registers than two blocks leave: 16x1)
+    if (N == 2048) return {8, 4};
     if (forward || precision == SOFT_FP64) return {4, 4};
     return precision == SOFT_FP32 ? std::make_pair(8, 2) : std::make_pair(16, 1);
 }
@@ -516,7 +517,13 @@ hipError_t run_match(soft_match_s *m, const void *a, const void *b, void *grid, 
 
 // DWT launch shapes the library instantiates (waves, subsets of 64 beta
 // samples per wave).
-constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}, {4, 4}};
+constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2}, {4, 2}, {8, 2}, {16, 1}, {4, 4},
+                                 {8, 4}};
+
+// Largest bandwidth of a plan (2B = 2048 beta samples), and of the Clenshaw
+// DWT forms (one beta sample per lane, at most 1024 lanes a block).
+constexpr int kMaxB = 1024;
+constexpr int kMaxClenshawN = 1024;
 
 // Autotuner: for every DWT launch group and direction, time each shape that
 // covers the group's largest 2B (and is at most twice that), and also the
@@ -544,7 +551,7 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
                 const int cover = sh[0] * sh[1] * 64;
                 if (cover >= lg.nmax && cover <= 2 * lg.nmax) cand.emplace_back(sh[0], sh[1]);
             }
-            cand.emplace_back(0, 0);
+            if (lg.nmax <= kMaxClenshawN) cand.emplace_back(0, 0);
             auto launch = [&](std::pair<int, int> c) {
                 if (c.first == 0)
                     return dir == 0 ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax,
@@ -955,7 +962,7 @@ extern "C" {
 
 int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out) {
     if (!out || B < 1 || batch < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
-    if (!is_pow2(B) || B > 512 || batch > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
+    if (!is_pow2(B) || B > kMaxB || batch > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     std::vector<int> Bs;
     try {
         Bs.assign(batch, B);
@@ -971,7 +978,7 @@ int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, so
         if (B_list[i] < 1) return SOFT_ERR_INVALID;
     if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     for (int i = 0; i < n; ++i)
-        if (!is_pow2(B_list[i]) || B_list[i] > 512) return SOFT_ERR_UNSUPPORTED;
+        if (!is_pow2(B_list[i]) || B_list[i] > kMaxB) return SOFT_ERR_UNSUPPORTED;
     return make_plan(B_list, n, precision, flags, out);
 }
 
@@ -981,7 +988,7 @@ int soft_plan_check(const int *B_list, int n, int precision, unsigned flags) {
         if (B_list[i] < 1) return SOFT_ERR_INVALID;
     if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     for (int i = 0; i < n; ++i)
-        if (!is_pow2(B_list[i]) || B_list[i] > 512) return SOFT_ERR_UNSUPPORTED;
+        if (!is_pow2(B_list[i]) || B_list[i] > kMaxB) return SOFT_ERR_UNSUPPORTED;
     soft_plan_s *p = new (std::nothrow) soft_plan_s;
     if (!p) return SOFT_ERR_OOM;
     int rc;
@@ -1036,6 +1043,7 @@ int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves,
         return SOFT_ERR_INVALID;
     LaunchGroup &lg = p->groups[launch];
     if (waves == 0 && subsets == 0) {  // the Clenshaw forms
+        if (lg.nmax > kMaxClenshawN) return SOFT_ERR_INVALID;
         (direction == 0 ? lg.nw_f : lg.nw_i) = 0;
         (direction == 0 ? lg.nsub_f : lg.nsub_i) = 0;
         return SOFT_OK;
@@ -1237,6 +1245,27 @@ int soft_match(soft_match_t m, const void *a, const void *b, void *grid, long lo
         default: e = run_match<soft::P32S>(m, a, b, grid, index, s); break;
     }
     if (e == hipSuccess) e = mark_done(m->plan, s);
+    return hip_status(e);
+}
+
+int soft_sh_forward(int B, int n, int precision, const void *f, void *a, hipStream_t s) {
+    if (B < 1 || n < 1 || !f || !a || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!is_pow2(B) || B > 512 || n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
+    const hipError_t e =
+        precision == SOFT_FP64
+            ? soft::launch_sh_forward<double2>(B, n, static_cast<const double2 *>(f), static_cast<double2 *>(a), s)
+            : soft::launch_sh_forward<float2>(B, n, static_cast<const float2 *>(f), static_cast<float2 *>(a), s);
+    return hip_status(e);
+}
+
+int soft_match_refine(soft_match_t m, const void *grid, const long long *index, double *angles, hipStream_t s) {
+    if (!m || !grid || !index || !angles) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, grid, angles);
+    if (rc != SOFT_OK) return rc;
+    const hipError_t e =
+        m->plan->precision == SOFT_FP64
+            ? soft::launch_match_refine<double2>(m->B, m->n, static_cast<const double2 *>(grid), index, angles, s)
+            : soft::launch_match_refine<float2>(m->B, m->n, static_cast<const float2 *>(grid), index, angles, s);
     return hip_status(e);
 }
 

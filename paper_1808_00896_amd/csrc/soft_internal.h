@@ -292,6 +292,15 @@ hipError_t launch_argmax_final(const ArgBest *part, int nblk, int n, long long *
 template <typename C>
 hipError_t launch_argmax_real(const C *x, long long count, int n, void *workspace, long long *index, hipStream_t s);
 
+// Functions on the sphere (sphere.hip): the spherical-harmonic transform of
+// n functions sampled on the (2B)^2 grid (theta_j, phi_k) into B^2
+// coefficients each, and the refined rotation read-out of n correlation
+// grids at their maxima (3 doubles per pair).
+template <typename C>
+hipError_t launch_sh_forward(int B, int n, const C *f, C *a, hipStream_t s);
+template <typename C>
+hipError_t launch_match_refine(int B, int n, const C *grid, const long long *index, double *out, hipStream_t s);
+
 // Device ceilings (probe.hip): a streaming copy of `words` 16-byte words,
 // and dependent-chain loops (kind 0: FP64 vector FMA, 1: FP64 MFMA 16x16x4,
 // 2: FP32 MFMA 16x16x4) over `blocks` blocks of 4 waves; probe_flop_count is

@@ -74,6 +74,10 @@ def lib():
         L.soft_match_argmax.argtypes = [vp, vp, vp, vp]
         L.soft_match_argmax_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.soft_match.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.soft_sh_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.soft_sh_forward.restype = ctypes.c_int
+        L.soft_match_refine.argtypes = [vp, vp, vp, vp, vp]
+        L.soft_match_refine.restype = ctypes.c_int
         L.soft_match_destroy.argtypes = [vp]
         for name in ("soft_match_plan", "soft_match_sizes", "soft_match_plan_soft", "soft_match_coeffs",
                      "soft_match_coeffs_vjp", "soft_match_argmax", "soft_match_argmax_noalloc", "soft_match",
@@ -154,7 +158,7 @@ def soft_plan_describe(plan):
     return json.loads(buf.value.decode())
 
 
-DWT_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (8, 2), (16, 1), (4, 4))
+DWT_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (8, 2), (16, 1), (4, 4), (8, 4))
 CLENSHAW = (0, 0)  # inverse-DWT "shape" of the Clenshaw kernel (soft_plan_set_dwt_shape)
 
 
@@ -276,6 +280,18 @@ def soft_probe_flops(kind, blocks, iters, sink, stream=None):
     _check(lib().soft_probe_flops(int(kind), int(blocks), int(iters), _ptr(sink), _stream(stream)),
            "soft_probe_flops")
     return lib().soft_probe_flop_count(int(kind), int(blocks), int(iters))
+
+
+def soft_sh_forward(B, n, precision, f, a, stream=None):
+    """Spherical-harmonic coefficients a (n x B^2) of n sampled functions f (n x 2B x 2B)."""
+    _check(lib().soft_sh_forward(int(B), int(n), int(precision), _ptr(f), _ptr(a), _stream(stream)),
+           "soft_sh_forward")
+
+
+def soft_match_refine(match, grid, index, angles, stream=None):
+    """Refined rotation (alpha, beta, gamma) of each pair at its grid maximum."""
+    _check(lib().soft_match_refine(ctypes.c_void_p(match), _ptr(grid), _ptr(index), _ptr(angles),
+                                   _stream(stream)), "soft_match_refine")
 
 
 def soft_match(match, a, b, grid, index, stream=None):
@@ -539,6 +555,36 @@ class MatchPlan:
         idx = index if index is not None else torch.empty(self.n, dtype=torch.int64, device=self.device)
         soft_match(self.handle, a, b, None, idx)
         return idx
+
+    def sh_forward(self, f):
+        """Spherical-harmonic coefficients [n, B^2] (or [B^2]) of functions
+        sampled on the sphere, f: [n, 2B, 2B] (or [2B, 2B]) with
+        f[j, k] = f(theta_j = (2j+1) pi/(4B), phi_k = k pi/B)."""
+        N = 2 * self.B
+        shape = (N, N) if self.n == 1 else (self.n, N, N)
+        f = self._chk(f, shape, "f")
+        a = torch.empty(self.sh_shape(), dtype=self.dtype, device=self.device)
+        soft_sh_forward(self.B, self.n, self.precision, f, a)
+        return a
+
+    def refine(self, grid, index):
+        """Rotation (alpha, beta, gamma) [n, 3] (float64, intrinsic z-y-z) of
+        each pair at its grid maximum, refined below the grid spacing."""
+        grid = self._chk(grid, self.plan.grid_shape(), "grid")
+        if index.dtype != torch.int64 or index.numel() != self.n or index.device != self.device:
+            raise ValueError("index: n int64 on the head's device")
+        angles = torch.empty(self.n, 3, dtype=torch.float64, device=self.device)
+        soft_match_refine(self.handle, grid, index.contiguous(), angles)
+        return angles
+
+    def match_rotation(self, f, g):
+        """The whole matching pipeline for sampled functions on the sphere:
+        the rotation R (Euler angles [n, 3], R = Rz(alpha) Ry(beta) Rz(gamma))
+        with g(w) ~ f(R^-1 w) best on the SO(3) grid, refined below it.
+        Returns (angles, grid index)."""
+        a, b = self.sh_forward(f), self.sh_forward(g)
+        grid, idx = self.match(a, b)
+        return self.refine(grid, idx), idx
 
     def close(self):
         if getattr(self, "handle", None):

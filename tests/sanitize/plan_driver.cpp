@@ -20,7 +20,7 @@ int main() {
     // plan host sides: one bandwidth, batches, mixed bandwidths, every precision and flag
     const std::vector<std::vector<int>> cases = {
         {1}, {2}, {4}, {8}, {16}, {32}, {64}, {128}, {256}, {512}, {16, 16, 16},
-        {1, 2, 4, 8, 16, 32, 64, 128}, {128, 4, 64, 4, 32, 1}, {512, 2, 256}};
+        {1, 2, 4, 8, 16, 32, 64, 128}, {128, 4, 64, 4, 32, 1}, {512, 2, 256}, {1024}};
     for (const auto &bs : cases)
         for (int prec = 0; prec < 3; ++prec)
             for (unsigned flags : {0u, 2u, 4u})
@@ -29,14 +29,14 @@ int main() {
     for (size_t i = 0; i < many.size(); ++i) many[i] = 1 << (i % 8);
     expect(soft_plan_check(many.data(), (int)many.size(), 2, 0), SOFT_OK, "300 functions");
     // argument errors
-    const int odd[2] = {8, 12}, zero[2] = {8, 0}, big[1] = {1024};
+    const int odd[2] = {8, 12}, zero[2] = {8, 0}, big[1] = {2048};
     expect(soft_plan_check(nullptr, 1, 0, 0), SOFT_ERR_INVALID, "null list");
     expect(soft_plan_check(odd, 0, 0, 0), SOFT_ERR_INVALID, "n = 0");
     expect(soft_plan_check(zero, 2, 0, 0), SOFT_ERR_INVALID, "B = 0");
     expect(soft_plan_check(odd, 1, 3, 0), SOFT_ERR_INVALID, "precision");
     expect(soft_plan_check(odd, 1, 0, 8u), SOFT_ERR_INVALID, "flag");
     expect(soft_plan_check(odd, 2, 0, 0), SOFT_ERR_UNSUPPORTED, "B = 12");
-    expect(soft_plan_check(big, 1, 0, 0), SOFT_ERR_UNSUPPORTED, "B = 1024");
+    expect(soft_plan_check(big, 1, 0, 0), SOFT_ERR_UNSUPPORTED, "B = 2048");
     soft_plan_t h = nullptr;
     expect(soft_plan(0, 1, 0, 0, &h), SOFT_ERR_INVALID, "soft_plan B = 0");
     expect(soft_plan(8, 1, 0, 0, nullptr), SOFT_ERR_INVALID, "soft_plan out");

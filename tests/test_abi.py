@@ -53,7 +53,7 @@ def test_argument_errors_need_no_gpu(L):
     assert L.soft_plan(8, 1, 7, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 1, 0, 0, None) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(6, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
-    assert L.soft_plan(1024, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
+    assert L.soft_plan(2048, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert L.soft_plan(8, 65536, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert L.soft_match_plan(8, 65536, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert h.value is None
@@ -76,7 +76,7 @@ def test_uneven_argument_errors_need_no_gpu(L):
     assert L.soft_plan_uneven(bad, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     odd = (ctypes.c_int * 3)(8, 12, 4)
     assert L.soft_plan_uneven(odd, 3, 1, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
-    big = (ctypes.c_int * 2)(8, 1024)
+    big = (ctypes.c_int * 2)(8, 2048)
     assert L.soft_plan_uneven(big, 2, 2, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert h.value is None
     assert L.soft_plan_offsets(None, None, None) == soft.SOFT_ERR_INVALID
@@ -99,6 +99,10 @@ def test_match_argument_errors_need_no_gpu(L):
     assert L.soft_match_coeffs(None, None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_coeffs_vjp(None, None, None, None, None, None, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_argmax(None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_refine(None, None, None, None, None) == soft.SOFT_ERR_INVALID
+    assert L.soft_sh_forward(0, 1, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == soft.SOFT_ERR_INVALID
+    assert L.soft_sh_forward(8, 1, 0, None, ctypes.c_void_p(16), None) == soft.SOFT_ERR_INVALID
+    assert L.soft_sh_forward(12, 1, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == soft.SOFT_ERR_UNSUPPORTED
     one = ctypes.c_void_p(16)  # never dereferenced: the arguments are rejected first
     assert L.soft_match_argmax_noalloc(8, 2, 0, None, one, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_argmax_noalloc(8, 2, 0, one, None, None) == soft.SOFT_ERR_INVALID

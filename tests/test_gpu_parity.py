@@ -168,7 +168,7 @@ def test_plan_errors_on_gpu(dev):
     with pytest.raises(soft.SoftError):
         soft.Plan(3)
     with pytest.raises(soft.SoftError):
-        soft.Plan(1024)
+        soft.Plan(2048)
     p = soft.Plan(4)
     with pytest.raises(ValueError):
         p.inverse(torch.zeros(10, dtype=torch.complex128, device=dev))

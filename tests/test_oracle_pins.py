@@ -155,6 +155,28 @@ def test_weights_discrete_orthogonality(oracle, B):
     assert worst < 1e-14, worst
 
 
+@pytest.mark.parametrize("B,m,mp,err64", [(512, 185, 185, False), (1024, 375, 375, True), (1024, 375, -375, True)])
+def test_seed_range_double_vs_long_double(oracle, B, m, mp, err64):
+    """Discrete orthogonality of one order pair's d(l; beta_j), l < B, against
+    the weights (the identity pinned above): the long-double build keeps it
+    at B = 1024, where seeds of Sect. 2.2 that the recurrence needs lie below
+    double precision's range (about 2^-1240 for these pairs), so the double
+    build loses d values of order 0.04 and breaks it; at B = 512 the smallest
+    seed that matters is about 2^-660 and both builds hold it."""
+    w = oracle.weights(B, "f80")
+    N = 2 * B
+    l0 = max(abs(m), abs(mp))
+    want = np.diag([2 * np.pi / ((2 * l + 1) * B) for l in range(l0, B)])
+    for prec in ("f80", "f64"):
+        D = np.array([oracle.wigner_d_grid(B, m, mp, j, prec)[l0:] for j in range(N)]).T
+        G = (D * w) @ D.T
+        worst = float(np.abs(G - want).max() / want.max())
+        if prec == "f80" or not err64:
+            assert worst < 1e-10, (prec, worst)
+        else:
+            assert worst > 1e-3, (prec, worst)
+
+
 def test_weights_against_numpy_evaluation(oracle):
     """The long-double weights round to the double ones."""
     for B in (3, 16, 100):
@@ -415,3 +437,104 @@ def test_correlation_vjp_matches_finite_differences(oracle):
 def test_argmax_real_first_on_ties(oracle):
     x = np.array([1.0, 3.0 + 5j, 3.0, -2.0, 3.0 - 1j])
     assert oracle.argmax_real(x) == 1
+
+
+# --------------------------------------------------------------------------
+# Functions on the sphere: spherical-harmonic transform and rotation read-out
+# (the rotational matching of Sect. 1), pinned to scipy's spherical harmonics
+# and rotations.
+# --------------------------------------------------------------------------
+
+def _sphere_grid(B):
+    N = 2 * B
+    theta = (2 * np.arange(N) + 1) * np.pi / (4 * B)
+    phi = np.arange(N) * np.pi / B
+    return np.meshgrid(theta, phi, indexing="ij")
+
+
+def _synth(B, a, theta, phi):
+    """sum_{l<B, |m|<=l} a(l,m) Y_l^m(theta, phi) with scipy's orthonormal Y."""
+    from scipy.special import sph_harm_y
+    out = np.zeros(np.broadcast(theta, phi).shape, complex)
+    for l in range(B):
+        for m in range(-l, l + 1):
+            out += a[l * l + m + l] * sph_harm_y(l, m, theta, phi)
+    return out
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 5, 8])
+def test_sh_forward_inverts_scipy_synthesis(oracle, B):
+    """Sampled sum of scipy's Y_l^m (Condon-Shortley phase) -> the same
+    coefficients: the sampling theorem of Sect. 2.3 at m' = 0."""
+    rng = np.random.default_rng(40 + B)
+    a = rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)
+    TH, PH = _sphere_grid(B)
+    assert np.abs(oracle.sh_forward(B, _synth(B, a, TH, PH)) - a).max() <= 1e-13 * np.abs(a).max()
+
+
+def test_sh_forward_single_harmonic(oracle):
+    """One Y_l^m gives the unit vector at (l, m) (orthonormality under the
+    quadrature of eq. "weights")."""
+    B = 6
+    TH, PH = _sphere_grid(B)
+    for l, m in ((0, 0), (3, -2), (5, 5), (4, 1)):
+        a = np.zeros(B * B, complex)
+        a[l * l + m + l] = 1.0
+        got = oracle.sh_forward(B, _synth(B, a, TH, PH))
+        assert np.abs(got - a).max() <= 1e-13, (l, m)
+
+
+def _rotated_samples(B, a, R):
+    """g(w) = f(R^-1 w) on the sampling grid, f = sum a(l,m) Y_l^m."""
+    TH, PH = _sphere_grid(B)
+    pts = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1).reshape(-1, 3)
+    q = R.inv().apply(pts)
+    th = np.arccos(np.clip(q[:, 2], -1, 1))
+    ph = np.arctan2(q[:, 1], q[:, 0])
+    return _synth(B, a, th, ph).reshape(TH.shape)
+
+
+def test_correlation_peak_reads_the_rotation(oracle):
+    """For g = f rotated by a grid rotation R0 (scipy's Rotation, intrinsic
+    z-y-z), the correlation grid of (a, b) = (coefficients of f, of g) peaks
+    at the index whose read-out is R0."""
+    from scipy.spatial.transform import Rotation
+    B = 6
+    N = 2 * B
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)
+    beta = (2 * np.arange(N) + 1) * np.pi / (4 * B)
+    for _ in range(4):
+        i0, j0, k0 = rng.integers(0, N, 3)
+        R0 = Rotation.from_euler("ZYZ", (k0 * np.pi / B, beta[j0], i0 * np.pi / B))
+        b = oracle.sh_forward(B, _rotated_samples(B, a, R0))
+        grid = oracle.inverse(B, oracle.correlation_coeffs(B, a, b))
+        idx = oracle.argmax_real(grid)
+        assert idx == (i0 * N + j0) * N + k0
+        got = Rotation.from_euler("ZYZ", oracle.rotation_of_index(B, idx))
+        assert (got.inv() * R0).magnitude() <= 1e-12
+
+
+def test_quadratic_refinement_moves_toward_off_grid_rotation(oracle):
+    """An off-grid R0: the refined read-out lies closer to R0 than the grid
+    maximum's, and a parabola through three samples of a parabola finds its
+    vertex exactly."""
+    from scipy.spatial.transform import Rotation
+    B = 8
+    rng = np.random.default_rng(11)
+    a = (rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)) * 0.5 ** np.repeat(
+        np.arange(B), [2 * l + 1 for l in range(B)])
+    R0 = Rotation.from_euler("ZYZ", (1.1, 1.0, 2.3))
+    b = oracle.sh_forward(B, _rotated_samples(B, a, R0))
+    grid = oracle.inverse(B, oracle.correlation_coeffs(B, a, b))
+    idx = oracle.argmax_real(grid)
+    coarse = Rotation.from_euler("ZYZ", oracle.rotation_of_index(B, idx))
+    fine = Rotation.from_euler("ZYZ", oracle.refine_quadratic(B, grid, idx))
+    assert (fine.inv() * R0).magnitude() < 0.6 * (coarse.inv() * R0).magnitude()
+    # a separable parabola peaked off grid: the vertex itself
+    N = 2 * B
+    i, j, k = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    par = -((i - 5.3) ** 2) - 2 * (j - 7.8) ** 2 - 0.5 * (k - 3.1) ** 2
+    got = oracle.refine_quadratic(B, par, oracle.argmax_real(par))
+    want = (3.1 * np.pi / B, (2 * 7.8 + 1) * np.pi / (4 * B), 5.3 * np.pi / B)
+    assert np.allclose(got, want, atol=1e-12)
