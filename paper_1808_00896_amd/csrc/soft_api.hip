@@ -350,13 +350,13 @@ const WorkItem *items_of(const soft_plan_s *p, const LaunchGroup &lg) {
 // band's FFT pass writes nfunc N^3 elements, an inverse-DWT launch 8 slot rows
 // of up to 2B samples per item.
 template <typename C>
-bool band_streams(const Band &b) {
+bool band_streams(const Band &b, double from) {
     const double n = b.view.N;
-    return soft::stream_stores((double)b.view.nfunc * n * n * n * sizeof(C), b.view.N);
+    return soft::stream_stores((double)b.view.nfunc * n * n * n * sizeof(C), b.view.N, from);
 }
 template <typename C>
 bool group_streams(const LaunchGroup &lg) {
-    return soft::stream_stores((double)lg.nitems * soft::kSlots * lg.nmax * sizeof(C), lg.nmax);
+    return soft::stream_stores((double)lg.nitems * soft::kSlots * lg.nmax * sizeof(C), lg.nmax, soft::kStreamFrom);
 }
 
 template <int PR>
@@ -370,10 +370,10 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
     hipError_t e = hipSuccess;
     for (const Band &b : p->bands) {
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_FWD);
-        if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, band_streams<C>(b), s);
+        if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, band_streams<C>(b, soft::kStreamFrom), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_FWD);
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_FWD);
-        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, band_streams<C>(b), s);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, band_streams<C>(b, soft::kStreamFromLate), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_FWD);
     }
     for (const LaunchGroup &lg : p->groups) {
@@ -416,12 +416,12 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     }
     for (const Band &b : p->bands) {
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_INV);
-        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, band_streams<C>(b), s);
+        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, band_streams<C>(b, soft::kStreamFromLate), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_INV);
         if (e == hipSuccess)
             e = part ? soft::launch_fft_gamma_inv_argmax<C>(b.view, t1, part, s)
-                     : soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, band_streams<C>(b), s);
+                     : soft::launch_fft_gamma_inv<C>(b.view, t1, gout, scaled, band_streams<C>(b, soft::kStreamFromLate), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_INV);
     }
     return e;

@@ -36,13 +36,21 @@ constexpr int kFlagScale = 1;   // apply w_B(j) (FFT) or V_B (inverse DWT)
 constexpr int kFlagStream = 2;  // write the main output with streaming stores
 
 // Whether a launch writes its main output with streaming (non-temporal)
-// stores: bytes written by the launch, nmax its largest 2B.  Measured on
-// MI355X: they speed up the next kernel when the array written exceeds the
-// 256 MB last-level cache (B = 128 with 1 to 64 functions, B = 256: 2-4 %
-// per step); below that, plain stores leave the array cached for the next
-// kernel.  At 2B = 1024 streaming slowed the FFT passes down (B = 512: 3 %
-// per step), so those launches keep plain stores.
-inline bool stream_stores(double bytes, int nmax) { return nmax < 1024 && bytes > 192.0 * (1 << 20); }
+// stores: bytes written by the launch, nmax its largest 2B, above the
+// launch kind's threshold.  Measured on MI355X: they speed up the next kernel
+// when the array written is well beyond the 256 MB last-level cache (B = 128
+// with 4 to 64 functions, B = 256: 2-4 % per step); below that, plain stores
+// leave much of the array cached for the next kernel.  Near the cache size
+// the passes differ: at one B = 128 FP64 function (268 MB arrays) plain
+// stores in the alpha passes and the inverse gamma pass, and streaming ones
+// in the forward gamma pass and the iDWT, gave the fastest step of all 32
+// choices (616 -> 588 us), and two functions or four FP32 ones (536 MB)
+// were no slower or 2-3 % faster; so the former stream from 600 MB, the
+// latter from 192 MB.  At 2B = 1024 streaming slowed the FFT passes down
+// (B = 512: 3 % per step), so those launches keep plain stores.
+constexpr double kStreamFrom = 192.0 * (1 << 20);      // forward gamma pass, iDWT
+constexpr double kStreamFromLate = 600.0 * (1 << 20);  // alpha passes, inverse gamma pass
+inline bool stream_stores(double bytes, int nmax, double from) { return nmax < 1024 && bytes > from; }
 
 // Running argmax of Re over a grid: the larger value wins, on equal values
 // the smaller flat index; NaN never wins (comparisons with NaN are false), so
