@@ -109,8 +109,20 @@ typedef enum {
  *                   launch per kernel.  Results are bit-identical to calls
  *                   without the flag.  Calls made while stage timing is
  *                   enabled run without the graph.
+ *   SOFT_BETA_HALVES every band with 2B >= 128 holds its per-order-pair beta
+ *                   samples (the S workspace) for half of the beta samples
+ *                   at a time: the two halves j < 2B/4 or j >= 3(2B)/4 and
+ *                   the middle half (each closed under j -> 2B-1-j, so the
+ *                   members at pi - beta stay with their pair), each running
+ *                   its own alpha FFT pass and DWT launch; the forward adds
+ *                   the second half's sums to the first's.  Halves that
+ *                   workspace (FP64, B = 512: 17.2 -> 8.6 GB) for two more
+ *                   launches per direction.  Inverse results are
+ *                   bit-identical to a plan without the flag; forward
+ *                   results differ by the rounding of that one addition.
+ *                   Bands with 2B = 2048 always run this way.
  */
-enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u, SOFT_PLAN_GRAPH = 4u };
+enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u, SOFT_PLAN_GRAPH = 4u, SOFT_BETA_HALVES = 8u };
 
 typedef enum {
     SOFT_OK = 0,
@@ -131,11 +143,12 @@ typedef enum {
  *              that band keeps such seeds scaled by 2^1000 and the DWT runs
  *              those recurrences scaled until they pass 2^-200 (Sect. 5
  *              names B = 512 as the size where double precision alone falls
- *              short on its CPU design).  An FP64 plan at B = 1024 needs
- *              about 310 GB with the caller's grid and coefficients and
- *              fails with SOFT_ERR_OOM on one 288 GB GPU; an FP32 or
- *              FP32-split plan with SOFT_INPLACE_OK holds about 82 GB (162 GB
- *              with the caller's buffers).
+ *              short on its CPU design).  That band also runs in two beta
+ *              halves (the per-order-pair samples are held for half of the
+ *              beta samples at a time): with SOFT_INPLACE_OK an FP64 plan
+ *              at B = 1024 holds about 82 GB (242 GB with the caller's grid
+ *              and coefficients), an FP32 or FP32-split plan about 47 GB;
+ *              without the flag the FFT intermediate adds one grid's size.
  *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
  *   flags      any of SOFT_PLAN_TUNE, SOFT_INPLACE_OK and SOFT_PLAN_GRAPH;
@@ -143,7 +156,8 @@ typedef enum {
  *   out        receives the plan handle; unchanged on error.
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
- * samples, or about (2B)^3 with SOFT_INPLACE_OK; per distinct bandwidth,
+ * samples, or about (2B)^3 with SOFT_INPLACE_OK, half of that for the
+ * samples at 2B = 2048; per distinct bandwidth,
  * 12 bytes per recurrence row, about B^3/6 rows, and the 8-byte seeds d(l0, l0, m'; b_j) of every symmetry group at
  * every beta sample, B(B+1)/2 x 2B of them) and its tables (quadrature
  * weights, Wigner-d seed constants, FFT twiddles, symmetry groups, work
@@ -195,8 +209,9 @@ int soft_plan_sizes(soft_plan_t plan, size_t *grid_elems, size_t *coeff_elems,
 /*
  * soft_plan_describe -- a one-line JSON description of the plan (bands,
  * functions, workspace bytes, whether it was made with SOFT_INPLACE_OK, and
- * per DWT launch its largest 2B, work items, forward and inverse launch
- * shapes and whether they were tuned), written to
+ * per DWT launch its largest 2B, the number of beta halves it runs in (2 for
+ * 2B = 2048, see soft_plan), work items, forward and inverse launch shapes
+ * and whether they were tuned), written to
  * buf as a NUL-terminated string truncated to len - 1 characters.
  * Returns SOFT_OK or SOFT_ERR_INVALID (NULL plan or buf, len == 0).
  */
@@ -209,8 +224,9 @@ int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
  *   direction  0 = forward DWT, 1 = inverse DWT.
  *   waves, subsets  one of the built shapes (waves x subsets of 64 beta
  *              samples per wave): 1x1, 2x1, 4x1, 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4,
- *              covering the launch: waves * subsets * 64 >= its largest 2B;
- *              or 0x0: the DWT by Clenshaw-type recurrences on the FP64
+ *              8x4, covering the launch: waves * subsets * 64 >= its beta
+ *              rows (its largest 2B, or 2B/2 for a launch in beta halves);
+ *              or 0x0 (launches with 2B <= 1024): the DWT by Clenshaw-type recurrences on the FP64
  *              vector unit instead of the matrix contraction (Sect. 2.4),
  *              one beta sample per lane: the inverse by Clenshaw's backward
  *              summation over degrees, the forward by its transpose (the

@@ -270,22 +270,24 @@ __device__ __forceinline__ int out_row(int krow, int r) {
 // ---------------------------------------------------------------------------
 // Forward DWT: panel x X on MFMA.
 // ---------------------------------------------------------------------------
-// The launch shapes that cover 2B = 2048 run extended-range seeds.
-template <int NW, int NSUB>
-constexpr bool xr_of() { return NW * NSUB * 64 >= 2048; }
+// Beta sample of chunk-local row k (JMap; n = 0: the whole range, k = j).
+__device__ __forceinline__ int beta_of(const JMap &jm, int k) {
+    return jm.n ? k + (k < jm.split ? jm.off0 : jm.off1) : k;
+}
 
 // The panel loop of one forward work item: recurrence, panels, MFMA
 // contraction and the fused reorder epilogue.  On entry x, ecur, eprev and
 // xs hold each lane's cos b_j, first two recurrence values and seed scale,
 // xb the B operand, c the first panel's recurrence coefficients, and srow
-// the item's s_l (visible after the first barrier).
-template <int NW, int NSUB, int PR>
+// the item's s_l (visible after the first barrier).  flags: kFlagScale
+// applies V_B, kFlagAccum adds to the coefficients (the second beta half).
+template <int NW, int NSUB, int PR, bool XR>
 __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd], const double *srow,
                                                 const WorkItem &it, const double2 *__restrict__ Rr,
                                                 double2 (&c)[16], typename PrecT<PR>::R (&xb)[NSUB][16],
                                                 double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
                                                 double (&xs)[NSUB], typename PrecT<PR>::C *__restrict__ coeffs,
-                                                int apply_v) {
+                                                int flags) {
     using R = typename PrecT<PR>::R;
     const int B = it.B;
     const int m = it.m, mp = it.mp, mask = it.mask;
@@ -294,6 +296,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
     const int col = lane & 15, krow = lane >> 4;
     double *pan = panel[wave];
     R *out = reinterpret_cast<R *>(coeffs + it.coeff_off);
+    const bool apply_v = flags & kFlagScale, accum = flags & kFlagAccum;
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
     // Epilogue constants: thread slot q writes column t = threadIdx.x + q*NT of
     // every panel; its member, sign and part never change, because the
@@ -317,7 +320,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
             for (int a = 0; a < 4; ++a) acc[a] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-                panel_fill<PR, kRowFwd, xr_of<NW, NSUB>()>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
+                panel_fill<PR, kRowFwd, XR>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
                 double a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s) a[s] = pan[col * kRowFwd + 4 * s + krow];
@@ -343,7 +346,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
             for (int a = 0; a < 4; ++a) acc[a] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-                panel_fill<PR, kRowFwd, xr_of<NW, NSUB>()>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
+                panel_fill<PR, kRowFwd, XR>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
                 float2 a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s)
@@ -401,7 +404,8 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
                 for (int w = 0; w < NW; ++w) sum += panel[w][t];
                 const int l = m + li;
                 const double f = e_sign[q] * srow[li] * (apply_v ? (2.0 * l + 1.0) * v0 : 1.0);
-                out[2 * coeff_index64(l, e_mm[q], e_mmp[q]) + (t & 1)] = (R)(sum * f);
+                R *o = &out[2 * coeff_index64(l, e_mm[q], e_mmp[q]) + (t & 1)];
+                *o = accum ? (R)((double)*o + sum * f) : (R)(sum * f);
             }
         }
         // every wave has read the partial sums before any panel is refilled
@@ -423,18 +427,23 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
 // next panel's are loaded after this panel's LDS reads, behind the MFMAs.
 // Four accumulators keep four MFMA chains in flight (in the FP32 modes each
 // covers 16 beta samples; the split mode keeps the lo products apart).
-template <int NW, int NSUB, int PR>
+// Lane row k of the launch's beta rows (all 2B, or one beta half of jm) is
+// beta sample beta_of(jm, k); XR: extended-range seeds (2B = 2048).
+template <int NW, int NSUB, int PR, bool XR>
 __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
                                                     const typename PrecT<PR>::C *__restrict__ S,
-                                                    typename PrecT<PR>::C *__restrict__ coeffs, int apply_v) {
+                                                    typename PrecT<PR>::C *__restrict__ coeffs, int flags, JMap jm) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
-    // s_l of the group's degrees: at most B = NW*NSUB*32 for this shape.
+    // s_l of the group's degrees: at most B <= NW*NSUB*64 (a launch in beta
+    // halves covers B rows).
+    constexpr int SROW = NW * NSUB * 64;
     __shared__ double panel[NW][16 * kRowFwd];
-    __shared__ double srow[NW * NSUB * 32];
+    __shared__ double srow[SROW];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
-    const int B = it.B, N = 2 * B;
+    const int B = it.B;
+    const int N = jm.n ? jm.n : 2 * B;  // beta rows of S (samples past N are zeroed)
     const int m = it.m, mp = it.mp, mask = it.mask;
     const int L = B - m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -474,14 +483,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
             raw[h][s / 2].x = v[0];
             raw[h][s / 2].y = v[1];
         }
-        const int j = jbase + lane;
-        xv[h] = tab.cosb[it.jbase + (j < N ? j : 0)];
-        sv[h] = tab.seed[it.seed_off + (j < N ? j : 0)];
+        const int j = beta_of(jm, jbase + lane < N ? jbase + lane : 0);
+        xv[h] = tab.cosb[it.jbase + j];
+        sv[h] = tab.seed[it.seed_off + j];
     }
-    // s_l of the group's rows (L <= B <= NW*NSUB*32, so at most RSN per
-    // thread), read in the panel epilogues (visible after the first panel's
-    // barrier)
-    constexpr int RSN = (NSUB + 1) / 2;
+    // s_l of the group's rows (L <= B <= SROW, so at most RSN per thread),
+    // read in the panel epilogues (visible after the first panel's barrier)
+    constexpr int RSN = (SROW + NW * 64 - 1) / (NW * 64);
     double rs[RSN];
 #pragma unroll
     for (int q = 0; q < RSN; ++q) rs[q] = tab.rscale[goff + min((int)threadIdx.x + q * NW * 64, L - 1)];
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
 #pragma unroll
     for (int q = 0; q < RSN; ++q)
         if ((int)threadIdx.x + q * NW * 64 < L) srow[threadIdx.x + q * NW * 64] = rs[q];
-    fwd_item_panels<NW, NSUB, PR>(panel, srow, it, Rr, c, xb, x, ecur, eprev, xs, coeffs, apply_v);
+    fwd_item_panels<NW, NSUB, PR, XR>(panel, srow, it, Rr, c, xb, x, ecur, eprev, xs, coeffs, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -605,7 +613,7 @@ __device__ __forceinline__ void inv_put(const InvGather<NT, KC, R> &st, R *buf, 
 // recurrence fills the wave's panel and advances, and the panel (A) times
 // bop (B, this lane's four coefficient values of the panel) accumulates into
 // acc on matrix cores.  Loads the next panel's recurrence coefficients into c.
-template <int NW, int NSUB, int PR>
+template <int NW, int NSUB, int PR, bool XR>
 __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], const typename PrecT<PR>::R (&bop)[4],
                                           double2 (&c)[16], const double2 *__restrict__ Rr, int lp,
                                           const double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
@@ -617,7 +625,7 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
     if constexpr (PR == P32S) bopb = bf4((float)bop[0], (float)bop[1], (float)bop[2], (float)bop[3]);
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
-        panel_fill<PR, kRowInv, xr_of<NW, NSUB>()>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
+        panel_fill<PR, kRowInv, XR>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
         if constexpr (PR == P64) {
             double a[4][4];
 #pragma unroll
@@ -670,12 +678,11 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
 // goes through the wave's panel to each slot's row of S, beta contiguous.
 template <int NSUB, int PR>
 __device__ __forceinline__ void inv_store(double *pan, const v4d (&acc)[NSUB][4], const WorkItem &it,
-                                          typename PrecT<PR>::C *__restrict__ S, bool stream) {
+                                          typename PrecT<PR>::C *__restrict__ S, bool stream, int N) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
-    const int N = 2 * it.B;
     // Register r of lane holds Y[j = 16 t + out_row(krow, r)][c = col] of tile t.
     // Transpose through the wave's panel (pairs (re, im) swizzled by j) and
     // store each slot's beta samples contiguously.
@@ -702,11 +709,11 @@ __device__ __forceinline__ void inv_store(double *pan, const v4d (&acc)[NSUB][4]
     }
 }
 
-template <int NW, int NSUB, int PR>
+template <int NW, int NSUB, int PR, bool XR>
 __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
                                                     const typename PrecT<PR>::C *__restrict__ coeffs,
-                                                    typename PrecT<PR>::C *__restrict__ S, int flags) {
+                                                    typename PrecT<PR>::C *__restrict__ S, int flags, JMap jm) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
     constexpr int NT = NW * 64;
@@ -715,7 +722,8 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     constexpr int KC = chunk_of<NW>();
     __shared__ R stage[2][KC * 16];
     const WorkItem it = items[item_of_block(blockIdx.x, nitems)];
-    const int B = it.B, N = 2 * B;
+    const int B = it.B;
+    const int N = jm.n ? jm.n : 2 * B;  // beta rows of S this launch writes
     const int m = it.m, mp = it.mp;
     const int L = B - m;
     const int nchunk = (L + KC - 1) / KC;
@@ -732,10 +740,11 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
-        const int j = (wave * NSUB + h) * 64 + lane;
-        const bool jin = j < N;
-        const double xv = tab.cosb[it.jbase + (jin ? j : 0)];
-        const double sv = tab.seed[it.seed_off + (jin ? j : 0)];
+        const int k = (wave * NSUB + h) * 64 + lane;
+        const bool jin = k < N;
+        const int j = beta_of(jm, jin ? k : 0);
+        const double xv = tab.cosb[it.jbase + j];
+        const double sv = tab.seed[it.seed_off + j];
         x[h] = jin ? xv : 0.0;
         seed_load(sv, jin, ecur[h], xs[h]);
         eprev[h] = 0.0;
@@ -761,7 +770,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
-        inv_panel<NW, NSUB, PR>(panel, bop, c, Rr, lp, x, ecur, eprev, xs, acc);
+        inv_panel<NW, NSUB, PR, XR>(panel, bop, c, Rr, lp, x, ecur, eprev, xs, acc);
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
         if (lp + 16 - ch * KC == KC || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
@@ -772,7 +781,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         }
     }
 
-    inv_store<NSUB, PR>(pan, acc, it, S, stream);
+    inv_store<NSUB, PR>(pan, acc, it, S, stream, N);
 }
 
 }  // namespace
@@ -789,32 +798,37 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
 }
 
 // Launch shapes (waves x subsets of 64 beta samples per wave): 1x1, 2x1, 4x1,
-// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4, 8x4; a shape covers items with
-// 2B <= waves*subsets*64.
+// 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4, 8x4; a shape covers items with beta
+// rows (2B, or jm.n) <= waves*subsets*64.  The extended-range (xr) forms
+// exist for the shapes that cover a beta half of 2B = 2048 or all of it.
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
-                          hipStream_t s) {
+                          bool accum, const JMap &jm, bool xr, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    const int av = apply_v;
+    const int fl = (apply_v ? kFlagScale : 0) | (accum ? kFlagAccum : 0);
     const dim3 grid(nitems);
-#define SOFT_DWT_FWD(NW_, NS_)                                                                               \
-    if (nw == NW_ && nsub == NS_) {                                                                          \
-        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items, nitems, \
-                           S, coeffs, av);                                                                   \
+#define SOFT_DWT_FWD(NW_, NS_, XR_)                                                                         \
+    if (nw == NW_ && nsub == NS_ && xr == XR_) {                                                             \
+        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR, XR_>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items,  \
+                           nitems, S, coeffs, fl, jm);                                                       \
         return hipGetLastError();                                                                            \
     }
-    SOFT_DWT_FWD(1, 1)
-    SOFT_DWT_FWD(2, 1)
-    SOFT_DWT_FWD(4, 1)
-    SOFT_DWT_FWD(8, 1)
-    SOFT_DWT_FWD(1, 2)
-    SOFT_DWT_FWD(2, 2)
-    SOFT_DWT_FWD(4, 2)
-    SOFT_DWT_FWD(8, 2)
-    SOFT_DWT_FWD(4, 4)
-    SOFT_DWT_FWD(8, 4)
-    SOFT_DWT_FWD(16, 1)
+    SOFT_DWT_FWD(1, 1, false)
+    SOFT_DWT_FWD(2, 1, false)
+    SOFT_DWT_FWD(4, 1, false)
+    SOFT_DWT_FWD(8, 1, false)
+    SOFT_DWT_FWD(1, 2, false)
+    SOFT_DWT_FWD(2, 2, false)
+    SOFT_DWT_FWD(4, 2, false)
+    SOFT_DWT_FWD(8, 2, false)
+    SOFT_DWT_FWD(4, 4, false)
+    SOFT_DWT_FWD(8, 4, false)
+    SOFT_DWT_FWD(16, 1, false)
+    SOFT_DWT_FWD(8, 2, true)
+    SOFT_DWT_FWD(16, 1, true)
+    SOFT_DWT_FWD(4, 4, true)
+    SOFT_DWT_FWD(8, 4, true)
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
 }
@@ -822,36 +836,42 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
 template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                          bool stream, hipStream_t s) {
+                          bool stream, const JMap &jm, bool xr, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    const int av = (apply_v ? kFlagScale : 0) | (stream ? kFlagStream : 0);
+    const int fl = (apply_v ? kFlagScale : 0) | (stream ? kFlagStream : 0);
     const dim3 grid(nitems);
-#define SOFT_DWT_INV(NW_, NS_)                                                                               \
-    if (nw == NW_ && nsub == NS_) {                                                                          \
-        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items, nitems, \
-                           coeffs, S, av);                                                                   \
+#define SOFT_DWT_INV(NW_, NS_, XR_)                                                                         \
+    if (nw == NW_ && nsub == NS_ && xr == XR_) {                                                             \
+        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR, XR_>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items,  \
+                           nitems, coeffs, S, fl, jm);                                                       \
         return hipGetLastError();                                                                            \
     }
-    SOFT_DWT_INV(1, 1)
-    SOFT_DWT_INV(2, 1)
-    SOFT_DWT_INV(4, 1)
-    SOFT_DWT_INV(8, 1)
-    SOFT_DWT_INV(1, 2)
-    SOFT_DWT_INV(2, 2)
-    SOFT_DWT_INV(4, 2)
-    SOFT_DWT_INV(8, 2)
-    SOFT_DWT_INV(4, 4)
-    SOFT_DWT_INV(8, 4)
-    SOFT_DWT_INV(16, 1)
+    SOFT_DWT_INV(1, 1, false)
+    SOFT_DWT_INV(2, 1, false)
+    SOFT_DWT_INV(4, 1, false)
+    SOFT_DWT_INV(8, 1, false)
+    SOFT_DWT_INV(1, 2, false)
+    SOFT_DWT_INV(2, 2, false)
+    SOFT_DWT_INV(4, 2, false)
+    SOFT_DWT_INV(8, 2, false)
+    SOFT_DWT_INV(4, 4, false)
+    SOFT_DWT_INV(8, 4, false)
+    SOFT_DWT_INV(16, 1, false)
+    SOFT_DWT_INV(8, 2, true)
+    SOFT_DWT_INV(16, 1, true)
+    SOFT_DWT_INV(4, 4, true)
+    SOFT_DWT_INV(8, 4, true)
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;
 }
 
 #define SOFT_DWT_INSTANTIATE(PR)                                                                          \
     template hipError_t launch_dwt_fwd<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
-                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, hipStream_t);       \
+                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, bool, const JMap &,  \
+                                           bool, hipStream_t);                                              \
     template hipError_t launch_dwt_inv<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
-                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, bool, hipStream_t);
+                                           const PrecT<PR>::C *, PrecT<PR>::C *, bool, bool, const JMap &,  \
+                                           bool, hipStream_t);
 SOFT_DWT_INSTANTIATE(P64)
 SOFT_DWT_INSTANTIATE(P32)
 SOFT_DWT_INSTANTIATE(P32S)

@@ -341,6 +341,14 @@ __device__ __forceinline__ BlockPos block_pos(int ntile, int nline) {
     return {lin % ntile, lin / ntile, (int)blockIdx.z};
 }
 
+// Beta rows of the alpha passes (PlanView::jn, a beta half of 2B = 2048 or
+// all 2B): local row k is beta sample jrow(k), and S row position of beta
+// sample j is jloc(j) (with stride jn).
+__device__ __forceinline__ int jrow(const PlanView &p, int k) { return k + (k < p.jsplit ? p.joff0 : p.joff1); }
+__device__ __forceinline__ int jloc(const PlanView &p, int j) {
+    return j - (j < p.jsplit + p.joff0 ? p.joff0 : p.joff1);
+}
+
 // Twiddle table of a band for the complex type of the plan.
 template <typename C>
 __device__ __forceinline__ const C *twiddles(const PlanView &p, int sign);
@@ -356,8 +364,8 @@ __device__ __forceinline__ const float2 *twiddles<float2>(const PlanView &p, int
 // One pass over the functions of one band (blockIdx.z = index within the
 // band; t1 holds one N^3 intermediate per such index).  Element addresses:
 //   GAMMA_FWD: block (i-tile, j): in grid[(i*N + j)*N + k], out u(j, q, i)
-//   ALPHA_FWD: block (j-tile, q): in u(j, q, i),               out S[slot*N + j']
-//   ALPHA_INV: block (j-tile, q): in S[slot*N + j'],           out u(j, q, i)
+//   ALPHA_FWD: block (j-tile, q): in u(j, q, i),               out S[slot*jn + jloc(j')]
+//   ALPHA_INV: block (j-tile, q): in S[slot*jn + jloc(j')],    out u(j, q, i)
 //   GAMMA_INV: block (i-tile, j): in u(j, q, i),               out grid[(i*N + j)*N + k]
 // with u the intermediate in the t1 or the in-grid layout (u_index).  With
 // t1, an alpha block then reads or writes one contiguous run of T*N
@@ -386,7 +394,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     const C *tw = twiddles<C>(p, SIGN);
 
     // lines: j for gamma passes (N of them), q != B for alpha passes (N - 1).
-    const BlockPos bp = block_pos(N / T, ALPHA ? N - 1 : N);
+    const BlockPos bp = block_pos((ALPHA ? p.jn : N) / T, ALPHA ? N - 1 : N);
     const int tile = bp.tile;
     const int line = ALPHA ? (bp.line < B ? bp.line : bp.line + 1) : bp.line;
     const size_t N3 = (size_t)N * N * N;
@@ -416,7 +424,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     const int p_in = transposed_in<KIND>() ? tid / T : tid % P;
     {
         constexpr int R = radix_of<N, 0>(), BPT = N / R / P;
-        const int row = tile * T + t_in;  // i (gamma) or j (alpha)
+        const int row = ALPHA ? jrow(p, tile * T + t_in) : tile * T + t_in;  // i (gamma) or j (alpha)
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
 #pragma unroll
@@ -433,7 +441,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                     } else {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
-                        x = ld_in<N>(&src[(size_t)(sl >> 1) * N + jj]);
+                        x = ld_in<N>(&src[(size_t)(sl >> 1) * p.jn + jloc(p, jj)]);
                     }
                 } else {
                     x = n == B ? mk<C>(0.0, 0.0) : ld_in<N>(&src[u_index<N, TL, INGRID>(line, n, row)]);
@@ -466,7 +474,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     // ---- last stage outputs to HBM: element b + r*N/R ----
     {
         constexpr int R = radix_of<N, LAST>(), BPT = N / R / P;
-        const int row = tile * T + t_out;
+        const int row = ALPHA ? jrow(p, tile * T + t_out) : tile * T + t_out;
         double wj = 1.0;
         if constexpr (KIND == ALPHA_FWD || KIND == GAMMA_INV) {
             if (apply_w) wj = p.w[KIND == ALPHA_FWD ? row : line];
@@ -484,7 +492,7 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
                     if (n != B) {
                         const int sl = slot_code(n < B ? n : n - N, mp_line);
                         const int jj = (sl & 1) ? N - 1 - row : row;
-                        put_c(&dst[(size_t)(sl >> 1) * N + jj], cscale(x, wj), stream);
+                        put_c(&dst[(size_t)(sl >> 1) * p.jn + jloc(p, jj)], cscale(x, wj), stream);
                     }
                 } else if constexpr (KIND == ALPHA_INV) {
                     put_c(&dst[u_index<N, TL, INGRID>(row, line, n)], x, stream);
@@ -560,7 +568,8 @@ hipError_t launch_kind(const PlanView &p, const C *in, C *out, int flags, hipStr
     constexpr bool ALPHA = KIND == ALPHA_FWD || KIND == ALPHA_INV;
     const int nline = ALPHA ? N - 1 : N;
     // Grid (tiles, lines, functions of the band); block_pos() re-deals (tile, line) across XCDs.
-    dim3 g(N / Ti::T, nline, p.nfunc);
+    // The alpha passes cover the view's beta rows (all, or one beta half).
+    dim3 g((ALPHA ? p.jn : N) / Ti::T, nline, p.nfunc);
     if constexpr (INGRID)
         hipLaunchKernelGGL((k_fft_ingrid<N, KIND, SIGN, C>), g, dim3(Ti::NT), 0, s, p, in, out, flags);
     else

@@ -36,6 +36,7 @@ using soft::WorkItem;
 
 struct Band {
     int B = 0, N = 0, G = 0;
+    int chunks = 1;            // beta halves of S (2 at 2B = 2048: soft::JMap)
     int jbase = 0, gbase = 0;  // first entry in the plan-wide beta and group tables
     long long seed_base = 0;   // first entry of the band's G x 2B seeds in the seed table
     long long Nc = 0, rows = 0, row_base = 0;
@@ -48,6 +49,8 @@ struct LaunchGroup {
     int nw_f = 1, nsub_f = 1;  // forward DWT launch shape (waves, subsets of 64 beta samples)
     int nw_i = 1, nsub_i = 1;  // inverse DWT launch shape
     int nmax = 0;              // largest 2B among the group's items
+    int chunks = 1;            // beta halves its band runs in (soft::JMap)
+    int rows = 0;              // beta rows per launch: nmax / chunks (what a shape must cover)
     int nitems = 0;
     bool tuned = false;
     size_t items_off = 0;  // byte offset of the work items in the table block
@@ -117,7 +120,7 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // the pairs (matching head) in a 16-bit grid dimension.
 constexpr int kMaxFunctions = 65535;
 
-constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE | SOFT_INPLACE_OK | SOFT_PLAN_GRAPH;
+constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE | SOFT_INPLACE_OK | SOFT_PLAN_GRAPH | SOFT_BETA_HALVES;
 
 void free_plan(soft_plan_s *p) {
     if (!p) return;
@@ -251,8 +254,9 @@ int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double 
 }
 
 // Default DWT launch shape (waves per block, subsets of 64 beta samples per
-// wave) of length N = 2B, forward and inverse: the fastest shape measured per
-// length on MI355X (SOFT_PLAN_TUNE re-measures on the plan itself).
+// wave) for N beta rows (2B, or a beta half of 2B = 2048), forward and
+// inverse: the fastest shape measured per length on MI355X (SOFT_PLAN_TUNE
+// re-measures on the plan itself).
 std::pair<int, int> shape_for(int N, bool forward, int precision) {
     if (N <= 32) return {1, 1};
     if (N == 64) return forward ? std::make_pair(1, 1) : std::make_pair(2, 1);
@@ -262,7 +266,6 @@ std::pair<int, int> shape_for(int N, bool forward, int precision) {
     // 2B = 1024: four waves of four subsets, two blocks per CU, except for the
     // FP32 inverses (FP32: 8x2; FP32-split, whose four-subset inverse needs
     // more registers than two blocks leave: 16x1)
-    if (N == 2048) return {8, 4};
     if (forward || precision == SOFT_FP64) return {4, 4};
     return precision == SOFT_FP32 ? std::make_pair(8, 2) : std::make_pair(16, 1);
 }
@@ -345,7 +348,9 @@ const WorkItem *items_of(const soft_plan_s *p, const LaunchGroup &lg) {
 
 // Forward-type transform: per band the gamma then alpha FFT pass (optional W),
 // then the DWT launches, which write the l-major coefficients (optional V).
-// soft_forward uses W and V; soft_adjoint_inverse uses neither.
+// soft_forward uses W and V; soft_adjoint_inverse uses neither.  A band in
+// beta halves (2B = 2048) runs, after its gamma pass, the alpha pass and the
+// DWT once per half; the second half's DWT adds to the first's coefficients.
 // Streaming stores (soft::stream_stores) by the bytes a launch writes: a
 // band's FFT pass writes nfunc N^3 elements, an inverse-DWT launch 8 slot rows
 // of up to 2B samples per item.
@@ -358,6 +363,20 @@ template <typename C>
 bool group_streams(const LaunchGroup &lg) {
     return soft::stream_stores((double)lg.nitems * soft::kSlots * lg.nmax * sizeof(C), lg.nmax, soft::kStreamFrom);
 }
+
+// The view of beta half c of a band (its alpha passes read or write S rows of
+// that half only), and the DWT row map of a launch group's half c.
+PlanView half_view(const Band &b, int c) {
+    PlanView v = b.view;
+    const soft::JMap m = soft::beta_chunk(b.N, c);
+    v.jn = m.n;
+    v.jsplit = m.split;
+    v.joff0 = m.off0;
+    v.joff1 = m.off1;
+    return v;
+}
+soft::JMap group_rows(const LaunchGroup &lg, int c) { return lg.chunks > 1 ? soft::beta_chunk(lg.nmax, c) : soft::JMap{}; }
+bool group_xr(const LaunchGroup &lg) { return lg.nmax >= soft::kBetaChunkN; }
 
 template <int PR>
 hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_t s, bool scaled) {
@@ -372,25 +391,37 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_FWD);
         if (e == hipSuccess) e = soft::launch_fft_gamma_fwd<C>(b.view, gin, t1, band_streams<C>(b, soft::kStreamFrom), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_GAMMA_FWD);
+        if (b.chunks > 1) continue;  // its alpha passes run per beta half below
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_FWD);
         if (e == hipSuccess) e = soft::launch_fft_alpha_fwd<C>(b.view, t1, gin, S, scaled, band_streams<C>(b, soft::kStreamFromLate), s);
         if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_FWD);
     }
     for (const LaunchGroup &lg : p->groups) {
-        if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_FWD);
-        if (e == hipSuccess)
-            e = lg.nw_f == 0
-                    ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, S, cout_, scaled, s)
-                    : soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S, cout_,
-                                               scaled, s);
-        if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_FWD);
+        for (int c = 0; c < lg.chunks; ++c) {
+            if (lg.chunks > 1) {
+                const Band &b = p->bands[lg.bands[0]];
+                if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_FWD);
+                if (e == hipSuccess)
+                    e = soft::launch_fft_alpha_fwd<C>(half_view(b, c), t1, gin, S, scaled,
+                                                      band_streams<C>(b, soft::kStreamFromLate), s);
+                if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_FWD);
+            }
+            if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_FWD);
+            if (e == hipSuccess)
+                e = lg.nw_f == 0 ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, S,
+                                                                     cout_, scaled, s)
+                                 : soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S,
+                                                            cout_, scaled, c > 0, group_rows(lg, c), group_xr(lg), s);
+            if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_FWD);
+        }
     }
     return e;
 }
 
 // Inverse-type transform: the iDWT launches (reading the l-major coefficients,
 // optional V), then per band the alpha then gamma FFT pass (optional W).
-// soft_inverse uses neither factor; soft_adjoint uses both.
+// soft_inverse uses neither factor; soft_adjoint uses both.  A band in beta
+// halves runs the iDWT and its alpha pass once per half, then its gamma pass.
 //
 // With part (a one-band plan with its own FFT intermediate) the grid is not
 // written: the last pass reduces each block's values to argmax partials
@@ -406,18 +437,31 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
     StageClock clk(p, s);
     hipError_t e = hipSuccess;
     for (const LaunchGroup &lg : p->groups) {
-        if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_INV);
-        if (e == hipSuccess)
-            e = lg.nw_i == 0 ? soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cin, S,
-                                                               scaled, group_streams<C>(lg), s)
-                             : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i, cin,
-                                                        S, scaled, group_streams<C>(lg), s);
-        if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_INV);
+        for (int c = 0; c < lg.chunks; ++c) {
+            if (e == hipSuccess) e = clk.before(SOFT_STAGE_DWT_INV);
+            if (e == hipSuccess)
+                e = lg.nw_i == 0 ? soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, cin,
+                                                                   S, scaled, group_streams<C>(lg), s)
+                                 : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i,
+                                                            cin, S, scaled, group_streams<C>(lg), group_rows(lg, c),
+                                                            group_xr(lg), s);
+            if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_INV);
+            if (lg.chunks > 1) {
+                const Band &b = p->bands[lg.bands[0]];
+                if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_INV);
+                if (e == hipSuccess)
+                    e = soft::launch_fft_alpha_inv<C>(half_view(b, c), S, t1, gout,
+                                                      band_streams<C>(b, soft::kStreamFromLate), s);
+                if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
+            }
+        }
     }
     for (const Band &b : p->bands) {
-        if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_INV);
-        if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, band_streams<C>(b, soft::kStreamFromLate), s);
-        if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
+        if (b.chunks == 1) {
+            if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_ALPHA_INV);
+            if (e == hipSuccess) e = soft::launch_fft_alpha_inv<C>(b.view, S, t1, gout, band_streams<C>(b, soft::kStreamFromLate), s);
+            if (e == hipSuccess) e = clk.after(SOFT_STAGE_FFT_ALPHA_INV);
+        }
         if (e == hipSuccess) e = clk.before(SOFT_STAGE_FFT_GAMMA_INV);
         if (e == hipSuccess)
             e = part ? soft::launch_fft_gamma_inv_argmax<C>(b.view, t1, part, s)
@@ -544,14 +588,15 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
     C *S = static_cast<C *>(p->S), *cf = static_cast<C *>(coeffs);
     for (LaunchGroup &lg : p->groups) {
         for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-            // candidates (waves, subsets): the covering matrix-core shapes and
-            // the Clenshaw form (0, 0)
+            // candidates (waves, subsets): the matrix-core shapes that cover
+            // the launch's beta rows, and the Clenshaw form (0, 0); a band in
+            // beta halves is timed on its first half
             std::vector<std::pair<int, int>> cand;
             for (const auto &sh : kDwtShapes) {
                 const int cover = sh[0] * sh[1] * 64;
-                if (cover >= lg.nmax && cover <= 2 * lg.nmax) cand.emplace_back(sh[0], sh[1]);
+                if (cover >= lg.rows && cover <= 2 * lg.rows) cand.emplace_back(sh[0], sh[1]);
             }
-            if (lg.nmax <= kMaxClenshawN) cand.emplace_back(0, 0);
+            if (lg.chunks == 1 && lg.nmax <= kMaxClenshawN) cand.emplace_back(0, 0);
             auto launch = [&](std::pair<int, int> c) {
                 if (c.first == 0)
                     return dir == 0 ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax,
@@ -559,9 +604,10 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
                                     : soft::launch_idwt_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax,
                                                                      cf, S, false, group_streams<C>(lg), 0);
                 const int nw = c.first, ns = c.second;
-                return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true, 0)
+                return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true,
+                                                           false, group_rows(lg, 0), group_xr(lg), 0)
                                 : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false,
-                                                           group_streams<C>(lg), 0);
+                                                           group_streams<C>(lg), group_rows(lg, 0), group_xr(lg), 0);
             };
             std::vector<float> best(cand.size(), 0.f);
             for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) e = launch(cand[i]);
@@ -637,6 +683,9 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
         b.B = B;
         b.N = 2 * B;
         b.G = B * (B + 1) / 2;
+        // Beta halves: always at 2B = 2048; on request from 2B = 128 (a half's
+        // quarter-range segments then hold whole FFT tiles).
+        b.chunks = b.N == soft::kBetaChunkN || ((flags & SOFT_BETA_HALVES) && b.N >= 128) ? 2 : 1;
         b.jbase = jtot;
         b.gbase = gtot;
         b.seed_base = p->seed_total;
@@ -661,7 +710,7 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
         fi.s_off = (long long)p->s_total;
         p->grid_total += (size_t)b.N * b.N * b.N;
         p->coeff_total += (size_t)b.Nc;
-        p->s_total += (size_t)b.G * kSlots * b.N;
+        p->s_total += (size_t)b.G * kSlots * (b.N / b.chunks);
         b.funcs.push_back(f);
     }
     // The tile-blocked FFT intermediate; a SOFT_INPLACE_OK plan has none
@@ -726,7 +775,7 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
                 const int m = gm[r.band][g], mp = g - m * (m + 1) / 2;
                 WorkItem w{};
                 w.goff = grow[r.band][g];
-                w.s_off = fi.s_off + (long long)g * kSlots * b.N;
+                w.s_off = fi.s_off + (long long)g * kSlots * (b.N / b.chunks);
                 w.coeff_off = fi.coeff_off;
                 w.B = b.B;
                 w.jbase = b.jbase;
@@ -739,11 +788,15 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
         }
         if (lists[gi].size() > (size_t)0x7fffffff) return SOFT_ERR_UNSUPPORTED;
         LaunchGroup lg;
-        const int len = keys[gi] ? keys[gi] : 64;
+        lg.bands = group_bands[gi];
+        for (int bi : group_bands[gi]) {
+            lg.nmax = std::max(lg.nmax, p->bands[bi].N);
+            lg.chunks = std::max(lg.chunks, p->bands[bi].chunks);  // a band in halves has its own launch
+        }
+        lg.rows = lg.nmax / lg.chunks;
+        const int len = keys[gi] ? lg.rows : 64;
         std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision);
         std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision);
-        lg.bands = group_bands[gi];
-        for (int bi : group_bands[gi]) lg.nmax = std::max(lg.nmax, p->bands[bi].N);
         lg.nitems = (int)lists[gi].size();
         p->groups.push_back(lg);
     }
@@ -797,7 +850,10 @@ int check_host(const soft_plan_s *p, const HostTables &ht) {
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         const LaunchGroup &lg = p->groups[gi];
         if ((size_t)lg.nitems != ht.lists[gi].size()) return SOFT_ERR_INVALID;
-        if (lg.nw_f * lg.nsub_f * 64 < lg.nmax || lg.nw_i * lg.nsub_i * 64 < lg.nmax) return SOFT_ERR_INVALID;
+        if ((lg.nw_f && lg.nw_f * lg.nsub_f * 64 < lg.rows) || (lg.nw_i && lg.nw_i * lg.nsub_i * 64 < lg.rows))
+            return SOFT_ERR_INVALID;
+        if (lg.chunks > 1 && (lg.bands.size() != 1 || p->bands[lg.bands[0]].chunks != lg.chunks))
+            return SOFT_ERR_INVALID;
         for (const WorkItem &w : ht.lists[gi]) {
             int f = -1;
             for (int q = 0; q < p->n && f < 0; ++q)
@@ -810,8 +866,8 @@ int check_host(const soft_plan_s *p, const HostTables &ht) {
             const int g = w.m * (w.m + 1) / 2 + w.mp;
             if (seen[f][g]++) return SOFT_ERR_INVALID;
             if (w.mask != group_mask(w.m, w.mp) || b.N > lg.nmax) return SOFT_ERR_INVALID;
-            if (w.s_off != p->funcs[f].s_off + (long long)g * kSlots * N ||
-                w.s_off + kSlots * N > (long long)p->s_total)
+            const long long NS = N / b.chunks;  // S rows per slot
+            if (w.s_off != p->funcs[f].s_off + (long long)g * kSlots * NS || w.s_off + kSlots * NS > (long long)p->s_total)
                 return SOFT_ERR_INVALID;
             if (w.seed_off != b.seed_base + (long long)g * N || w.seed_off + N > p->seed_total) return SOFT_ERR_INVALID;
             if (w.goff < b.row_base || w.goff + (b.B - w.m) > b.row_base + b.rows) return SOFT_ERR_INVALID;
@@ -893,6 +949,10 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             v.rscale = p->rscale;
             v.funcs = reinterpret_cast<const FuncInfo *>(p->tables + funcs_off);
             v.band_funcs = reinterpret_cast<const int *>(base + lay.bfuncs);
+            v.jn = b.N;  // all beta rows (half_view() narrows a band in halves)
+            v.jsplit = b.N;
+            v.joff0 = 0;
+            v.joff1 = 0;
         }
 
         hipError_t e = hipMemcpy(p->tables, host.data(), total, hipMemcpyHostToDevice);
@@ -1027,7 +1087,8 @@ int soft_plan_describe(soft_plan_t p, char *buf, size_t len) {
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         const LaunchGroup &lg = p->groups[gi];
         d += std::string(gi ? ", " : "") + "{\"max_2B\": " + std::to_string(lg.nmax) +
-             ", \"items\": " + std::to_string(lg.nitems) + ", \"forward\": [" + std::to_string(lg.nw_f) + ", " +
+             ", \"beta_halves\": " + std::to_string(lg.chunks) + ", \"items\": " + std::to_string(lg.nitems) +
+             ", \"forward\": [" + std::to_string(lg.nw_f) + ", " +
              std::to_string(lg.nsub_f) + "], \"inverse\": [" + std::to_string(lg.nw_i) + ", " +
              std::to_string(lg.nsub_i) + "], \"tuned\": " + (lg.tuned ? "true" : "false") + "}";
     }
@@ -1050,7 +1111,7 @@ int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves,
     }
     bool known = false;
     for (const auto &sh : kDwtShapes) known = known || (sh[0] == waves && sh[1] == subsets);
-    if (!known || waves * subsets * 64 < lg.nmax) return SOFT_ERR_INVALID;
+    if (!known || waves * subsets * 64 < lg.rows) return SOFT_ERR_INVALID;
     (direction == 0 ? lg.nw_f : lg.nw_i) = waves;
     (direction == 0 ? lg.nsub_f : lg.nsub_i) = subsets;
     return SOFT_OK;

@@ -34,6 +34,35 @@ constexpr int kPadRows = 32;
 // Kernel flag bits (the int flag argument of the FFT and inverse-DWT kernels).
 constexpr int kFlagScale = 1;   // apply w_B(j) (FFT) or V_B (inverse DWT)
 constexpr int kFlagStream = 2;  // write the main output with streaming stores
+constexpr int kFlagAccum = 4;   // forward DWT: add to the coefficients instead of writing them
+
+// Beta halves.  The band of 2B = 2048 keeps S for half of its beta samples
+// at a time (half the workspace: FP64 at B = 1024 then fits one GPU), in two
+// chunks closed under j -> 2B-1-j (the members at pi - beta are stored
+// j-reversed, so a chunk holds both ends of every pair): chunk 0 is
+// j < 2B/4 and j >= 3(2B)/4, chunk 1 the middle half.  A chunk's S rows are
+// indexed by the chunk-local k in [0, n); its beta sample is
+//   j = k + (k < split ? off0 : off1),
+// and back, k = j - (j < split + off0 ? off0 : off1).  n = 0 means the whole
+// range with k = j (every band below 2B = 2048).
+struct JMap {
+    int n = 0, split = 0, off0 = 0, off1 = 0;
+};
+constexpr int kBetaChunkN = 2048;  // bands of this 2B run in two beta halves
+inline JMap beta_chunk(int N, int c) {
+    JMap m;
+    m.n = N / 2;
+    if (c == 0) {
+        m.split = N / 4;
+        m.off0 = 0;
+        m.off1 = N / 2;
+    } else {
+        m.split = N / 2;
+        m.off0 = N / 4;
+        m.off1 = N / 4;
+    }
+    return m;
+}
 
 // Whether a launch writes its main output with streaming (non-temporal)
 // stores: bytes written by the launch, nmax its largest 2B, above the
@@ -219,6 +248,10 @@ struct PlanView {
     const double *rscale;  // plan-wide per-row s_l (d(l) = s_l e(l)), indexed by goff
     const FuncInfo *funcs; // plan-wide function table
     const int *band_funcs; // [nfunc] function indices of this band
+    // Beta rows of the alpha passes and of S (JMap with n = 0 as the whole
+    // range): jn rows, S row stride jn, beta sample j = k + (k < jsplit ?
+    // joff0 : joff1) of local row k.
+    int jn, jsplit, joff0, joff1;
 };
 
 // FFT stage (separation of variables, Sect. 2.4), one launch per band; t1 is
@@ -258,17 +291,20 @@ hipError_t launch_fill_seeds(const PlanView &p, double *seed, hipStream_t s);
 
 // DWT and iDWT over a device work list (one block per item), all items
 // sharing one launch shape: nw waves, nsub subsets of 64 beta samples per
-// wave (nw * nsub * 64 >= 2B of every item).  The forward writes the l-major
-// coefficients (symmetry signs, s_l and, when apply_v, V_B applied); the
-// inverse reads them and writes S, with streaming stores when stream.
+// wave (nw * nsub * 64 >= the beta rows of every item: its 2B, or jm.n).
+// The forward writes the l-major coefficients (symmetry signs, s_l and, when
+// apply_v, V_B applied), or adds to them with accum; the inverse reads them
+// and writes S, with streaming stores when stream.  jm selects a beta half
+// (JMap); xr runs the extended-range seeds of the 2B = 2048 band (the shapes
+// 8x2, 16x1, 4x4 and 8x4 only).
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
-                          hipStream_t s);
+                          bool accum, const JMap &jm, bool xr, hipStream_t s);
 template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                          bool stream, hipStream_t s);
+                          bool stream, const JMap &jm, bool xr, hipStream_t s);
 
 // The same inverse DWT by Clenshaw's backward summation (clenshaw.hip): one
 // block of nmax rounded up to 64 lanes per work item, nmax/2 x 128 bytes of

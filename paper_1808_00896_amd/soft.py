@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": SOFT_FP64, "fp32": SOFT_FP32, "fp32_split": SOFT_FP32_SPLI
 SOFT_PLAN_TUNE = 1
 SOFT_INPLACE_OK = 2
 SOFT_PLAN_GRAPH = 4
+SOFT_BETA_HALVES = 8
 SOFT_OK = 0
 SOFT_ERR_INVALID = -1
 SOFT_ERR_UNSUPPORTED = -2
@@ -319,9 +320,9 @@ def _precision(precision):
     return int(precision)
 
 
-def _flags(tune, inplace_ok, graph=False):
+def _flags(tune, inplace_ok, graph=False, beta_halves=False):
     return (SOFT_PLAN_TUNE if tune else 0) | (SOFT_INPLACE_OK if inplace_ok else 0) | \
-        (SOFT_PLAN_GRAPH if graph else 0)
+        (SOFT_PLAN_GRAPH if graph else 0) | (SOFT_BETA_HALVES if beta_halves else 0)
 
 
 class _PlanBase:
@@ -437,15 +438,18 @@ class Plan(_PlanBase):
     ``tune`` times the DWT launch shapes at plan time; ``inplace_ok`` drops
     the plan's FFT intermediate and stages it in the grid tensors instead
     (forward and adjoint_inverse then overwrite their input grid); ``graph``
-    replays each call kind as a captured HIP graph (SOFT_PLAN_GRAPH).
+    replays each call kind as a captured HIP graph (SOFT_PLAN_GRAPH);
+    ``beta_halves`` holds the per-order-pair samples for half of the beta
+    samples at a time (SOFT_BETA_HALVES, 2B >= 128; always at B = 1024).
     Calls are asynchronous on the current torch stream.
     """
 
-    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False):
+    def __init__(self, B, batch=1, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False,
+                 beta_halves=False):
         self._init_device(device, precision)
         self.inplace_ok = bool(inplace_ok)
         with torch.cuda.device(self.device):
-            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok, graph))
+            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok, graph, beta_halves))
         self.B, self.batch, self.N = B, batch, 2 * B
         self.nc = num_coeffs(B)
 
@@ -465,12 +469,13 @@ class UnevenPlan(_PlanBase):
     where each starts, and ``split_grids`` / ``split_coeffs`` return views.
     """
 
-    def __init__(self, Bs, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False):
+    def __init__(self, Bs, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False,
+                 beta_halves=False):
         self._init_device(device, precision)
         self.inplace_ok = bool(inplace_ok)
         self.Bs = [int(b) for b in Bs]
         with torch.cuda.device(self.device):
-            self.handle = soft_plan_uneven(self.Bs, self.precision, _flags(tune, inplace_ok, graph))
+            self.handle = soft_plan_uneven(self.Bs, self.precision, _flags(tune, inplace_ok, graph, beta_halves))
         self.grid_offsets, self.coeff_offsets = soft_plan_offsets(self.handle, len(self.Bs))
 
     def grid_shape(self):

@@ -1,15 +1,17 @@
-"""B = 1024 (2B = 2048 beta samples; a 2048^3 complex64 grid of 64 GiB and
-1.43e9 coefficients), through the C-ABI in the FP32 and FP32-split modes with
-SOFT_INPLACE_OK (the FP64 transform needs about 310 GB with every buffer of
-one plan, more than one GPU holds).  Checked at full size through properties
-and samples the oracle computes one by one: the round trip over all
-coefficients (forward of the inverse, the sampling theorem of Sect. 2.3) and
-beta slices of the inverse against the long-double oracle on the
-FP32-rounded input.  At this bandwidth some seeds of Sect. 2.2 that matter
-lie below double precision's range (the double-build oracle loses d values of
-order 0.04, see test_oracle_pins), so the long-double build is the reference,
-and slices 488 and 1560 are among those where the extended-range seeds
-decide the result.  Inputs are seeded synthetic coefficients.
+"""B = 1024 (2B = 2048 beta samples; a 2048^3 grid, 1.43e9 coefficients),
+through the C-ABI with SOFT_INPLACE_OK in all three precisions.  The band
+runs in beta halves (S for half of the beta samples at a time), which is what
+lets FP64 fit one GPU: 137 GB of grid, 23 GB of coefficients and 82 GB of
+plan.  Checked at full size through properties and samples the oracle
+computes one by one: the round trip over all coefficients (forward of the
+inverse, the sampling theorem of Sect. 2.3) and beta slices of the inverse
+against the long-double oracle on the same (rounded) input.  At this
+bandwidth some seeds of Sect. 2.2 that matter lie below double precision's
+range (the double-build oracle loses d values of order 0.04, see
+test_oracle_pins), so the long-double build is the reference; slices 488 and
+1560 are among those where the extended-range seeds decide the result, and
+the slices cover both beta halves (0, 488 and 1560 in the outer half, 1365 in
+the middle one).  Inputs are seeded synthetic coefficients.
 """
 import numpy as np
 import pytest
@@ -19,7 +21,10 @@ from paper_1808_00896_amd import inputs, soft
 
 pytestmark = pytest.mark.gpu
 
+B = 1024
 SLICES = (0, 488, 1365, 1560)
+TOL = {"fp64": 1e-9, "fp32": 2e-6, "fp32_split": 2e-6}
+SHAPES = {"fp64": ([4, 4], [4, 4]), "fp32": ([4, 4], [8, 2]), "fp32_split": ([4, 4], [16, 1])}
 
 
 @pytest.fixture(scope="module")
@@ -29,23 +34,38 @@ def dev():
     return torch.device("cuda", 0)
 
 
-@pytest.mark.parametrize("prec", ["fp32_split", "fp32"])
-def test_B1024(oracle, dev, prec):
-    B = 1024
-    print(f"B={B} {prec}: drawing {inputs.num_coeffs(B)} coefficients", flush=True)
-    c = inputs.coeffs_decay(B, 9).astype(np.complex64)
+@pytest.fixture(scope="module")
+def coeffs():
+    print(f"B={B}: drawing {inputs.num_coeffs(B)} coefficients", flush=True)
+    return inputs.coeffs_decay(B, 9)
+
+
+def _max_rel(a, b, chunk=1 << 27):
+    """max |a - b| / max |b| over two device vectors, in pieces (no full-size temporaries)."""
+    num = den = 0.0
+    for i in range(0, a.numel(), chunk):
+        num = max(num, float((a[i:i + chunk] - b[i:i + chunk]).abs().max()))
+        den = max(den, float(b[i:i + chunk].abs().max()))
+    return num / den
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_split", "fp32"])
+def test_B1024(oracle, dev, coeffs, prec):
+    c = coeffs if prec == "fp64" else coeffs.astype(np.complex64)
     with soft.Plan(B, precision=prec, inplace_ok=True) as p:
         d = p.describe()["dwt_launches"][0]
-        assert d["forward"] == [8, 4] and d["inverse"] == [8, 4]
+        assert d["beta_halves"] == 2
+        assert (d["forward"], d["inverse"]) == SHAPES[prec]
         cd = torch.from_numpy(c).to(dev)
-        print("inverse", flush=True)
+        print(f"{prec}: inverse", flush=True)
         g = p.inverse(cd)
         slices = {j: g[:, j, :].cpu().numpy().astype(np.complex128) for j in SLICES}
-        print("forward", flush=True)
+        print(f"{prec}: forward", flush=True)
         c2 = p.forward(g)  # overwrites g (SOFT_INPLACE_OK)
+        del g
         torch.cuda.synchronize()
-        err_rt = float((c2 - cd).abs().max() / cd.abs().max())
-        del g, c2, cd
+        err_rt = _max_rel(c2, cd)
+        del c2, cd
     torch.cuda.empty_cache()
     print(f"B={B} {prec} round trip {err_rt:.2e}", flush=True)
     c = c.astype(np.complex128)
@@ -54,5 +74,5 @@ def test_B1024(oracle, dev, prec):
         want = oracle.inverse_slice(B, c, j, "f80")
         errs[j] = float(np.abs(sl - want).max() / np.abs(want).max())
         print(f"B={B} {prec} inverse slice {j}: {errs[j]:.2e}", flush=True)
-    assert err_rt <= 2e-6
-    assert max(errs.values()) <= 2e-6, errs
+    assert err_rt <= TOL[prec]
+    assert max(errs.values()) <= TOL[prec], errs

@@ -1,0 +1,128 @@
+"""Plans in beta halves (SOFT_BETA_HALVES, and every band of 2B = 2048),
+through the C-ABI.  Such a band holds its per-order-pair beta samples for
+half of the beta samples at a time: the outer half (j < 2B/4 or j >= 3(2B)/4)
+and the middle half, each closed under j -> 2B-1-j, each with its own alpha
+FFT pass and DWT launch; the forward adds the second half's sums to the
+first's.  Checked here at 2B = 128 ... 512 (B = 1024 has its own test):
+  * every lane of an inverse does the same arithmetic as without halves, so
+    the inverse and the adjoint equal a plan without the flag bit for bit
+    when both run the same launch shape;
+  * the forward and the adjoint inverse differ only by the rounding of the
+    one added half: within 1e-14 (FP64) or 1e-6 (FP32 modes) of the plan
+    without the flag, and the oracle at B = 64 to the FP64 bar;
+  * with SOFT_INPLACE_OK, in uneven plans, with every covering launch shape
+    pinned, and under SOFT_PLAN_GRAPH.
+Inputs are seeded synthetic data from paper_1808_00896_amd.inputs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1808_00896_amd import inputs, soft
+
+pytestmark = pytest.mark.gpu
+
+CDT = {"fp64": torch.complex128, "fp32": torch.complex64, "fp32_split": torch.complex64}
+FWD_TOL = {"fp64": 1e-14, "fp32": 1e-6, "fp32_split": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dev, prec="fp64"):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(dev).to(CDT[prec])
+
+
+def rel(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def four(plan, c, g):
+    out = (plan.inverse(c), plan.adjoint(c), plan.forward(g.clone()), plan.adjoint_inverse(g.clone()))
+    torch.cuda.synchronize()
+    return out
+
+
+def same_inverse_shape(p0, p1):
+    """Pin the plan without halves' inverse shape on the plan with them (it
+    covers 2B, so also the half's B rows)."""
+    for i, (a, b) in enumerate(zip(p0.describe()["dwt_launches"], p1.describe()["dwt_launches"])):
+        p1.set_dwt_shape(i, 1, *a["inverse"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_split"])
+@pytest.mark.parametrize("B", [64, 128, 256])
+def test_halves_against_whole(dev, prec, B):
+    c = to_dev(inputs.coeffs_decay(B, 300 + B), dev, prec)
+    g = to_dev(inputs.grid_random(B, 310 + B), dev, prec)
+    with soft.Plan(B, precision=prec) as p0, soft.Plan(B, precision=prec, beta_halves=True) as p1:
+        assert [d["beta_halves"] for d in p1.describe()["dwt_launches"]] == [2]
+        same_inverse_shape(p0, p1)
+        want, got = four(p0, c, g), four(p1, c, g)
+    for name, a, b in zip(("inverse", "adjoint"), want[:2], got[:2]):
+        assert torch.equal(a, b), f"{name}: max rel diff {rel(b, a):.3e}"
+    for name, a, b in zip(("forward", "adjoint_inverse"), want[2:], got[2:]):
+        assert rel(b, a) <= FWD_TOL[prec], name
+
+
+def test_halves_against_oracle(oracle, dev):
+    B = 64
+    c = inputs.coeffs_decay(B, 320)
+    g = inputs.grid_random(B, 321)
+    with soft.Plan(B, beta_halves=True) as p:
+        gi = p.inverse(to_dev(c, dev)).cpu().numpy()
+        cf = p.forward(to_dev(g, dev)).cpu().numpy()
+    want_g, want_c = oracle.inverse(B, c), oracle.forward(B, g)
+    assert np.abs(gi.reshape(-1) - want_g.reshape(-1)).max() / np.abs(want_g).max() <= 1e-11
+    assert np.abs(cf - want_c).max() / np.abs(want_c).max() <= 1e-11
+
+
+def test_halves_only_from_2B_128(dev):
+    with soft.Plan(32, beta_halves=True) as p:
+        assert p.describe()["dwt_launches"][0]["beta_halves"] == 1
+    with soft.UnevenPlan([16, 32, 64, 128, 256], beta_halves=True) as p:
+        got = {d["max_2B"]: d["beta_halves"] for d in p.describe()["dwt_launches"]}
+    assert got == {64: 1, 128: 2, 256: 2, 512: 2}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_split"])
+def test_halves_inplace_uneven_graph(dev, prec):
+    Bs = [16, 128, 64, 128, 32]
+    cs = [inputs.coeffs_decay(B, 330 + i) for i, B in enumerate(Bs)]
+    with soft.UnevenPlan(Bs, precision=prec) as p0, \
+            soft.UnevenPlan(Bs, precision=prec, beta_halves=True, inplace_ok=True, graph=True) as p1:
+        same_inverse_shape(p0, p1)
+        c = to_dev(np.concatenate(cs), dev, prec)
+        g0 = p0.inverse(c)
+        c0 = p0.forward(g0.clone())
+        for _ in range(3):  # graph replays, with eager work between them
+            g1 = p1.inverse(c)
+            c1 = p1.forward(g1.clone())
+            torch.cuda.synchronize()
+            assert torch.equal(g0, g1)
+            assert rel(c1, c0) <= FWD_TOL[prec]
+            _ = (c0 * 2).sum().item()
+
+
+def test_halves_every_shape(dev):
+    """B = 256 in halves (128 beta rows per launch): every shape that covers
+    a half, pinned in both directions, agrees with the default."""
+    B = 256
+    c = to_dev(inputs.coeffs_decay(B, 340), dev)
+    with soft.Plan(B, beta_halves=True) as p:
+        ref_g = p.inverse(c).clone()
+        ref_c = p.forward(ref_g.clone()).clone()
+        for sh in soft.DWT_SHAPES:
+            if sh[0] * sh[1] * 64 < B:
+                continue
+            p.set_dwt_shape(0, 0, *sh)
+            p.set_dwt_shape(0, 1, *sh)
+            assert torch.equal(p.inverse(c), ref_g), sh
+            assert rel(p.forward(ref_g.clone()), ref_c) <= 1e-13, sh
+        with pytest.raises(soft.SoftError):
+            p.set_dwt_shape(0, 0, 1, 1)  # 64 lanes do not cover 256 rows
