@@ -90,6 +90,13 @@ typedef enum {
  *                   fastest.  Costs a few
  *                   DWT launches per candidate at plan creation; without it
  *                   a fixed shape per 2B, direction and precision is used.
+ *                   When the environment variable SOFT_TUNE_CACHE names a
+ *                   file, a plan whose key (device architecture, precision,
+ *                   beta halves or not, bandwidths with their function
+ *                   counts) is in it takes the stored shapes instead of
+ *                   timing, and a plan that times writes its entry there
+ *                   (a JSON object, one entry per line, rewritten whole
+ *                   through a temporary file and a rename).
  *   SOFT_INPLACE_OK the plan may use the grid buffers as scratch, and holds
  *                   no FFT intermediate of its own (that saves (2B)^3 complex
  *                   elements per function of the largest band: 16 GiB at
@@ -208,7 +215,8 @@ int soft_plan_sizes(soft_plan_t plan, size_t *grid_elems, size_t *coeff_elems,
 
 /*
  * soft_plan_describe -- a one-line JSON description of the plan (bands,
- * functions, workspace bytes, whether it was made with SOFT_INPLACE_OK, and
+ * functions, workspace bytes, whether it was made with SOFT_INPLACE_OK,
+ * whether its tuned shapes came from the SOFT_TUNE_CACHE file, and
  * per DWT launch its largest 2B, the number of beta halves it runs in (2 for
  * 2B = 2048, see soft_plan), work items, forward and inverse launch shapes
  * and whether they were tuned), written to

@@ -15,14 +15,20 @@
 // all bands with 2B <= 256 share a single DWT launch.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <new>
 #include <string>
 #include <tuple>
 #include <utility>
 #include <vector>
+
+#include <unistd.h>
 
 #include "soft_internal.h"
 
@@ -62,6 +68,7 @@ struct LaunchGroup {
 struct soft_plan_s {
     int precision = 0, n = 0, device = 0;
     unsigned flags = 0;
+    bool tune_cached = false;  // SOFT_PLAN_TUNE shapes came from the SOFT_TUNE_CACHE file
     std::vector<Band> bands;
     std::vector<FuncInfo> funcs;
     std::vector<LaunchGroup> groups;
@@ -569,6 +576,12 @@ constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2},
 constexpr int kMaxB = 1024;
 constexpr int kMaxClenshawN = 1024;
 
+bool known_shape(int waves, int subsets) {
+    for (const auto &sh : kDwtShapes)
+        if (sh[0] == waves && sh[1] == subsets) return true;
+    return false;
+}
+
 // Autotuner: for every DWT launch group and direction, time each shape that
 // covers the group's largest 2B (and is at most twice that), and also the
 // Clenshaw kernel of the direction, on the plan's own work list and
@@ -634,6 +647,130 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     return e;
+}
+
+// Autotune cache (SOFT_TUNE_CACHE names a file): the launch shapes a tuned
+// plan chose, keyed by the device architecture, the precision, whether the
+// plan runs beta halves, and its bandwidths with their function counts.  The
+// file is a JSON object with one entry per line,
+//   "gfx950|fp64|whole|128x1": [[4, 1, 4, 1]],
+// one [forward waves, subsets, inverse waves, subsets] per DWT launch in
+// plan order.  A plan whose key is present, with one valid shape per launch,
+// takes those shapes instead of timing; otherwise it tunes and writes its
+// entry (the file is rewritten whole: through a temporary file and a
+// rename, so readers never see a partial one).  Lines that do not parse are
+// dropped on that rewrite.  Plans made at the same time in several
+// processes may each tune and the last rename wins; every entry stays valid.
+std::mutex g_tune_cache_mu;
+
+std::string tune_cache_key(const soft_plan_s *p) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    static const char *const prec[] = {"fp64", "fp32", "fp32_split"};
+    std::string k = arch + "|" + prec[p->precision] + "|" + ((p->flags & SOFT_BETA_HALVES) ? "halves" : "whole") + "|";
+    for (size_t bi = 0; bi < p->bands.size(); ++bi)
+        k += (bi ? "," : "") + std::to_string(p->bands[bi].B) + "x" + std::to_string(p->bands[bi].funcs.size());
+    return k;
+}
+
+// Entries of a cache file: key -> flat list of shape numbers (4 per launch).
+std::map<std::string, std::vector<int>> read_tune_cache(const char *path) {
+    std::map<std::string, std::vector<int>> out;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"'), q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+        if (q1 == std::string::npos) continue;
+        const size_t colon = line.find(':', q1);
+        if (colon == std::string::npos) continue;
+        std::vector<int> nums;
+        bool ok = true;
+        for (size_t i = colon + 1; i < line.size() && ok;) {
+            const char ch = line[i];
+            if (ch >= '0' && ch <= '9') {
+                long v = 0;
+                while (i < line.size() && line[i] >= '0' && line[i] <= '9' && v < 100000) v = v * 10 + (line[i++] - '0');
+                nums.push_back((int)v);
+            } else {
+                ok = ch == '[' || ch == ']' || ch == ',' || ch == ' ';
+                ++i;
+            }
+        }
+        if (ok && !nums.empty() && nums.size() % 4 == 0) out[line.substr(q0 + 1, q1 - q0 - 1)] = nums;
+    }
+    return out;
+}
+
+bool write_tune_cache(const char *path, const std::map<std::string, std::vector<int>> &entries) {
+    static int serial = 0;
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid()) + "." + std::to_string(++serial);
+    {
+        std::ofstream f(tmp);
+        if (!f) return false;
+        f << "{\n";
+        size_t i = 0;
+        for (const auto &kv : entries) {
+            f << "\"" << kv.first << "\": [";
+            for (size_t s = 0; s < kv.second.size(); s += 4)
+                f << (s ? ", " : "") << "[" << kv.second[s] << ", " << kv.second[s + 1] << ", " << kv.second[s + 2]
+                  << ", " << kv.second[s + 3] << "]";
+            f << "]" << (++i < entries.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+        if (!f) return false;
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return false;
+    }
+    return true;
+}
+
+// A launch shape from the cache is usable for a launch group when it is
+// built and covers the group (or is a Clenshaw form the group allows).
+bool cached_shape_ok(const LaunchGroup &lg, int waves, int subsets) {
+    if (waves == 0 && subsets == 0) return lg.chunks == 1 && lg.nmax <= 1024;
+    return known_shape(waves, subsets) && waves * subsets * 64 >= lg.rows;
+}
+
+// Applies the cached shapes of p, if its key is in the file; true on a hit.
+bool tune_from_cache(soft_plan_s *p, const char *path) {
+    std::lock_guard<std::mutex> lock(g_tune_cache_mu);
+    const auto entries = read_tune_cache(path);
+    const auto it = entries.find(tune_cache_key(p));
+    if (it == entries.end() || it->second.size() != 4 * p->groups.size()) return false;
+    const std::vector<int> &v = it->second;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi)
+        if (!cached_shape_ok(p->groups[gi], v[4 * gi], v[4 * gi + 1]) ||
+            !cached_shape_ok(p->groups[gi], v[4 * gi + 2], v[4 * gi + 3]))
+            return false;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        LaunchGroup &lg = p->groups[gi];
+        lg.nw_f = v[4 * gi];
+        lg.nsub_f = v[4 * gi + 1];
+        lg.nw_i = v[4 * gi + 2];
+        lg.nsub_i = v[4 * gi + 3];
+        lg.tuned = true;
+    }
+    return true;
+}
+
+void tune_to_cache(const soft_plan_s *p, const char *path) {
+    std::lock_guard<std::mutex> lock(g_tune_cache_mu);
+    auto entries = read_tune_cache(path);
+    std::vector<int> &v = entries[tune_cache_key(p)];
+    v.clear();
+    for (const LaunchGroup &lg : p->groups) {
+        v.push_back(lg.nw_f);
+        v.push_back(lg.nsub_f);
+        v.push_back(lg.nw_i);
+        v.push_back(lg.nsub_i);
+    }
+    (void)write_tune_cache(path, entries);  // a cache that cannot be written only costs the next plan a tuning
 }
 
 int tune_dwt(soft_plan_s *p) {
@@ -965,10 +1102,16 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         }
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e == hipSuccess && (flags & SOFT_PLAN_TUNE)) {
-            const int rc = tune_dwt(p);
-            if (rc != SOFT_OK) {
-                free_plan(p);
-                return rc;
+            const char *cache = std::getenv("SOFT_TUNE_CACHE");
+            if (cache && *cache && tune_from_cache(p, cache)) {
+                p->tune_cached = true;
+            } else {
+                const int rc = tune_dwt(p);
+                if (rc != SOFT_OK) {
+                    free_plan(p);
+                    return rc;
+                }
+                if (cache && *cache) tune_to_cache(p, cache);
             }
         }
         if (e != hipSuccess) {
@@ -1079,7 +1222,8 @@ int soft_plan_describe(soft_plan_t p, char *buf, size_t len) {
     if (!p || !buf || len == 0) return SOFT_ERR_INVALID;
     std::string d = "{\"precision\": " + std::to_string(p->precision) + ", \"functions\": " + std::to_string(p->n) +
                     ", \"workspace_bytes\": " + std::to_string(p->ws_bytes) +
-                    ", \"inplace_ok\": " + ((p->flags & SOFT_INPLACE_OK) ? "true" : "false") + ", \"bands\": [";
+                    ", \"inplace_ok\": " + ((p->flags & SOFT_INPLACE_OK) ? "true" : "false") +
+                    ", \"tuned_from_cache\": " + (p->tune_cached ? "true" : "false") + ", \"bands\": [";
     for (size_t bi = 0; bi < p->bands.size(); ++bi)
         d += std::string(bi ? ", " : "") + "{\"B\": " + std::to_string(p->bands[bi].B) +
              ", \"functions\": " + std::to_string(p->bands[bi].funcs.size()) + "}";
@@ -1109,9 +1253,7 @@ int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves,
         (direction == 0 ? lg.nsub_f : lg.nsub_i) = 0;
         return SOFT_OK;
     }
-    bool known = false;
-    for (const auto &sh : kDwtShapes) known = known || (sh[0] == waves && sh[1] == subsets);
-    if (!known || waves * subsets * 64 < lg.rows) return SOFT_ERR_INVALID;
+    if (!known_shape(waves, subsets) || waves * subsets * 64 < lg.rows) return SOFT_ERR_INVALID;
     (direction == 0 ? lg.nw_f : lg.nw_i) = waves;
     (direction == 0 ? lg.nsub_f : lg.nsub_i) = subsets;
     return SOFT_OK;
