@@ -232,8 +232,21 @@ struct Tile {
     static constexpr int T = T0 < N ? T0 : N;
     static constexpr int TL = TL0 < N ? TL0 : N;
     static constexpr int NT = T * Shape<N>::P;
-    static constexpr int LDS = Shape<N>::P > 1 ? T * Shape<N>::RS : 1;
+    // Row halves: a tile whose exchange buffer would exceed 96 KB exchanges
+    // through LDS one half of its rows at a time (RH = 2), so that two
+    // blocks can share a CU without shortening the runs on the transposed
+    // side.  That needs a kernel within 128 VGPRs at 512 threads: measured
+    // (B = 512 / 1024 FP64, results bit-identical) it pays for the forward
+    // gamma pass (7.8 -> 7.5 ms; in place 7.7 -> 6.9 ms; B = 1024 52.9 ->
+    // 49.0 ms) and the in-grid inverse alpha pass at 2B = 1024 (8.5 -> 8.1 ms),
+    // while the passes above 128 VGPRs only gain barriers (forward alpha 7.6
+    // -> 8.7 ms; forcing 128 VGPRs made them spill and slower still).
+    static constexpr bool BIG = (size_t)T * Shape<N>::RS * sizeof(C) > 96 * 1024;
+    static constexpr bool RH_PAYS = KIND == GAMMA_FWD || (KIND == ALPHA_INV && INGRID && N == 1024);
+    static constexpr int RH = Shape<N>::P > 1 && BIG && T % 2 == 0 && NT <= 512 && RH_PAYS ? 2 : 1;
+    static constexpr int LDS = Shape<N>::P > 1 ? (T / RH) * Shape<N>::RS : 1;
 };
+
 
 // Radix of stage s: R0 first (when the decomposition needs it), then 16s.
 template <int N, int S>
@@ -298,6 +311,28 @@ __device__ __forceinline__ void get_stage(C (&v)[Shape<N>::E], const C *lds, int
         const int b = p + k * P;
 #pragma unroll
         for (int r = 0; r < R; ++r) v[k * R + r] = lds[lds_pos(t, b + r * (N / R), RS)];
+    }
+}
+
+// One LDS exchange between stage SP (outputs in v, row tp, position pp_)
+// and stage SG (inputs into v, row tg, position pg).  With row halves the
+// buffer holds T/RH rows and the exchange runs in RH rounds; every thread's
+// put row and get row lie in the same half (myh), so a thread puts before it
+// gets and never overwrites values it has yet to store.
+template <int N, int SP, int SG, typename C, int RH, int TH>
+__device__ __forceinline__ void exchange(C (&v)[Shape<N>::E], C *lds, int tp, int pp_, int tg, int pg, int myh) {
+    if constexpr (RH == 1) {
+        put_stage<N, SP, C>(v, lds, tp, pp_);
+        __syncthreads();
+        get_stage<N, SG, C>(v, lds, tg, pg);
+    } else {
+#pragma unroll
+        for (int h = 0; h < RH; ++h) {
+            if (myh == h) put_stage<N, SP, C>(v, lds, tp - h * TH, pp_);
+            __syncthreads();
+            if (myh == h) get_stage<N, SG, C>(v, lds, tg - h * TH, pg);
+            if (h + 1 < RH) __syncthreads();
+        }
     }
 }
 
@@ -419,9 +454,26 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     const int mp_line = line < B ? line : line - N;  // m' of an alpha-pass block
 
     C v[E];
+    // Thread -> (row, position).  On a transposed side the row index is
+    // fastest (row tid % T), so T neighbouring lanes move one run of T
+    // elements.  On a row side, position fastest; with row halves (RH = 2)
+    // the rows are dealt so that a thread's row on every side lies in the
+    // same half, (tid % T) / TH: lanes of one half take consecutive
+    // positions of one row (runs of up to 32 elements per row and wave).
+    constexpr int RH = Tile<N, C, KIND, INGRID>::RH, TH = T / RH;
+    const int myh = RH == 1 ? 0 : (tid % T) / TH;
+    int row_t, row_p;
+    if constexpr (RH == 1) {
+        row_t = tid / P;
+        row_p = tid % P;
+    } else {
+        const int rank = (tid / T) * TH + tid % TH;
+        row_t = myh * TH + rank / P;
+        row_p = rank % P;
+    }
     // ---- stage 0 inputs from HBM: element b + r*N/R ----
-    const int t_in = transposed_in<KIND>() ? tid % T : tid / P;
-    const int p_in = transposed_in<KIND>() ? tid / T : tid % P;
+    const int t_in = transposed_in<KIND>() ? tid % T : row_t;
+    const int p_in = transposed_in<KIND>() ? tid / T : row_p;
     {
         constexpr int R = radix_of<N, 0>(), BPT = N / R / P;
         const int row = ALPHA ? jrow(p, tile * T + t_in) : tile * T + t_in;  // i (gamma) or j (alpha)
@@ -452,22 +504,20 @@ __device__ __forceinline__ void fft_pass(const PlanView &p, const C *in, C *out,
     }
     run_stage<N, 0, SIGN, C>(v, p_in, tw);
 
-    // ---- exchanges through LDS (lane order: row index fastest) ----
+    // ---- exchanges through LDS ----
     int t_out = t_in, p_out = p_in;
     if constexpr (NSTG > 1) {
-        const int t = tid / P, pp = tid % P;
-        put_stage<N, 0, C>(v, lds, t_in, p_in);
-        __syncthreads();
-        if constexpr (NSTG > 2) {
-            get_stage<N, 1, C>(v, lds, t, pp);
-            run_stage<N, 1, SIGN, C>(v, pp, tw);
-            __syncthreads();
-            put_stage<N, 1, C>(v, lds, t, pp);
-            __syncthreads();
-        }
+        const int t = row_t, pp = row_p;
         t_out = transposed_out<KIND>() ? tid % T : t;
         p_out = transposed_out<KIND>() ? tid / T : pp;
-        get_stage<N, LAST, C>(v, lds, t_out, p_out);
+        if constexpr (NSTG > 2) {
+            exchange<N, 0, 1, C, RH, TH>(v, lds, t_in, p_in, t, pp, myh);
+            run_stage<N, 1, SIGN, C>(v, pp, tw);
+            __syncthreads();
+            exchange<N, 1, LAST, C, RH, TH>(v, lds, t, pp, t_out, p_out, myh);
+        } else {
+            exchange<N, 0, LAST, C, RH, TH>(v, lds, t_in, p_in, t_out, p_out, myh);
+        }
         run_stage<N, LAST, SIGN, C>(v, p_out, tw);
     }
 

@@ -288,13 +288,17 @@ def test_tuned_plans_match_oracle(oracle, dev, prec):
         assert relerr(c2[p.coeff_offsets[f]:p.coeff_offsets[f + 1]], cs[f]) <= TOL[prec], (f, B)
 
 
-def test_fp32_split_B512_sampled(oracle, dev):
-    """B = 512 in FP32-split: sampled beta-slices of the inverse against the
-    FP64 oracle on the same FP32-rounded coefficients, and the round trip."""
+@pytest.mark.parametrize("prec", ["fp32_split", "fp32"])
+def test_fp32_B512_sampled(oracle, dev, prec):
+    """B = 512 in the FP32 modes (their own 2B = 1024 launch shapes and the
+    complex64 half-height forward alpha pass): sampled beta-slices of the
+    inverse against the FP64 oracle on the same FP32-rounded coefficients,
+    sampled order pairs of the forward of that grid against the oracle's
+    forward of the same (FP32) grid, and the round trip."""
     B = 512
-    c = rounded(inputs.coeffs_decay(B, 3), "fp32_split")
-    with soft.Plan(B, precision="fp32_split") as p:
-        gd = p.inverse(to_dev(c, dev, "fp32_split"))
+    c = rounded(inputs.coeffs_decay(B, 3), prec)
+    with soft.Plan(B, precision=prec) as p:
+        gd = p.inverse(to_dev(c, dev, prec))
         cd = to_host(p.forward(gd))
         g = to_host(gd)
         del gd
@@ -302,3 +306,11 @@ def test_fp32_split_B512_sampled(oracle, dev):
     assert relerr(cd, c) <= 1e-6
     for j in (0, 511, 700):
         assert relerr(g[:, j, :], oracle.inverse_slice(B, c, j)) <= 1e-6, j
+    pairs = [(0, 0), (3, -2), (100, 50), (-200, 7), (511, -511)]
+    want = oracle.forward_pairs(B, g, pairs)
+    scale = np.abs(c).max()
+    for (m, mp), w in zip(pairs, want):
+        l0 = max(abs(m), abs(mp))
+        ls = np.arange(l0, B)
+        got = cd[ls * (4 * ls * ls - 1) // 3 + (m + ls) * (2 * ls + 1) + (mp + ls)]
+        assert np.abs(got - w[l0:]).max() / scale <= 1e-6, (m, mp)
