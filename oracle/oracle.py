@@ -314,3 +314,126 @@ def refine_quadratic(B, grid, idx):
     dk = step(g[i, j, (k - 1) % N], g[i, j, (k + 1) % N])
     dj = step(g[i, j - 1, k], g[i, j + 1, k]) if 0 < j < N - 1 else 0.0
     return ((k + dk) * np.pi / B, (2 * (j + dj) + 1) * np.pi / (4 * B), (i + di) * np.pi / B)
+
+
+def corr_eval(B, fo, alpha, beta, gamma, prec="f64"):
+    """The SO(3) function with coefficients fo at an arbitrary point:
+        C(alpha, beta, gamma) = sum_{l,m,m'} fo(l,m,m') e^{-i m alpha}
+                                d(l,m,m';beta) e^{-i m' gamma},
+    the sum of eq. "fourier_representation" that the inverse transform
+    evaluates at the grid points (alpha_i, beta_j, gamma_k); d by the seeds
+    and recurrence of Sect. 2.2 at this beta.  A beta outside [0, pi] names
+    the same rotation as (alpha + pi, beta', gamma - pi) with beta' = -beta
+    or 2 pi - beta (Rz(pi) Ry(b) Rz(-pi) = Ry(-b)), so it is evaluated there."""
+    fo = _c128(fo).reshape(-1)
+    beta = float(np.mod(beta, 2 * np.pi))
+    if beta > np.pi:
+        alpha, beta, gamma = alpha + np.pi, 2 * np.pi - beta, gamma - np.pi
+    tot = 0j
+    for m in range(1 - B, B):
+        for mp in range(1 - B, B):
+            l0 = max(abs(m), abs(mp))
+            ls = np.arange(l0, B)
+            d = wigner_d(B, m, mp, beta, prec)[l0:]
+            tot += np.exp(-1j * (m * alpha + mp * gamma)) * np.dot(d, fo[coeff_index(ls, m, ls * 0 + mp)])
+    return tot
+
+
+def _rz(a):
+    c, s_ = np.cos(a), np.sin(a)
+    return np.array([[c, -s_, 0.0], [s_, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def _ry(b):
+    c, s_ = np.cos(b), np.sin(b)
+    return np.array([[c, 0.0, s_], [0.0, 1.0, 0.0], [-s_, 0.0, c]])
+
+
+def _expso3(w):
+    """Rotation matrix exp([w]x) (Rodrigues)."""
+    t = np.sqrt(w @ w)
+    K = np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+    if t < 1e-300:
+        return np.eye(3)
+    return np.eye(3) + np.sin(t) / t * K + (1 - np.cos(t)) / (t * t) * (K @ K)
+
+
+def zyz_of(Q):
+    """Angles (a, b, c), b in [0, pi], with Q = Rz(a) Ry(b) Rz(c); on the
+    axis (sin b = 0) c = 0 and a carries the whole turn."""
+    sb = np.hypot(Q[0, 2], Q[1, 2])
+    b = np.arctan2(sb, Q[2, 2])
+    if sb > 0.0:
+        return np.arctan2(Q[1, 2], Q[0, 2]), b, np.arctan2(Q[2, 1], -Q[2, 0])
+    if Q[2, 2] > 0:
+        return np.arctan2(Q[1, 0], Q[0, 0]), b, 0.0
+    return np.arctan2(-Q[1, 0], -Q[0, 0]), b, 0.0
+
+
+def corr_at(B, fo, Q, prec="f64"):
+    """C at the rotation Q: the rotation read off grid index (i, j, k) is
+    Rz(gamma_k) Ry(beta_j) Rz(alpha_i) (rotation_of_index), so C is
+    evaluated at (alpha, beta, gamma) = (c, b, a) of Q's angles (a, b, c)."""
+    a, b, c = zyz_of(Q)
+    return corr_eval(B, fo, c, b, a, prec)
+
+
+def polish_rotation(B, fo, start, iters=8, prec="f64"):
+    """Off-grid refinement of a correlation maximum by Newton steps on
+    F(w) = Re C(Q0 exp([w]x)), local rotation-vector coordinates w around
+    the current rotation Q0 (no pole of Euler angles on the way).  Q0 starts
+    at Rz(a) Ry(b) Rz(c) for start = (a, b, c).  Each step samples F at w = 0,
+    +-h e_i and h (e_i + e_j), i < j (ten points: the quadratic model through
+    them is exact for quadratics), takes g_i = (F(h e_i) - F(-h e_i)) / 2h,
+    H_ii = (F(h e_i) - 2 F(0) + F(-h e_i)) / h^2 and H_ij from F(h e_i + h e_j);
+    steps by -H^-1 g when -H is positive definite (its Cholesky factor exists)
+    and otherwise by -g_i / H_ii per axis (or h toward larger F where
+    H_ii >= 0), clamps each component to [-h, h], sets Q0 = Q0 exp([step]x)
+    and h = min(h, max(1e-5, 2 max|step|)); h starts at pi/(4B).  Returns the
+    angles (a, b, c) of the final rotation (a, c in [0, 2 pi), b in [0, pi])
+    and Re C there."""
+    Q0 = _rz(start[0]) @ _ry(start[1]) @ _rz(start[2])
+    h = np.pi / (4 * B)
+    E = np.eye(3)
+    val = 0.0
+    for it in range(iters + 1):
+        F0 = corr_at(B, fo, Q0, prec).real
+        if it == iters:
+            val = F0
+            break
+        Fp = [corr_at(B, fo, Q0 @ _expso3(h * E[i]), prec).real for i in range(3)]
+        Fm = [corr_at(B, fo, Q0 @ _expso3(-h * E[i]), prec).real for i in range(3)]
+        g = np.array([(Fp[i] - Fm[i]) / (2 * h) for i in range(3)])
+        H = np.diag([(Fp[i] - 2 * F0 + Fm[i]) / (h * h) for i in range(3)])
+        for i, j in ((0, 1), (0, 2), (1, 2)):
+            Fij = corr_at(B, fo, Q0 @ _expso3(h * (E[i] + E[j])), prec).real
+            H[i, j] = H[j, i] = (Fij - F0 - h * (g[i] + g[j]) - 0.5 * h * h * (H[i, i] + H[j, j])) / (h * h)
+        A = -H
+        ok = A[0, 0] > 0
+        if ok:
+            l00 = np.sqrt(A[0, 0])
+            l10, l20 = A[1, 0] / l00, A[2, 0] / l00
+            r11 = A[1, 1] - l10 * l10
+            ok = r11 > 0
+        if ok:
+            l11 = np.sqrt(r11)
+            l21 = (A[2, 1] - l20 * l10) / l11
+            r22 = A[2, 2] - l20 * l20 - l21 * l21
+            ok = r22 > 0
+        if ok:
+            l22 = np.sqrt(r22)
+            y0 = g[0] / l00
+            y1 = (g[1] - l10 * y0) / l11
+            y2 = (g[2] - l20 * y0 - l21 * y1) / l22
+            d2 = y2 / l22
+            d1 = (y1 - l21 * d2) / l11
+            d0 = (y0 - l10 * d1 - l20 * d2) / l00
+            step = np.array([d0, d1, d2])
+        else:
+            step = np.array([-g[i] / H[i, i] if H[i, i] < 0 else (h if g[i] >= 0 else -h) for i in range(3)])
+        step = np.clip(step, -h, h)
+        Q0 = Q0 @ _expso3(step)
+        h = min(h, max(1e-5, 2 * np.abs(step).max()))
+    a, b, c = zyz_of(Q0)
+    two_pi = 2 * np.pi
+    return (float(np.mod(a, two_pi)), float(b), float(np.mod(c, two_pi))), float(val)

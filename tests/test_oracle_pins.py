@@ -538,3 +538,55 @@ def test_quadratic_refinement_moves_toward_off_grid_rotation(oracle):
     got = oracle.refine_quadratic(B, par, oracle.argmax_real(par))
     want = (3.1 * np.pi / B, (2 * 7.8 + 1) * np.pi / (4 * B), 5.3 * np.pi / B)
     assert np.allclose(got, want, atol=1e-12)
+
+
+def test_corr_eval_is_the_inverse_at_grid_points(oracle):
+    """corr_eval at (alpha_i, beta_j, gamma_k) equals the inverse transform's
+    grid value there, and one coefficient f°(1, 1, 0) gives the closed form
+    e^{-i alpha} sin(beta)/sqrt(2) (d(1,1,0) of Sect. 2.2) anywhere."""
+    B = 4
+    N = 2 * B
+    fo = inputs.coeffs_decay(B, 60)
+    grid = oracle.inverse(B, fo).reshape(N, N, N)
+    for (i, j, k) in ((0, 0, 0), (3, 5, 1), (7, 2, 6)):
+        got = oracle.corr_eval(B, fo, i * np.pi / B, (2 * j + 1) * np.pi / (4 * B), k * np.pi / B)
+        assert abs(got - grid[i, j, k]) <= 1e-13 * np.abs(grid).max()
+    one = np.zeros(oracle.num_coeffs(B), complex)
+    one[oracle.coeff_index(1, 1, 0)] = 1.0
+    for a, b, c in ((0.3, 0.7, 2.0), (5.0, 2.9, 0.1)):
+        want = np.exp(-1j * a) * np.sin(b) / np.sqrt(2)
+        assert abs(oracle.corr_eval(B, one, a, b, c) - want) <= 1e-15
+
+
+def test_polish_recovers_off_grid_rotation(oracle):
+    """For g = f rotated by an off-grid R0, Newton steps on the correlation
+    from the grid maximum's (parabola-refined) read-out land on R0: the
+    continuous maximum of Re <f o Q^-1, g> is at Q = R0 (Cauchy-Schwarz), and
+    band-limited sampling makes the coefficients exact.  Two of the rotations
+    lie near the poles of the Euler angles (beta = 0.05 and 3.1), where the
+    local rotation-vector steps still converge."""
+    from scipy.spatial.transform import Rotation
+    B = 6
+    rng = np.random.default_rng(12)
+    a = (rng.standard_normal(B * B) + 1j * rng.standard_normal(B * B)) * 0.7 ** np.repeat(
+        np.arange(B), [2 * l + 1 for l in range(B)])
+    for angles in ((1.1, 1.0, 2.3), (4.0, 2.2, 0.4), (0.3, 0.05, 5.0), (2.0, 3.1, 1.0)):
+        R0 = Rotation.from_euler("ZYZ", angles)
+        b = oracle.sh_forward(B, _rotated_samples(B, a, R0))
+        fo = oracle.correlation_coeffs(B, a, b)
+        grid = oracle.inverse(B, fo)
+        idx = oracle.argmax_real(grid)
+        start = oracle.refine_quadratic(B, grid, idx)
+        got, val = oracle.polish_rotation(B, fo, start, iters=8)
+        err = (Rotation.from_euler("ZYZ", got).inv() * R0).magnitude()
+        assert err <= 1e-8, (angles, err)
+        assert val >= grid.real.max()
+
+
+def test_zyz_read_out_round_trips(oracle):
+    """zyz_of inverts Rz(a) Ry(b) Rz(c), also on the axis (b = 0 or pi)."""
+    for ang in ((0.3, 0.7, 2.0), (1.0, 0.0, 2.0), (1.0, np.pi, 2.0), (5.9, 1e-9, 0.2), (2.0, 3.0, 6.0)):
+        Q = oracle._rz(ang[0]) @ oracle._ry(ang[1]) @ oracle._rz(ang[2])
+        a, b, c = oracle.zyz_of(Q)
+        assert 0.0 <= b <= np.pi
+        assert np.abs(oracle._rz(a) @ oracle._ry(b) @ oracle._rz(c) - Q).max() <= 1e-15
