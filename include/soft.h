@@ -496,6 +496,36 @@ int soft_sh_forward(int B, int n, int precision, const void *f, void *a, hipStre
 int soft_match_refine(soft_match_t match, const void *grid, const long long *index, double *angles,
                       hipStream_t stream);
 
+/*
+ * soft_match_polish -- the maximum of each pair's correlation function off
+ * the grid: Newton steps on Re C(Q), C the SO(3) function with the pair's
+ * correlation coefficients evaluated at a rotation Q by the sum of eq.
+ * "fourier_representation" (at the rotation that grid index (i, j, k) names,
+ * soft_match_refine's read-out, C equals the grid value).  The steps run in
+ * local rotation-vector coordinates w around the current rotation Q0 (no
+ * Euler-angle pole on the way): F(w) = Re C(Q0 exp([w]x)) at the ten points
+ * w = 0, +-h e_i, h (e_i + e_j) gives the gradient and Hessian of a quadratic
+ * model; the step is -H^-1 g when -H is positive definite, else a per-axis
+ * step, each component clamped to [-h, h]; then Q0 = Q0 exp([step]x) and h =
+ * min(h, max(1e-5, 2 max|step|)), from h = pi/(4B).  For band-limited
+ * functions the correlation's maximum is the rotation itself, which the
+ * steps reach to about 1e-9 from soft_match_refine's start.
+ *   match   a match plan (B <= 512): its bandwidth, n and precision.
+ *   coeffs  device, n correlation coefficient vectors (soft_match_coeffs
+ *           layout and complex type; read only).
+ *   start   device, n x 3 double rotation angles (a, b, c) of Rz(a) Ry(b) Rz(c)
+ *           (soft_match_refine's output; read only).
+ *   iters   Newton steps, 0 .. 64 (each costs ten evaluations of C, each a
+ *           pass over the coefficients; about 6 converge).
+ *   angles  device, n x 3 double (written): the polished (a, b, c), b in
+ *           [0, pi], a and c in [0, 2 pi).
+ *   value   device, n double (written): Re C at the polished rotation.
+ * One block per pair; allocates nothing.  Returns SOFT_OK, SOFT_ERR_INVALID
+ * or SOFT_ERR_HIP.
+ */
+int soft_match_polish(soft_match_t match, const void *coeffs, const double *start, int iters, double *angles,
+                      double *value, hipStream_t stream);
+
 /* soft_match_destroy -- release the head and its soft_plan, after waiting for the
  * work of its last call as soft_plan_destroy does (NULL ignored). */
 int soft_match_destroy(soft_match_t match);

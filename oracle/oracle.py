@@ -355,7 +355,7 @@ def _expso3(w):
     K = np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
     if t < 1e-300:
         return np.eye(3)
-    return np.eye(3) + np.sin(t) / t * K + (1 - np.cos(t)) / (t * t) * (K @ K)
+    return np.eye(3) + np.sin(t) / t * K + 2.0 * np.sin(0.5 * t) ** 2 / (t * t) * (K @ K)
 
 
 def zyz_of(Q):

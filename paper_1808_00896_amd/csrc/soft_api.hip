@@ -117,6 +117,7 @@ struct soft_match_s {
     soft_plan_t plan = nullptr;  // owned
     void *coeffs = nullptr;      // n coefficient vectors
     void *part = nullptr;        // argmax partial results
+    double *polish = nullptr;    // soft_match_polish: per-pair state and chunk partials
 };
 
 namespace {
@@ -150,6 +151,7 @@ void free_match(soft_match_s *m) {
     if (!m) return;
     if (m->coeffs) (void)hipFree(m->coeffs);
     if (m->part) (void)hipFree(m->part);
+    if (m->polish) (void)hipFree(m->polish);
     free_plan(m->plan);
     delete m;
 }
@@ -1351,7 +1353,8 @@ int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *o
                                        sizeof(soft::ArgBest) * (size_t)n *
                                            (size_t)soft::gamma_argmax_blocks(2 * B, (int)m->plan->csize));
     if (hipMalloc(&m->coeffs, m->plan->coeff_total * m->plan->csize) != hipSuccess ||
-        hipMalloc(&m->part, part_bytes) != hipSuccess) {
+        hipMalloc(&m->part, part_bytes) != hipSuccess ||
+        hipMalloc(&m->polish, soft::polish_workspace_bytes(B * (B + 1) / 2, n)) != hipSuccess) {
         (void)hipGetLastError();
         free_match(m);
         return SOFT_ERR_OOM;
@@ -1458,6 +1461,22 @@ int soft_sh_forward(int B, int n, int precision, const void *f, void *a, hipStre
         precision == SOFT_FP64
             ? soft::launch_sh_forward<double2>(B, n, static_cast<const double2 *>(f), static_cast<double2 *>(a), s)
             : soft::launch_sh_forward<float2>(B, n, static_cast<const float2 *>(f), static_cast<float2 *>(a), s);
+    return hip_status(e);
+}
+
+int soft_match_polish(soft_match_t m, const void *coeffs, const double *start, int iters, double *angles,
+                      double *value, hipStream_t s) {
+    if (!m || !coeffs || !start || !angles || !value || iters < 0 || iters > 64) return SOFT_ERR_INVALID;
+    const int rc = check_call(m->plan, coeffs, angles);
+    if (rc != SOFT_OK) return rc;
+    const soft_plan_s *p = m->plan;
+    const PlanView &v = p->bands[0].view;
+    const hipError_t e =
+        p->precision == SOFT_FP64
+            ? soft::launch_corr_polish<double2>(v, p->rec, p->rscale, m->n, static_cast<const double2 *>(coeffs),
+                                                start, iters, angles, value, m->polish, s)
+            : soft::launch_corr_polish<float2>(v, p->rec, p->rscale, m->n, static_cast<const float2 *>(coeffs),
+                                               start, iters, angles, value, m->polish, s);
     return hip_status(e);
 }
 

@@ -344,6 +344,17 @@ template <typename C>
 hipError_t launch_sh_forward(int B, int n, const C *f, C *a, hipStream_t s);
 template <typename C>
 hipError_t launch_match_refine(int B, int n, const C *grid, const long long *index, double *out, hipStream_t s);
+// Off-grid Newton polishing of n correlation maxima (sphere.hip): coeffs are
+// the n correlation coefficient vectors of the one-band view v (B <= 512),
+// rec / rscale the plan's recurrence table, start and angles n x 3 rotation
+// angles (a, b, c) of Rz(a) Ry(b) Rz(c), value n values Re C at the result;
+// ws a device workspace of polish_workspace_bytes(v.G, n) (state and chunk
+// partials).
+size_t polish_workspace_bytes(int G, int n);
+template <typename C>
+hipError_t launch_corr_polish(const PlanView &v, const double2 *rec, const double *rscale, int n, const C *coeffs,
+                              const double *start, int iters, double *angles, double *value, double *ws,
+                              hipStream_t s);
 
 // Device ceilings (probe.hip): a streaming copy of `words` 16-byte words,
 // and dependent-chain loops (kind 0: FP64 vector FMA, 1: FP64 MFMA 16x16x4,

@@ -79,6 +79,8 @@ def lib():
         L.soft_sh_forward.restype = ctypes.c_int
         L.soft_match_refine.argtypes = [vp, vp, vp, vp, vp]
         L.soft_match_refine.restype = ctypes.c_int
+        L.soft_match_polish.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
+        L.soft_match_polish.restype = ctypes.c_int
         L.soft_match_destroy.argtypes = [vp]
         for name in ("soft_match_plan", "soft_match_sizes", "soft_match_plan_soft", "soft_match_coeffs",
                      "soft_match_coeffs_vjp", "soft_match_argmax", "soft_match_argmax_noalloc", "soft_match",
@@ -293,6 +295,12 @@ def soft_match_refine(match, grid, index, angles, stream=None):
     """Refined rotation (alpha, beta, gamma) of each pair at its grid maximum."""
     _check(lib().soft_match_refine(ctypes.c_void_p(match), _ptr(grid), _ptr(index), _ptr(angles),
                                    _stream(stream)), "soft_match_refine")
+
+
+def soft_match_polish(match, coeffs, start, iters, angles, value, stream=None):
+    """Newton-polished rotation of each pair's correlation maximum, off the grid."""
+    _check(lib().soft_match_polish(ctypes.c_void_p(match), _ptr(coeffs), _ptr(start), int(iters), _ptr(angles),
+                                   _ptr(value), _stream(stream)), "soft_match_polish")
 
 
 def soft_match(match, a, b, grid, index, stream=None):
@@ -582,14 +590,30 @@ class MatchPlan:
         soft_match_refine(self.handle, grid, index.contiguous(), angles)
         return angles
 
-    def match_rotation(self, f, g):
+    def polish(self, coeffs, start, iters=6):
+        """Newton steps on the correlation off the grid from ``start``
+        (``refine``'s angles [n, 3]); ``coeffs`` the pairs' correlation
+        coefficients (``coeffs``).  Returns (angles [n, 3], Re C there [n])."""
+        c = self._chk(coeffs, self.plan.coeff_shape(), "coeffs")
+        if start.dtype != torch.float64 or start.numel() != 3 * self.n or start.device != self.device:
+            raise ValueError("start: n x 3 float64 on the head's device")
+        angles = torch.empty(self.n, 3, dtype=torch.float64, device=self.device)
+        value = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        soft_match_polish(self.handle, c, start.contiguous(), iters, angles, value)
+        return angles, value
+
+    def match_rotation(self, f, g, polish_iters=6):
         """The whole matching pipeline for sampled functions on the sphere:
         the rotation R (Euler angles [n, 3], R = Rz(alpha) Ry(beta) Rz(gamma))
-        with g(w) ~ f(R^-1 w) best on the SO(3) grid, refined below it.
-        Returns (angles, grid index)."""
+        with g(w) ~ f(R^-1 w): the maximum on the SO(3) grid, a parabola
+        through its neighbours, then ``polish_iters`` Newton steps off the
+        grid (0: none).  Returns (angles, grid index)."""
         a, b = self.sh_forward(f), self.sh_forward(g)
         grid, idx = self.match(a, b)
-        return self.refine(grid, idx), idx
+        angles = self.refine(grid, idx)
+        if polish_iters:
+            angles, _ = self.polish(self.coeffs(a, b), angles, polish_iters)
+        return angles, idx
 
     def close(self):
         if getattr(self, "handle", None):
