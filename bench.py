@@ -226,10 +226,12 @@ def timed_steps(plan, c, steps, warmup, fwd_in=None):
     breakdown, and the slowest kernel), then `steps` timed steps of inverse
     then forward in which only the slowest kernel carries stage events (its
     launch durations for the roofline), so the timed region is perturbed as
-    little as possible.  HIP events on the launch stream between the calls
-    give the inverse and forward times of every step.  The forward reads the
-    inverse's output grid, or fwd_in when given (a SOFT_INPLACE_OK plan's
-    forward overwrites it).  Returns a dict."""
+    little as possible; the host clock around them (after a synchronize on
+    both sides) gives the throughput.  A second, shorter pass with HIP events
+    on the launch stream between the calls gives the inverse and forward
+    times of each step (their percentiles).  The forward reads the inverse's
+    output grid, or fwd_in when given (a SOFT_INPLACE_OK plan's forward
+    overwrites it).  Returns a dict."""
     import torch
     from paper_1808_00896_amd import soft
     grid = torch.empty(plan.grid_shape(), dtype=plan.dtype, device=DEV)
@@ -252,26 +254,32 @@ def timed_steps(plan, c, steps, warmup, fwd_in=None):
     avg = {k: ms / n for k, (ms, n) in breakdown.items() if n}
     slowest = max(avg, key=avg.get)
     soft.soft_plan_set_timing_stages(plan.handle, [slowest])
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    soft.soft_plan_set_timing(plan.handle, False)
+    st = soft.soft_plan_stage_times(plan.handle, reset=True)
+    # the inverse / forward split, from events between the calls
+    nsplit = max(1, min(steps, 50))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nsplit + 1)]
+    torch.cuda.synchronize()
     ev[0].record()
-    for i in range(steps):
+    for i in range(nsplit):
         plan.inverse(c, out=grid)
         ev[2 * i + 1].record()
         plan.forward(src, out=c2)
         ev[2 * i + 2].record()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    soft.soft_plan_set_timing(plan.handle, False)
-    st = soft.soft_plan_stage_times(plan.handle, reset=True)
-    inv_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
-    fwd_ms = [ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(steps)]
+    inv_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(nsplit)]
+    fwd_ms = [ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(nsplit)]
     step_ms = [a + b for a, b in zip(inv_ms, fwd_ms)]
     slow = dict(st)
     slow = {slowest: slow[slowest], "_steps": steps}
     return {"seconds": t1 - t0, "breakdown": breakdown, "kcal": kcal, "slowest": slow, "grid": grid, "c2": c2,
-            "step_ms": step_ms, "inv_ms": inv_ms, "fwd_ms": fwd_ms}
+            "step_ms": step_ms, "inv_ms": inv_ms, "fwd_ms": fwd_ms, "nsplit": nsplit}
 
 
 def relerr_dev(a, b, chunk=1 << 27):
