@@ -509,13 +509,13 @@ class MatchPlan:
     soft.Plan of the n correlation functions (for backward passes);
     ``inplace_ok`` makes it a plan without an FFT intermediate of its own."""
 
-    def __init__(self, B, n=1, device=None, precision="fp64", tune=False, inplace_ok=False):
+    def __init__(self, B, n=1, device=None, precision="fp64", tune=False, inplace_ok=False, beta_halves=False):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.precision = _precision(precision)
         self.dtype = torch.complex128 if self.precision == SOFT_FP64 else torch.complex64
         with torch.cuda.device(self.device):
-            self.handle = soft_match_plan(B, n, self.precision, _flags(tune, inplace_ok))
+            self.handle = soft_match_plan(B, n, self.precision, _flags(tune, inplace_ok, False, beta_halves))
         self.B, self.n = B, n
         self.plan = Plan._borrow(soft_match_plan_soft(self.handle), B, n, self.device, self.precision,
                                  bool(inplace_ok))

@@ -76,3 +76,36 @@ def test_B1024(oracle, dev, coeffs, prec):
         print(f"B={B} {prec} inverse slice {j}: {errs[j]:.2e}", flush=True)
     assert err_rt <= TOL[prec]
     assert max(errs.values()) <= TOL[prec], errs
+
+
+def test_B1024_in_an_uneven_plan(oracle, dev, coeffs):
+    """B = 1024 (in beta halves, extended-range seeds) sharing a plan with
+    B = 16 and B = 64 functions, FP32-split in place: the small functions
+    equal their single-bandwidth plans bit for bit, and the B = 1024 one
+    round-trips."""
+    prec = "fp32_split"
+    Bs = [16, 1024, 64]
+    small = {16: inputs.coeffs_decay(16, 91), 64: inputs.coeffs_decay(64, 92)}
+    cs = [small[16], coeffs, small[64]]
+    with soft.UnevenPlan(Bs, precision=prec, inplace_ok=True) as p:
+        halves = {d["max_2B"]: d["beta_halves"] for d in p.describe()["dwt_launches"]}
+        assert halves[2048] == 2 and halves.get(128, 1) == 1
+        cd = torch.from_numpy(np.concatenate(cs).astype(np.complex64)).to(dev)
+        g = p.inverse(cd)
+        gs = {B: g[p.grid_offsets[f]:p.grid_offsets[f + 1]].clone() for f, B in enumerate(Bs) if B < 1024}
+        c2 = p.forward(g)
+        del g
+        torch.cuda.synchronize()
+        o = p.coeff_offsets
+        err = _max_rel(c2[o[1]:o[2]], cd[o[1]:o[2]])
+        c_small = {B: c2[o[f]:o[f + 1]].clone() for f, B in enumerate(Bs) if B < 1024}
+        del c2, cd
+    torch.cuda.empty_cache()
+    print(f"uneven with B=1024 {prec}: round trip {err:.2e}", flush=True)
+    assert err <= TOL[prec]
+    for B in (16, 64):
+        with soft.Plan(B, precision=prec, inplace_ok=True) as q:
+            c1 = torch.from_numpy(small[B].astype(np.complex64)).to(dev)
+            g1 = q.inverse(c1)
+            assert torch.equal(g1.reshape(-1), gs[B]), B
+            assert torch.equal(q.forward(g1).reshape(-1), c_small[B]), B

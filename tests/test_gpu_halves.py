@@ -126,3 +126,22 @@ def test_halves_every_shape(dev):
             assert rel(p.forward(ref_g.clone()), ref_c) <= 1e-13, sh
         with pytest.raises(soft.SoftError):
             p.set_dwt_shape(0, 0, 1, 1)  # 64 lanes do not cover 256 rows
+
+
+def test_match_head_in_halves(dev):
+    """The matching head over a plan in beta halves: the correlation grids
+    (an inverse transform) equal the head without halves bit for bit, and so
+    do the argmaxes, with and without grids."""
+    B, n = 64, 3
+    rng = np.random.default_rng(350)
+    a = torch.from_numpy(rng.standard_normal((n, B * B)) + 1j * rng.standard_normal((n, B * B))).to(dev)
+    b = torch.from_numpy(rng.standard_normal((n, B * B)) + 1j * rng.standard_normal((n, B * B))).to(dev)
+    with soft.MatchPlan(B, n) as m0, soft.MatchPlan(B, n, beta_halves=True) as m1:
+        assert m1.plan.describe()["dwt_launches"][0]["beta_halves"] == 2
+        same_inverse_shape(m0.plan, m1.plan)
+        g0, i0 = m0.match(a, b)
+        g1, i1 = m1.match(a, b)
+        j1 = m1.match_index(a, b)
+        torch.cuda.synchronize()
+        assert torch.equal(g0, g1)
+        assert torch.equal(i0, i1) and torch.equal(i0, j1)
