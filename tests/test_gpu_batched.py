@@ -120,11 +120,13 @@ def test_uneven_matches_oracle(oracle, dev, prec):
         gf = g[goff[f]:goff[f + 1]].reshape(N, N, N)
         assert relerr(gf, oracle.inverse(B, cs[f])) <= TOL[prec], (f, B)
         assert relerr(c2[coff[f]:coff[f + 1]], cs[f]) <= TOL[prec], (f, B)
-    # forward of the device grids against the oracle's forward of the same grids
+    # forward of random grids (one per function) against the oracle's forward of the same grids
+    gs = [rounded(inputs.grid_random(B, 60 + f), prec) for f, B in enumerate(Bs)]
+    with soft.UnevenPlan(Bs, precision=prec) as p:
+        cr = to_host(p.forward(to_dev(np.concatenate([x.reshape(-1) for x in gs]), dev, prec)))
     for f in (int(np.argmax(Bs)), int(np.argmin(Bs))):
-        B, N = Bs[f], 2 * Bs[f]
-        gf = g[goff[f]:goff[f + 1]].reshape(N, N, N).astype(np.complex128)
-        assert relerr(c2[coff[f]:coff[f + 1]], oracle.forward(B, gf)) <= TOL[prec], (f, B)
+        B = Bs[f]
+        assert relerr(cr[coff[f]:coff[f + 1]], oracle.forward(B, gs[f])) <= TOL[prec], (f, B)
 
 
 def test_uneven_offsets_and_sizes(dev):
@@ -293,24 +295,28 @@ def test_fp32_B512_sampled(oracle, dev, prec):
     """B = 512 in the FP32 modes (their own 2B = 1024 launch shapes and the
     complex64 half-height forward alpha pass): sampled beta-slices of the
     inverse against the FP64 oracle on the same FP32-rounded coefficients,
-    sampled order pairs of the forward of that grid against the oracle's
-    forward of the same (FP32) grid, and the round trip."""
+    the round trip, and sampled order pairs of the forward of an FP32-rounded
+    random grid against the oracle's forward of the same grid."""
     B = 512
     c = rounded(inputs.coeffs_decay(B, 3), prec)
+    js = (0, 511, 700)
     with soft.Plan(B, precision=prec) as p:
         gd = p.inverse(to_dev(c, dev, prec))
+        sl = {j: to_host(gd[:, j, :]) for j in js}
         cd = to_host(p.forward(gd))
-        g = to_host(gd)
         del gd
+        torch.cuda.empty_cache()
+        gr = rounded(inputs.grid_random(B, 4), prec)
+        cr = to_host(p.forward(to_dev(gr, dev, prec)))
     torch.cuda.empty_cache()
     assert relerr(cd, c) <= 1e-6
-    for j in (0, 511, 700):
-        assert relerr(g[:, j, :], oracle.inverse_slice(B, c, j)) <= 1e-6, j
+    for j in js:
+        assert relerr(sl[j], oracle.inverse_slice(B, c, j)) <= 1e-6, j
     pairs = [(0, 0), (3, -2), (100, 50), (-200, 7), (511, -511)]
-    want = oracle.forward_pairs(B, g, pairs)
-    scale = np.abs(c).max()
+    want = oracle.forward_pairs(B, gr, pairs)
+    scale = np.abs(want).max()
     for (m, mp), w in zip(pairs, want):
         l0 = max(abs(m), abs(mp))
         ls = np.arange(l0, B)
-        got = cd[ls * (4 * ls * ls - 1) // 3 + (m + ls) * (2 * ls + 1) + (mp + ls)]
+        got = cr[ls * (4 * ls * ls - 1) // 3 + (m + ls) * (2 * ls + 1) + (mp + ls)]
         assert np.abs(got - w[l0:]).max() / scale <= 1e-6, (m, mp)

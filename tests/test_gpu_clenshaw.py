@@ -129,29 +129,35 @@ def test_clenshaw_forward_adjoint_batch_uneven(oracle, dev):
 @pytest.mark.parametrize("B", [256, 512])
 def test_clenshaw_large_against_oracle(oracle, dev, B):
     """2B = 512 and 1024: both Clenshaw directions against the oracle on
-    sampled beta slices (inverse; the long-double oracle at B = 512) and
-    sampled order pairs (forward of the band-limited grid)."""
+    sampled beta slices (inverse; the long-double oracle at B = 512), the
+    round trip, and sampled order pairs of the forward of a random grid."""
     c = inputs.coeffs_decay(B, 230 + B)
+    js = (0, B + 3, 2 * B - 1)
     with soft.Plan(B) as p:
         clenshaw(p, (0, 1))
         gd = p.inverse(to_dev(c, dev))
+        sl = {j: host(gd[:, j, :]) for j in js}
         cd = host(p.forward(gd))
-        g = host(gd)
         del gd
+        torch.cuda.empty_cache()
+        gr = inputs.grid_random(B, 240 + B)
+        cr = host(p.forward(to_dev(gr, dev)))
     torch.cuda.empty_cache()
     prec = "f80" if B == 512 else "f64"
-    for j in (0, B + 3, 2 * B - 1):
-        err = relerr(g[:, j, :], oracle.inverse_slice(B, c, j, prec=prec))
+    tol = 1e-9 if B == 512 else 1e-11
+    assert relerr(cd, c) <= tol
+    for j in js:
+        err = relerr(sl[j], oracle.inverse_slice(B, c, j, prec=prec))
         print(f"B={B} inverse slice {j}: {err:.2e}")
-        assert err <= (1e-9 if B == 512 else 1e-11), j
+        assert err <= tol, j
     pairs = [(0, 0), (B - 1, 1 - B), (-(B // 2), 7), (B // 4, B // 4 - 1)]
-    want = oracle.forward_pairs(B, g, pairs)
+    want = oracle.forward_pairs(B, gr, pairs, prec)
     for k, (m, mp) in enumerate(pairs):
         l0 = max(abs(m), abs(mp))
-        got = np.array([cd[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
-        err = np.abs(got - want[k, l0:]).max() / np.abs(c).max()
+        got = np.array([cr[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
+        err = np.abs(got - want[k, l0:]).max() / np.abs(want).max()
         print(f"B={B} forward pair {(m, mp)}: {err:.2e}")
-        assert err <= (1e-9 if B == 512 else 1e-11), (m, mp)
+        assert err <= tol, (m, mp)
 
 
 @pytest.mark.parametrize("B", [256, 512])

@@ -55,14 +55,16 @@ def test_inplace_bit_identical(dev, prec, B):
 def test_inplace_matches_oracle(oracle, dev):
     B = 16
     c = inputs.coeffs_uniform(B, 0)
+    gr = inputs.grid_random(B, 1)
     with soft.Plan(B, inplace_ok=True) as p:
         g = p.inverse(to_dev(c, dev))
         gh = g.cpu().numpy()
         c2 = p.forward(g).cpu().numpy()  # overwrites g
+        cr = p.forward(to_dev(gr, dev)).cpu().numpy()
     want = oracle.inverse(B, c)
     assert np.abs(gh - want).max() <= 1e-11 * np.abs(want).max()
-    want_c = oracle.forward(B, gh)
-    assert np.abs(c2 - want_c).max() <= 1e-11 * np.abs(want_c).max()
+    want_c = oracle.forward(B, gr)
+    assert np.abs(cr - want_c).max() <= 1e-11 * np.abs(want_c).max()
     assert np.abs(c2 - c).max() <= 1e-11 * np.abs(c).max()
 
 

@@ -118,50 +118,61 @@ def test_B128_full(oracle, dev):
     assert relerr(cd, c) <= TOL64
 
 
-def test_B256_sampled(oracle, dev):
-    """B = 256 (512^3 grid): sampled beta-slices of the inverse and sampled
-    order pairs of the forward against the double oracle; round trip."""
-    B = 256
-    c = inputs.coeffs_decay(B, 2)
-    with soft.Plan(B) as p:
-        gd = p.inverse(to_dev(c, dev))
-        cd = to_host(p.forward(gd))
-        g = to_host(gd)
-        del gd
-    for j in (0, 1, 255, 256, 511):
-        want = oracle.inverse_slice(B, c, j)
-        assert relerr(g[:, j, :], want) <= TOL64, j
-    assert relerr(cd, c) <= TOL64
-    pairs = [(0, 0), (1, -1), (37, 200), (-128, 5), (255, -255), (-3, 254)]
-    want = oracle.forward_pairs(B, g, pairs)
+def forward_pair_errors(oracle, B, grid, cd, pairs, prec="f64"):
+    """Largest error over the listed order pairs of the coefficients cd (the
+    HIP forward of grid) against the oracle's forward of the same grid,
+    relative to the largest oracle coefficient of those pairs."""
+    want = oracle.forward_pairs(B, grid, pairs, prec)
+    errs = []
     for p_, (m, mp) in enumerate(pairs):
         l0 = max(abs(m), abs(mp))
         got = np.array([cd[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
-        assert np.abs(got - want[p_, l0:]).max() <= TOL64 * np.abs(c).max(), (m, mp)
+        errs.append(np.abs(got - want[p_, l0:]).max())
+    return float(max(errs) / np.abs(want).max())
+
+
+def test_B256_sampled(oracle, dev):
+    """B = 256 (512^3 grid): sampled beta-slices of the inverse against the
+    double oracle, the round trip, and sampled order pairs of the forward of a
+    random grid."""
+    B = 256
+    c = inputs.coeffs_decay(B, 2)
+    gr = inputs.grid_random(B, 22)
+    js = (0, 1, 255, 256, 511)
+    with soft.Plan(B) as p:
+        gd = p.inverse(to_dev(c, dev))
+        sl = {j: to_host(gd[:, j, :]) for j in js}
+        cd = to_host(p.forward(gd))
+        del gd
+        cr = to_host(p.forward(to_dev(gr, dev)))
+    for j in js:
+        assert relerr(sl[j], oracle.inverse_slice(B, c, j)) <= TOL64, j
+    assert relerr(cd, c) <= TOL64
+    pairs = [(0, 0), (1, -1), (37, 200), (-128, 5), (255, -255), (-3, 254)]
+    assert forward_pair_errors(oracle, B, gr, cr, pairs) <= TOL64
 
 
 def test_B512_sampled(oracle, dev):
     """B = 512 (1024^3 complex128 grid, 16 GiB): sampled inverse slices against
-    the long-double oracle (gate 1e-9), forward on sampled order pairs, and the
-    round trip over all 1.8e8 coefficients."""
+    the long-double oracle (gate 1e-9), the round trip over all 1.8e8
+    coefficients, and sampled order pairs of the forward of a random grid."""
     B = 512
     c = inputs.coeffs_decay(B, 3)
+    js = (0, 700)
     with soft.Plan(B) as p:
         gd = p.inverse(to_dev(c, dev))
+        sl = {j: to_host(gd[:, j, :]) for j in js}
         cd = to_host(p.forward(gd))
-        g = to_host(gd)
         del gd
         torch.cuda.empty_cache()
+        gr = inputs.grid_random(B, 23)
+        cr = to_host(p.forward(to_dev(gr, dev)))
+        torch.cuda.empty_cache()
     assert relerr(cd, c) <= 1e-9
-    for j in (0, 700):
-        want = oracle.inverse_slice(B, c, j, prec="f80")
-        assert relerr(g[:, j, :], want) <= 1e-9, j
+    for j in js:
+        assert relerr(sl[j], oracle.inverse_slice(B, c, j, prec="f80")) <= 1e-9, j
     pairs = [(0, 0), (511, -511), (-300, 17), (64, 63)]
-    want = oracle.forward_pairs(B, g, pairs)
-    for p_, (m, mp) in enumerate(pairs):
-        l0 = max(abs(m), abs(mp))
-        got = np.array([cd[oracle.coeff_index(l, m, mp)] for l in range(l0, B)])
-        assert np.abs(got - want[p_, l0:]).max() <= 1e-9 * np.abs(c).max(), (m, mp)
+    assert forward_pair_errors(oracle, B, gr, cr, pairs) <= 1e-9
 
 
 def test_plan_errors_on_gpu(dev):

@@ -76,8 +76,8 @@ def test_match_rotation_recovers_rotation(oracle, dev, prec):
     """Pair 0: g = f rotated by a grid rotation, found exactly (the grid
     index and, after refinement, the rotation to 1e-6 rad in FP64).  Pair 1: an
     off-grid rotation, where the refined rotation lies closer to the truth
-    than the grid point.  The refinement equals the oracle's on the same
-    grid."""
+    than the grid point.  The argmax equals the oracle's on the oracle's
+    correlation grid, and the refinement of that grid equals the oracle's."""
     from scipy.spatial.transform import Rotation
     B = 16
     N = 2 * B
@@ -100,12 +100,24 @@ def test_match_rotation_recovers_rotation(oracle, dev, prec):
         ang = m.refine(grid, idx)
         ang2, idx2 = m.match_rotation(fd, gd, polish_iters=0)
         torch.cuda.synchronize()
-        ang, idx, grid_h = ang.cpu().numpy(), idx.cpu().numpy(), grid.cpu().numpy()
+        ang, idx = ang.cpu().numpy(), idx.cpu().numpy()
         assert np.array_equal(idx, idx2.cpu().numpy()) and np.array_equal(ang, ang2.cpu().numpy())
     assert idx[0] == (i0 * N + j0) * N + k0
+    # the oracle's chain on the same sampled functions: S^2 transforms,
+    # correlation coefficients, inverse, argmax; the GPU refinement of that
+    # grid at that index against the oracle's refinement
+    rnd = (lambda x: x.astype(np.complex64).astype(np.complex128)) if prec != "fp64" else (lambda x: x)
+    Co = np.stack([rnd(oracle.inverse(B, oracle.correlation_coeffs(B, oracle.sh_forward(B, rnd(fs[p])),
+                                                                    oracle.sh_forward(B, rnd(gs[p])))))
+                   for p in range(2)])
+    io = [oracle.argmax_real(Co[p].reshape(-1)) for p in range(2)]
+    assert io == [int(i) for i in idx], (io, idx)
+    with soft.MatchPlan(B, 2, precision=prec) as m:
+        ango = m.refine(torch.from_numpy(Co).to(dev).to(m.dtype),
+                        torch.tensor(io, dtype=torch.int64, device=dev)).cpu().numpy()
     for p in range(2):
-        want = oracle.refine_quadratic(B, grid_h[p].astype(np.complex128), int(idx[p]))
-        assert np.allclose(ang[p], want, atol=1e-12), (p, ang[p], want)
+        want = oracle.refine_quadratic(B, Co[p], io[p])
+        assert np.allclose(ango[p], want, atol=1e-12), (p, ango[p], want)
     # the correlation peak of a rotated copy is symmetric about the rotation,
     # so the parabolas stay on it (up to the grid values' rounding)
     assert (Rotation.from_euler("ZYZ", ang[0]).inv() * R_grid).magnitude() <= (1e-6 if prec == "fp64" else 1e-3)
