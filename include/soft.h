@@ -91,8 +91,8 @@ typedef enum {
  *                   DWT launches per candidate at plan creation; without it
  *                   a fixed shape per 2B, direction and precision is used.
  *                   When the environment variable SOFT_TUNE_CACHE names a
- *                   file, a plan whose key (device architecture, precision,
- *                   beta halves or not, bandwidths with their function
+ *                   file, a plan whose key (device architecture, precision
+ *                   and recurrence, beta halves or not, bandwidths with their function
  *                   counts) is in it takes the stored shapes instead of
  *                   timing, and a plan that times writes its entry there
  *                   (a JSON object, one entry per line, rewritten whole
@@ -128,8 +128,31 @@ typedef enum {
  *                   bit-identical to a plan without the flag; forward
  *                   results differ by the rounding of that one addition.
  *                   Bands with 2B = 2048 always run this way.
+ *   SOFT_DD_RECURRENCE  (FP64 plans only; SOFT_ERR_INVALID with the other
+ *                   precisions) the DWT runs the three-term recurrence of
+ *                   eq. "Wigner_d_recurrence" in double-double: its
+ *                   coefficients (filled in double-double at plan time, 16
+ *                   more bytes per recurrence row), cos(beta_j) and the
+ *                   recurrence values carry about 106 bits, and each value
+ *                   enters the FP64 matrix contraction rounded once.  The
+ *                   FP64 recurrence loses accuracy with the degree (near
+ *                   beta = 0 most: there alpha_l x - gamma_l cancels, and the
+ *                   rounding of the coefficients and of cos(beta_j) is
+ *                   amplified); this mode leaves the FP64 rounding of the FFT
+ *                   and of the contraction (Sect. 5 names B = 512 as the size
+ *                   where double precision alone falls short on its CPU
+ *                   design, which used extended precision).  Costs about
+ *                   fifteen times the recurrence's arithmetic; the DWT launch
+ *                   shapes are the FP64 defaults 1x1, 2x1, 4x1, 2x2, 4x2 and
+ *                   4x4, and the Clenshaw forms are not available.
  */
-enum { SOFT_PLAN_TUNE = 1u, SOFT_INPLACE_OK = 2u, SOFT_PLAN_GRAPH = 4u, SOFT_BETA_HALVES = 8u };
+enum {
+    SOFT_PLAN_TUNE = 1u,
+    SOFT_INPLACE_OK = 2u,
+    SOFT_PLAN_GRAPH = 4u,
+    SOFT_BETA_HALVES = 8u,
+    SOFT_DD_RECURRENCE = 16u
+};
 
 typedef enum {
     SOFT_OK = 0,
@@ -158,8 +181,9 @@ typedef enum {
  *              without the flag the FFT intermediate adds one grid's size.
  *   batch      number of functions per call, 1 <= batch <= 65535.
  *   precision  a soft_precision.
- *   flags      any of SOFT_PLAN_TUNE, SOFT_INPLACE_OK and SOFT_PLAN_GRAPH;
- *              other bits are SOFT_ERR_INVALID.
+ *   flags      any of SOFT_PLAN_TUNE, SOFT_INPLACE_OK, SOFT_PLAN_GRAPH,
+ *              SOFT_BETA_HALVES and (FP64) SOFT_DD_RECURRENCE; other bits
+ *              are SOFT_ERR_INVALID.
  *   out        receives the plan handle; unchanged on error.
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
@@ -216,6 +240,7 @@ int soft_plan_sizes(soft_plan_t plan, size_t *grid_elems, size_t *coeff_elems,
 /*
  * soft_plan_describe -- a one-line JSON description of the plan (bands,
  * functions, workspace bytes, whether it was made with SOFT_INPLACE_OK,
+ * whether it runs the double-double recurrence (SOFT_DD_RECURRENCE),
  * whether its tuned shapes came from the SOFT_TUNE_CACHE file, and
  * per DWT launch its largest 2B, the number of beta halves it runs in (2 for
  * 2B = 2048, see soft_plan), work items, forward and inverse launch shapes
@@ -241,6 +266,8 @@ int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
  *              adjoint-Clenshaw evaluation: each lane runs the three-term
  *              recurrence forward and the sums over beta are reduced across
  *              lanes).  soft_plan_describe reports it as [0, 0].
+ *              A SOFT_DD_RECURRENCE plan takes 1x1, 2x1, 4x1, 2x2, 4x2 and
+ *              4x4 only (no Clenshaw form).
  * Takes effect for later calls.  Returns SOFT_OK or SOFT_ERR_INVALID.
  */
 int soft_plan_set_dwt_shape(soft_plan_t plan, int launch, int direction, int waves, int subsets);

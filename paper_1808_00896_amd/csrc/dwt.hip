@@ -58,14 +58,66 @@ struct DD {
     double hi, lo;
 };
 
+// The error-free sums and products below hold only if every operation
+// rounds as written: hipcc contracts a product and a later sum into one FMA
+// by default, which would drop the rounding that the error terms recover.
+// Each of these functions turns that off for its own operations.
 __device__ __forceinline__ DD two_prod(double a, double b) {
+#pragma clang fp contract(off)
     const double h = a * b;
     return {h, fma(a, b, -h)};
 }
 __device__ __forceinline__ DD two_sum(double a, double b) {
+#pragma clang fp contract(off)
     const double s = a + b;
     const double bb = s - a;
     return {s, (a - (s - bb)) + (b - bb)};
+}
+// s + err = a + b exactly, for |a| >= |b| (or a = 0)
+__device__ __forceinline__ DD quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+
+// Double-double arithmetic (Dekker's and Knuth's error-free sums and
+// products, with the product's error by FMA): a value is hi + lo with
+// |lo| <= ulp(hi)/2, about 106 significant bits.  The sums drop the rounding
+// of lo + lo, so their relative error is about 2^-104 of |a| + |b|.
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+#pragma clang fp contract(off)
+    const DD s = two_sum(a.hi, b.hi);
+    return quick_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+__device__ __forceinline__ DD dd_mul(DD a, DD b) {
+#pragma clang fp contract(off)
+    DD p = two_prod(a.hi, b.hi);
+    p.lo = fma(a.hi, b.lo, fma(a.lo, b.hi, p.lo));
+    return quick_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ DD dd_mul(DD a, double b) {
+#pragma clang fp contract(off)
+    DD p = two_prod(a.hi, b);
+    p.lo = fma(a.lo, b, p.lo);
+    return quick_two_sum(p.hi, p.lo);
+}
+// a / b by long division: three quotient digits, each from the remainder so far.
+__device__ __forceinline__ DD dd_div(DD a, DD b) {
+#pragma clang fp contract(off)
+    const double q1 = a.hi / b.hi;
+    DD r = dd_add(a, dd_mul(b, -q1));
+    const double q2 = r.hi / b.hi;
+    r = dd_add(r, dd_mul(b, -q2));
+    const double q3 = r.hi / b.hi;
+    return dd_add(quick_two_sum(q1, q2), DD{q3, 0.0});
+}
+// sqrt(v) for a double v >= 0: the rounded root plus one Newton correction
+// from its exact residual v - h^2 (one FMA).
+__device__ __forceinline__ DD dd_sqrt(double v) {
+#pragma clang fp contract(off)
+    if (v <= 0.0) return {0.0, 0.0};
+    const double h = sqrt(v);
+    return quick_two_sum(h, fma(-h, h, v) / (2.0 * h));
 }
 
 // Seed d(l0, l0, m'; b_j) = sqrt((2 l0)!/((l0+m')!(l0-m')!)) cos^{l0+m'}(b/2)
@@ -83,6 +135,7 @@ constexpr double kXrScale = 0x1p1000, kXrUnscale = 0x1p-1000;
 constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;  // ln 2 = hi + lo
 
 __device__ __forceinline__ double seed_d(double2 lb, double4 t, int m, int mp, bool xr) {
+#pragma clang fp contract(off)
     const double P = (double)(m + mp), Q = (double)(m - mp);
     DD a = two_prod(P, t.x);
     a.lo = fma(P, t.y, a.lo);
@@ -137,6 +190,42 @@ __global__ __launch_bounds__(256) void k_fill_recurrence(PlanView p, double2 *__
         const double r = s_cur / s_next;
         row[t] = make_double2(A * r, C * r);
         srow[t] = s_cur;
+        s_prev = s_cur;
+        s_cur = s_next;
+    }
+}
+
+// The same table in double-double (plans with SOFT_DD_RECURRENCE): rec gets
+// the rounded (alpha_l, gamma_l), reclo what they lose in that rounding, and
+// rscale the rounded s_l of a double-double running product.  The integer
+// products under the square roots stay below 2^53 (l <= 2048), so they are
+// exact, and every other step carries about 106 bits.
+__global__ __launch_bounds__(256) void k_fill_recurrence_dd(PlanView p, double2 *__restrict__ rec,
+                                                           double2 *__restrict__ reclo,
+                                                           double *__restrict__ rscale) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= p.G) return;
+    const GroupInfo gi = p.grp[g];
+    const int m = gi.m, mp = gi.mp, l0 = m;
+    const double M2 = (double)m * m, MP2 = (double)mp * mp, MMP = (double)m * mp;
+    double2 *row = rec + p.goff[g];
+    double2 *rlo = reclo + p.goff[g];
+    double *srow = rscale + p.goff[g];
+    DD s_prev = {0.0, 0.0}, s_cur = {1.0, 0.0};  // s_{l-1}, s_l
+    for (int t = 0; t < p.B - l0; ++t) {
+        const int l = l0 + t;
+        const double L = l, L1 = l + 1;
+        const DD den = dd_sqrt((L1 * L1 - M2) * (L1 * L1 - MP2));
+        const DD A = dd_div(DD{L1 * (2.0 * L + 1.0), 0.0}, den);
+        const DD C = l > 0 ? dd_div(dd_mul(A, MMP), DD{L * L1, 0.0}) : DD{0.0, 0.0};
+        const DD Bc = l > l0 ? dd_div(dd_mul(dd_sqrt((L * L - M2) * (L * L - MP2)), L1), dd_mul(den, L))
+                             : DD{0.0, 0.0};
+        const DD s_next = t == 0 ? DD{1.0, 0.0} : dd_mul(Bc, s_prev);
+        const DD r = dd_div(s_cur, s_next);
+        const DD a = dd_mul(A, r), c = dd_mul(C, r);
+        row[t] = make_double2(a.hi, c.hi);
+        rlo[t] = make_double2(a.lo, c.lo);
+        srow[t] = s_cur.hi;
         s_prev = s_cur;
         s_cur = s_next;
     }
@@ -229,9 +318,42 @@ __device__ __forceinline__ void seed_load(double sd, bool in, double &e, double 
 // and writes e * xs; once |e| passes 2^800 the scale is folded back (d grows
 // by at most about 2^116 over 16 degrees, so e stays far below the double
 // range in between).  A wave without a scaled lane takes the plain loop.
-template <int PR, int RS, bool XR>
-__device__ __forceinline__ void panel_fill(double *pan, const double2 (&c)[16], double x, double &ecur,
-                                           double &eprev, double &xs) {
+// With DD (SOFT_DD_RECURRENCE) the step runs in double-double: alpha, gamma
+// (c + cl), x (x + xl) and e (ecur + ecl, eprev + epl), and the panel gets e
+// rounded to double.
+template <int PR, int RS, bool XR, bool DD_>
+__device__ __forceinline__ void panel_fill(double *pan, const double2 (&c)[16], const double2 (&cl)[16], double x,
+                                           double xl, double &ecur, double &eprev, double &ecl, double &epl,
+                                           double &xs) {
+    if constexpr (DD_) {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            panel_put<PR>(&pan[r * RS], XR ? ecur * xs : ecur);
+            // u = alpha x - gamma
+            DD pr = two_prod(c[r].x, x);
+            pr.lo = fma(c[r].x, xl, fma(cl[r].x, x, pr.lo));
+            DD u = two_sum(pr.hi, -c[r].y);
+            u = quick_two_sum(u.hi, u.lo + (pr.lo - cl[r].y));
+            // e(l + 1) = u e(l) - e(l - 1)
+            DD q = two_prod(u.hi, ecur);
+            q.lo = fma(u.hi, ecl, fma(u.lo, ecur, q.lo));
+            DD en = two_sum(q.hi, -eprev);
+            en = quick_two_sum(en.hi, en.lo + (q.lo - epl));
+            eprev = ecur;
+            epl = ecl;
+            ecur = en.hi;
+            ecl = en.lo;
+        }
+        if (XR && xs != 1.0 && fabs(ecur) >= 0x1p800) {
+            ecur *= kXrUnscale;
+            ecl *= kXrUnscale;
+            eprev *= kXrUnscale;
+            epl *= kXrUnscale;
+            xs = 1.0;
+        }
+        return;
+    }
     if constexpr (XR) {
         if (__builtin_amdgcn_ballot_w64(xs != 1.0) != 0) {
 #pragma unroll
@@ -281,11 +403,13 @@ __device__ __forceinline__ int beta_of(const JMap &jm, int k) {
 // xb the B operand, c the first panel's recurrence coefficients, and srow
 // the item's s_l (visible after the first barrier).  flags: kFlagScale
 // applies V_B, kFlagAccum adds to the coefficients (the second beta half).
-template <int NW, int NSUB, int PR, bool XR>
+template <int NW, int NSUB, int PR, bool XR, bool DD_>
 __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd], const double *srow,
                                                 const WorkItem &it, const double2 *__restrict__ Rr,
-                                                double2 (&c)[16], typename PrecT<PR>::R (&xb)[NSUB][16],
-                                                double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
+                                                const double2 *__restrict__ Rl, double2 (&c)[16],
+                                                double2 (&cl)[16], typename PrecT<PR>::R (&xb)[NSUB][16],
+                                                double (&x)[NSUB], double (&xl)[NSUB], double (&ecur)[NSUB],
+                                                double (&eprev)[NSUB], double (&ecl)[NSUB], double (&epl)[NSUB],
                                                 double (&xs)[NSUB], typename PrecT<PR>::C *__restrict__ coeffs,
                                                 int flags) {
     using R = typename PrecT<PR>::R;
@@ -320,7 +444,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
             for (int a = 0; a < 4; ++a) acc[a] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-                panel_fill<PR, kRowFwd, XR>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
+                panel_fill<PR, kRowFwd, XR, DD_>(pan + lane, c, cl, x[h], xl[h], ecur[h], eprev[h], ecl[h], epl[h], xs[h]);
                 double a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s) a[s] = pan[col * kRowFwd + 4 * s + krow];
@@ -328,6 +452,10 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
                     lds_wait_all();
 #pragma unroll
                     for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                    if constexpr (DD_) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) cl[r] = Rl[lp + 16 + r];
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
@@ -346,7 +474,7 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
             for (int a = 0; a < 4; ++a) acc[a] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-                panel_fill<PR, kRowFwd, XR>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
+                panel_fill<PR, kRowFwd, XR, DD_>(pan + lane, c, cl, x[h], xl[h], ecur[h], eprev[h], ecl[h], epl[h], xs[h]);
                 float2 a[16];
 #pragma unroll
                 for (int s = 0; s < 16; ++s)
@@ -355,6 +483,10 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
                     lds_wait_all();
 #pragma unroll
                     for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                    if constexpr (DD_) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) cl[r] = Rl[lp + 16 + r];
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
@@ -429,11 +561,12 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
 // covers 16 beta samples; the split mode keeps the lo products apart).
 // Lane row k of the launch's beta rows (all 2B, or one beta half of jm) is
 // beta sample beta_of(jm, k); XR: extended-range seeds (2B = 2048).
-template <int NW, int NSUB, int PR, bool XR>
+template <int NW, int NSUB, int PR, bool XR, bool DD_>
 __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
                                                     const typename PrecT<PR>::C *__restrict__ S,
-                                                    typename PrecT<PR>::C *__restrict__ coeffs, int flags, JMap jm) {
+                                                    typename PrecT<PR>::C *__restrict__ coeffs, int flags, JMap jm,
+                                                    DdTables ddt) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
     // s_l of the group's degrees: at most B <= NW*NSUB*64 (a launch in beta
@@ -449,6 +582,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long goff = it.goff;
     const double2 *__restrict__ Rr = rec + goff;
+    const double2 *__restrict__ Rl = DD_ ? ddt.rec_lo + goff : nullptr;
 
     const C *Sg = S + it.s_off;
     // B operand: X[j][c] with c = 2*slot + (re, im); lane holds row k = lane/16, column lane%16.
@@ -460,9 +594,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     // all in flight at once: the recurrence coefficients of the first panel
     // (scalar), the S block (read once: non-temporal loads, about 1 % off the
     // B = 128 step), cos b_j and seeds, and s_l of the lane's row.
-    double2 c[16];
+    double2 c[16], cl[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
+    if constexpr (DD_) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cl[r] = Rl[r];
+    }
     // Lanes load whole complex samples: the even lane of a pair (re) that of
     // step s, the odd lane (im) that of step s + 1; one swap of a half between
     // the two lanes later leaves each with its part of both steps.  A load
@@ -470,7 +608,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     // slot row.  Samples past N load sample 0 and, like absent slots, are
     // zeroed: no branches.
     C raw[NSUB][8];
-    double xv[NSUB], sv[NSUB];
+    double xv[NSUB], xlv[NSUB], sv[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int jbase = (wave * NSUB + h) * 64;
@@ -485,6 +623,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         }
         const int j = beta_of(jm, jbase + lane < N ? jbase + lane : 0);
         xv[h] = tab.cosb[it.jbase + j];
+        if constexpr (DD_) xlv[h] = ddt.cosb_lo[it.jbase + j];
         sv[h] = tab.seed[it.seed_off + j];
     }
     // s_l of the group's rows (L <= B <= SROW, so at most RSN per thread),
@@ -496,7 +635,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
     __builtin_amdgcn_sched_barrier(0);
 
     R xb[NSUB][16];
-    double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB];
+    double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB], xl[NSUB], ecl[NSUB], epl[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int jbase = (wave * NSUB + h) * 64;
@@ -512,11 +651,17 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double
         x[h] = jin ? xv[h] : 0.0;
         seed_load(sv[h], jin, ecur[h], xs[h]);
         eprev[h] = 0.0;
+        if constexpr (DD_) {
+            xl[h] = jin ? xlv[h] : 0.0;
+            ecl[h] = 0.0;
+            epl[h] = 0.0;
+        }
     }
 #pragma unroll
     for (int q = 0; q < RSN; ++q)
         if ((int)threadIdx.x + q * NW * 64 < L) srow[threadIdx.x + q * NW * 64] = rs[q];
-    fwd_item_panels<NW, NSUB, PR, XR>(panel, srow, it, Rr, c, xb, x, ecur, eprev, xs, coeffs, flags);
+    fwd_item_panels<NW, NSUB, PR, XR, DD_>(panel, srow, it, Rr, Rl, c, cl, xb, x, xl, ecur, eprev, ecl, epl, xs,
+                                           coeffs, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,11 +758,13 @@ __device__ __forceinline__ void inv_put(const InvGather<NT, KC, R> &st, R *buf, 
 // recurrence fills the wave's panel and advances, and the panel (A) times
 // bop (B, this lane's four coefficient values of the panel) accumulates into
 // acc on matrix cores.  Loads the next panel's recurrence coefficients into c.
-template <int NW, int NSUB, int PR, bool XR>
+template <int NW, int NSUB, int PR, bool XR, bool DD_>
 __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], const typename PrecT<PR>::R (&bop)[4],
-                                          double2 (&c)[16], const double2 *__restrict__ Rr, int lp,
-                                          const double (&x)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
-                                          double (&xs)[NSUB], v4d (&acc)[NSUB][4]) {
+                                          double2 (&c)[16], double2 (&cl)[16], const double2 *__restrict__ Rr,
+                                          const double2 *__restrict__ Rl, int lp, const double (&x)[NSUB],
+                                          const double (&xl)[NSUB], double (&ecur)[NSUB], double (&eprev)[NSUB],
+                                          double (&ecl)[NSUB], double (&epl)[NSUB], double (&xs)[NSUB],
+                                          v4d (&acc)[NSUB][4]) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, krow = lane >> 4;
     double *pan = panel[threadIdx.x >> 6];
@@ -625,7 +772,7 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
     if constexpr (PR == P32S) bopb = bf4((float)bop[0], (float)bop[1], (float)bop[2], (float)bop[3]);
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
-        panel_fill<PR, kRowInv, XR>(pan + lane, c, x[h], ecur[h], eprev[h], xs[h]);
+        panel_fill<PR, kRowInv, XR, DD_>(pan + lane, c, cl, x[h], xl[h], ecur[h], eprev[h], ecl[h], epl[h], xs[h]);
         if constexpr (PR == P64) {
             double a[4][4];
 #pragma unroll
@@ -636,6 +783,10 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
                 lds_wait_all();
 #pragma unroll
                 for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                if constexpr (DD_) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) cl[r] = Rl[lp + 16 + r];
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
@@ -654,6 +805,10 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
                 lds_wait_all();
 #pragma unroll
                 for (int r = 0; r < 16; ++r) c[r] = Rr[lp + 16 + r];
+                if constexpr (DD_) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) cl[r] = Rl[lp + 16 + r];
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
@@ -709,11 +864,12 @@ __device__ __forceinline__ void inv_store(double *pan, const v4d (&acc)[NSUB][4]
     }
 }
 
-template <int NW, int NSUB, int PR, bool XR>
+template <int NW, int NSUB, int PR, bool XR, bool DD_>
 __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
                                                     const typename PrecT<PR>::C *__restrict__ coeffs,
-                                                    typename PrecT<PR>::C *__restrict__ S, int flags, JMap jm) {
+                                                    typename PrecT<PR>::C *__restrict__ S, int flags, JMap jm,
+                                                    DdTables ddt) {
     using C = typename PrecT<PR>::C;
     using R = typename PrecT<PR>::R;
     constexpr int NT = NW * 64;
@@ -730,6 +886,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
     const double2 *__restrict__ Rr = rec + it.goff;
+    const double2 *__restrict__ Rl = DD_ ? ddt.rec_lo + it.goff : nullptr;
     const R *__restrict__ cin = reinterpret_cast<const R *>(coeffs + it.coeff_off);
     const double v0 = apply_v ? 1.0 / (8.0 * M_PI * (double)B) : 0.0;
 
@@ -737,7 +894,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
     inv_gather_init<NT, KC, R>(st, it);
     inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 0);
 
-    double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB];
+    double x[NSUB], ecur[NSUB], eprev[NSUB], xs[NSUB], xl[NSUB], ecl[NSUB], epl[NSUB];
 #pragma unroll
     for (int h = 0; h < NSUB; ++h) {
         const int k = (wave * NSUB + h) * 64 + lane;
@@ -748,6 +905,12 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         x[h] = jin ? xv : 0.0;
         seed_load(sv, jin, ecur[h], xs[h]);
         eprev[h] = 0.0;
+        if constexpr (DD_) {
+            const double xlv = ddt.cosb_lo[it.jbase + j];
+            xl[h] = jin ? xlv : 0.0;
+            ecl[h] = 0.0;
+            epl[h] = 0.0;
+        }
     }
     v4d acc[NSUB][4];
 #pragma unroll
@@ -755,9 +918,13 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[h][t] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    double2 c[16];
+    double2 c[16], cl[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = Rr[r];  // the table is padded past the last group
+    if constexpr (DD_) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cl[r] = Rl[r];
+    }
 
     inv_put<NT, KC, R>(st, stage[0], it, L, 0, v0);
     if (nchunk > 1) inv_gather<NT, KC, R>(st, tab.rscale, cin, it, L, 1);
@@ -770,7 +937,7 @@ __global__ __launch_bounds__(NW * 64) void k_dwt_inv(DwtTables tab, const double
         R bop[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) bop[s] = fb[(4 * s + krow) * 16 + col];
-        inv_panel<NW, NSUB, PR, XR>(panel, bop, c, Rr, lp, x, ecur, eprev, xs, acc);
+        inv_panel<NW, NSUB, PR, XR, DD_>(panel, bop, c, cl, Rr, Rl, lp, x, xl, ecur, eprev, ecl, epl, xs, acc);
         // Chunk boundary: stage the next chunk (its loads were issued a chunk ago).
         if (lp + 16 - ch * KC == KC || lp + 16 >= L) {
             if (ch + 1 < nchunk) {
@@ -797,38 +964,56 @@ hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscal
     return hipGetLastError();
 }
 
+hipError_t launch_fill_recurrence_dd(const PlanView &p, double2 *rec, double2 *reclo, double *rscale,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_recurrence_dd, dim3((p.G + 255) / 256), dim3(256), 0, s, p, rec, reclo, rscale);
+    return hipGetLastError();
+}
+
 // Launch shapes (waves x subsets of 64 beta samples per wave): 1x1, 2x1, 4x1,
 // 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4, 8x4; a shape covers items with beta
 // rows (2B, or jm.n) <= waves*subsets*64.  The extended-range (xr) forms
 // exist for the shapes that cover a beta half of 2B = 2048 or all of it.
+// The double-double recurrence (dd, FP64 only) is built for the FP64
+// default shapes 1x1, 2x1, 4x1, 2x2, 4x2, 4x4 (and 4x4 xr).
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
-                          bool accum, const JMap &jm, bool xr, hipStream_t s) {
+                          bool accum, const JMap &jm, bool xr, const DdTables *dd, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int fl = (apply_v ? kFlagScale : 0) | (accum ? kFlagAccum : 0);
     const dim3 grid(nitems);
-#define SOFT_DWT_FWD(NW_, NS_, XR_)                                                                         \
-    if (nw == NW_ && nsub == NS_ && xr == XR_) {                                                             \
-        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR, XR_>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items,  \
-                           nitems, S, coeffs, fl, jm);                                                       \
-        return hipGetLastError();                                                                            \
+    const DdTables ddt = dd ? *dd : DdTables{nullptr, nullptr};
+#define SOFT_DWT_FWD(NW_, NS_, XR_, DD_)                                                                     \
+    if (nw == NW_ && nsub == NS_ && xr == XR_ && (dd != nullptr) == DD_) {                                    \
+        hipLaunchKernelGGL((k_dwt_fwd<NW_, NS_, PR, XR_, DD_>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items,    \
+                           nitems, S, coeffs, fl, jm, ddt);                                                     \
+        return hipGetLastError();                                                                             \
     }
-    SOFT_DWT_FWD(1, 1, false)
-    SOFT_DWT_FWD(2, 1, false)
-    SOFT_DWT_FWD(4, 1, false)
-    SOFT_DWT_FWD(8, 1, false)
-    SOFT_DWT_FWD(1, 2, false)
-    SOFT_DWT_FWD(2, 2, false)
-    SOFT_DWT_FWD(4, 2, false)
-    SOFT_DWT_FWD(8, 2, false)
-    SOFT_DWT_FWD(4, 4, false)
-    SOFT_DWT_FWD(8, 4, false)
-    SOFT_DWT_FWD(16, 1, false)
-    SOFT_DWT_FWD(8, 2, true)
-    SOFT_DWT_FWD(16, 1, true)
-    SOFT_DWT_FWD(4, 4, true)
-    SOFT_DWT_FWD(8, 4, true)
+    SOFT_DWT_FWD(1, 1, false, false)
+    SOFT_DWT_FWD(2, 1, false, false)
+    SOFT_DWT_FWD(4, 1, false, false)
+    SOFT_DWT_FWD(8, 1, false, false)
+    SOFT_DWT_FWD(1, 2, false, false)
+    SOFT_DWT_FWD(2, 2, false, false)
+    SOFT_DWT_FWD(4, 2, false, false)
+    SOFT_DWT_FWD(8, 2, false, false)
+    SOFT_DWT_FWD(4, 4, false, false)
+    SOFT_DWT_FWD(8, 4, false, false)
+    SOFT_DWT_FWD(16, 1, false, false)
+    SOFT_DWT_FWD(8, 2, true, false)
+    SOFT_DWT_FWD(16, 1, true, false)
+    SOFT_DWT_FWD(4, 4, true, false)
+    SOFT_DWT_FWD(8, 4, true, false)
+    if constexpr (PR == P64) {
+        SOFT_DWT_FWD(1, 1, false, true)
+        SOFT_DWT_FWD(2, 1, false, true)
+        SOFT_DWT_FWD(4, 1, false, true)
+        SOFT_DWT_FWD(2, 2, false, true)
+        SOFT_DWT_FWD(4, 2, false, true)
+        SOFT_DWT_FWD(4, 4, false, true)
+        SOFT_DWT_FWD(4, 4, true, true)
+    }
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
 }
@@ -836,31 +1021,41 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
 template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                          bool stream, const JMap &jm, bool xr, hipStream_t s) {
+                          bool stream, const JMap &jm, bool xr, const DdTables *dd, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int fl = (apply_v ? kFlagScale : 0) | (stream ? kFlagStream : 0);
     const dim3 grid(nitems);
-#define SOFT_DWT_INV(NW_, NS_, XR_)                                                                         \
-    if (nw == NW_ && nsub == NS_ && xr == XR_) {                                                             \
-        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR, XR_>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items,  \
-                           nitems, coeffs, S, fl, jm);                                                       \
-        return hipGetLastError();                                                                            \
+    const DdTables ddt = dd ? *dd : DdTables{nullptr, nullptr};
+#define SOFT_DWT_INV(NW_, NS_, XR_, DD_)                                                                     \
+    if (nw == NW_ && nsub == NS_ && xr == XR_ && (dd != nullptr) == DD_) {                                    \
+        hipLaunchKernelGGL((k_dwt_inv<NW_, NS_, PR, XR_, DD_>), grid, dim3(NW_ * 64), 0, s, tab, tab.rec, items,    \
+                           nitems, coeffs, S, fl, jm, ddt);                                                     \
+        return hipGetLastError();                                                                             \
     }
-    SOFT_DWT_INV(1, 1, false)
-    SOFT_DWT_INV(2, 1, false)
-    SOFT_DWT_INV(4, 1, false)
-    SOFT_DWT_INV(8, 1, false)
-    SOFT_DWT_INV(1, 2, false)
-    SOFT_DWT_INV(2, 2, false)
-    SOFT_DWT_INV(4, 2, false)
-    SOFT_DWT_INV(8, 2, false)
-    SOFT_DWT_INV(4, 4, false)
-    SOFT_DWT_INV(8, 4, false)
-    SOFT_DWT_INV(16, 1, false)
-    SOFT_DWT_INV(8, 2, true)
-    SOFT_DWT_INV(16, 1, true)
-    SOFT_DWT_INV(4, 4, true)
-    SOFT_DWT_INV(8, 4, true)
+    SOFT_DWT_INV(1, 1, false, false)
+    SOFT_DWT_INV(2, 1, false, false)
+    SOFT_DWT_INV(4, 1, false, false)
+    SOFT_DWT_INV(8, 1, false, false)
+    SOFT_DWT_INV(1, 2, false, false)
+    SOFT_DWT_INV(2, 2, false, false)
+    SOFT_DWT_INV(4, 2, false, false)
+    SOFT_DWT_INV(8, 2, false, false)
+    SOFT_DWT_INV(4, 4, false, false)
+    SOFT_DWT_INV(8, 4, false, false)
+    SOFT_DWT_INV(16, 1, false, false)
+    SOFT_DWT_INV(8, 2, true, false)
+    SOFT_DWT_INV(16, 1, true, false)
+    SOFT_DWT_INV(4, 4, true, false)
+    SOFT_DWT_INV(8, 4, true, false)
+    if constexpr (PR == P64) {
+        SOFT_DWT_INV(1, 1, false, true)
+        SOFT_DWT_INV(2, 1, false, true)
+        SOFT_DWT_INV(4, 1, false, true)
+        SOFT_DWT_INV(2, 2, false, true)
+        SOFT_DWT_INV(4, 2, false, true)
+        SOFT_DWT_INV(4, 4, false, true)
+        SOFT_DWT_INV(4, 4, true, true)
+    }
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;
 }
@@ -868,10 +1063,10 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
 #define SOFT_DWT_INSTANTIATE(PR)                                                                          \
     template hipError_t launch_dwt_fwd<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
                                            const PrecT<PR>::C *, PrecT<PR>::C *, bool, bool, const JMap &,  \
-                                           bool, hipStream_t);                                              \
+                                           bool, const DdTables *, hipStream_t);                            \
     template hipError_t launch_dwt_inv<PR>(const DwtTables &, const WorkItem *, int, int, int,               \
                                            const PrecT<PR>::C *, PrecT<PR>::C *, bool, bool, const JMap &,  \
-                                           bool, hipStream_t);
+                                           bool, const DdTables *, hipStream_t);
 SOFT_DWT_INSTANTIATE(P64)
 SOFT_DWT_INSTANTIATE(P32)
 SOFT_DWT_INSTANTIATE(P32S)

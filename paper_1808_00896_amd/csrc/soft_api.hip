@@ -78,10 +78,12 @@ struct soft_plan_s {
     unsigned char *tables = nullptr;
     void *S = nullptr, *t1 = nullptr;
     double2 *rec = nullptr;
+    double2 *rec_lo = nullptr;  // SOFT_DD_RECURRENCE: the recurrence table's low parts
     double *rscale = nullptr;
     double *seed = nullptr;
     long long seed_total = 0;
     soft::DwtTables dtab{};
+    soft::DdTables ddtab{};  // read by the DWT launches of SOFT_DD_RECURRENCE plans
     size_t ws_bytes = 0;
     // stage timing
     struct Pending {
@@ -128,7 +130,12 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // the pairs (matching head) in a 16-bit grid dimension.
 constexpr int kMaxFunctions = 65535;
 
-constexpr unsigned kKnownFlags = SOFT_PLAN_TUNE | SOFT_INPLACE_OK | SOFT_PLAN_GRAPH | SOFT_BETA_HALVES;
+constexpr unsigned kKnownFlags =
+    SOFT_PLAN_TUNE | SOFT_INPLACE_OK | SOFT_PLAN_GRAPH | SOFT_BETA_HALVES | SOFT_DD_RECURRENCE;
+
+bool plan_dd(const soft_plan_s *p) { return (p->flags & SOFT_DD_RECURRENCE) != 0; }
+// The DWT launches' double-double tables: null unless the plan runs the recurrence in double-double.
+const soft::DdTables *dd_tables(const soft_plan_s *p) { return plan_dd(p) ? &p->ddtab : nullptr; }
 
 void free_plan(soft_plan_s *p) {
     if (!p) return;
@@ -142,6 +149,7 @@ void free_plan(soft_plan_s *p) {
     if (p->S) (void)hipFree(p->S);
     if (p->t1) (void)hipFree(p->t1);
     if (p->rec) (void)hipFree(p->rec);
+    if (p->rec_lo) (void)hipFree(p->rec_lo);
     if (p->rscale) (void)hipFree(p->rscale);
     if (p->seed) (void)hipFree(p->seed);
     delete p;
@@ -196,9 +204,9 @@ int group_mask(int m, int mp) {
 }
 
 // Fills one band's tables at host address base (laid out by band_layout) and
-// its slices cosb[N], lcs[N], lbin[G] of the plan-wide arrays.
-int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double *cosb, double4 *lcs,
-              double2 *lbin) {
+// its slices cosb[N], cosb_lo[N], lcs[N], lbin[G] of the plan-wide arrays.
+int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double *cosb, double *cosb_lo,
+              double4 *lcs, double2 *lbin) {
     const int B = b.B, N = b.N, P = 2 * B - 1;
     double *w = reinterpret_cast<double *>(base + lay.w);
     GroupInfo *grp = reinterpret_cast<GroupInfo *>(base + lay.grp);
@@ -216,6 +224,7 @@ int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double 
         for (int i = 0; i < B; ++i) s += sinl((long double)(2 * i + 1) * beta) / (long double)(2 * i + 1);
         w[j] = (double)(2.0L * PI * sinl(beta) / ((long double)B * (long double)B) * s);
         cosb[j] = (double)cosl(beta);
+        cosb_lo[j] = (double)(cosl(beta) - (long double)cosb[j]);
         double a, c, d, e;
         split_dd(logl(cosl(beta / 2)), a, c);
         split_dd(logl(sinl(beta / 2)), d, e);
@@ -420,7 +429,8 @@ hipError_t run_forward(soft_plan_t p, const void *grid, void *coeffs, hipStream_
                 e = lg.nw_f == 0 ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax, S,
                                                                      cout_, scaled, s)
                                  : soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_f, lg.nsub_f, S,
-                                                            cout_, scaled, c > 0, group_rows(lg, c), group_xr(lg), s);
+                                                            cout_, scaled, c > 0, group_rows(lg, c), group_xr(lg),
+                                                            dd_tables(p), s);
             if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_FWD);
         }
     }
@@ -453,7 +463,7 @@ hipError_t run_inverse(soft_plan_t p, const void *coeffs, void *grid, hipStream_
                                                                    S, scaled, group_streams<C>(lg), s)
                                  : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nw_i, lg.nsub_i,
                                                             cin, S, scaled, group_streams<C>(lg), group_rows(lg, c),
-                                                            group_xr(lg), s);
+                                                            group_xr(lg), dd_tables(p), s);
             if (e == hipSuccess) e = clk.after(SOFT_STAGE_DWT_INV);
             if (lg.chunks > 1) {
                 const Band &b = p->bands[lg.bands[0]];
@@ -578,7 +588,15 @@ constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2},
 constexpr int kMaxB = 1024;
 constexpr int kMaxClenshawN = 1024;
 
-bool known_shape(int waves, int subsets) {
+// The shapes built with the double-double recurrence (FP64 defaults).
+constexpr int kDdShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {2, 2}, {4, 2}, {4, 4}};
+
+bool known_shape(int waves, int subsets, bool dd) {
+    if (dd) {
+        for (const auto &sh : kDdShapes)
+            if (sh[0] == waves && sh[1] == subsets) return true;
+        return false;
+    }
     for (const auto &sh : kDwtShapes)
         if (sh[0] == waves && sh[1] == subsets) return true;
     return false;
@@ -609,9 +627,10 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
             std::vector<std::pair<int, int>> cand;
             for (const auto &sh : kDwtShapes) {
                 const int cover = sh[0] * sh[1] * 64;
-                if (cover >= lg.rows && cover <= 2 * lg.rows) cand.emplace_back(sh[0], sh[1]);
+                if (cover >= lg.rows && cover <= 2 * lg.rows && known_shape(sh[0], sh[1], plan_dd(p)))
+                    cand.emplace_back(sh[0], sh[1]);
             }
-            if (lg.chunks == 1 && lg.nmax <= kMaxClenshawN) cand.emplace_back(0, 0);
+            if (lg.chunks == 1 && lg.nmax <= kMaxClenshawN && !plan_dd(p)) cand.emplace_back(0, 0);
             auto launch = [&](std::pair<int, int> c) {
                 if (c.first == 0)
                     return dir == 0 ? soft::launch_dwt_fwd_clenshaw<PR>(p->dtab, items_of(p, lg), lg.nitems, lg.nmax,
@@ -620,9 +639,10 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
                                                                      cf, S, false, group_streams<C>(lg), 0);
                 const int nw = c.first, ns = c.second;
                 return dir == 0 ? soft::launch_dwt_fwd<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, S, cf, true,
-                                                           false, group_rows(lg, 0), group_xr(lg), 0)
+                                                           false, group_rows(lg, 0), group_xr(lg), dd_tables(p), 0)
                                 : soft::launch_dwt_inv<PR>(p->dtab, items_of(p, lg), lg.nitems, nw, ns, cf, S, false,
-                                                           group_streams<C>(lg), group_rows(lg, 0), group_xr(lg), 0);
+                                                           group_streams<C>(lg), group_rows(lg, 0), group_xr(lg),
+                                                           dd_tables(p), 0);
             };
             std::vector<float> best(cand.size(), 0.f);
             for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) e = launch(cand[i]);
@@ -673,7 +693,8 @@ std::string tune_cache_key(const soft_plan_s *p) {
         arch = arch.substr(0, arch.find(':'));
     }
     static const char *const prec[] = {"fp64", "fp32", "fp32_split"};
-    std::string k = arch + "|" + prec[p->precision] + "|" + ((p->flags & SOFT_BETA_HALVES) ? "halves" : "whole") + "|";
+    std::string k = arch + "|" + prec[p->precision] + (plan_dd(p) ? "_dd" : "") + "|" +
+                    ((p->flags & SOFT_BETA_HALVES) ? "halves" : "whole") + "|";
     for (size_t bi = 0; bi < p->bands.size(); ++bi)
         k += (bi ? "," : "") + std::to_string(p->bands[bi].B) + "x" + std::to_string(p->bands[bi].funcs.size());
     return k;
@@ -734,9 +755,9 @@ bool write_tune_cache(const char *path, const std::map<std::string, std::vector<
 
 // A launch shape from the cache is usable for a launch group when it is
 // built and covers the group (or is a Clenshaw form the group allows).
-bool cached_shape_ok(const LaunchGroup &lg, int waves, int subsets) {
-    if (waves == 0 && subsets == 0) return lg.chunks == 1 && lg.nmax <= 1024;
-    return known_shape(waves, subsets) && waves * subsets * 64 >= lg.rows;
+bool cached_shape_ok(const LaunchGroup &lg, int waves, int subsets, bool dd) {
+    if (waves == 0 && subsets == 0) return !dd && lg.chunks == 1 && lg.nmax <= 1024;
+    return known_shape(waves, subsets, dd) && waves * subsets * 64 >= lg.rows;
 }
 
 // Applies the cached shapes of p, if its key is in the file; true on a hit.
@@ -747,8 +768,8 @@ bool tune_from_cache(soft_plan_s *p, const char *path) {
     if (it == entries.end() || it->second.size() != 4 * p->groups.size()) return false;
     const std::vector<int> &v = it->second;
     for (size_t gi = 0; gi < p->groups.size(); ++gi)
-        if (!cached_shape_ok(p->groups[gi], v[4 * gi], v[4 * gi + 1]) ||
-            !cached_shape_ok(p->groups[gi], v[4 * gi + 2], v[4 * gi + 3]))
+        if (!cached_shape_ok(p->groups[gi], v[4 * gi], v[4 * gi + 1], plan_dd(p)) ||
+            !cached_shape_ok(p->groups[gi], v[4 * gi + 2], v[4 * gi + 3], plan_dd(p)))
             return false;
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         LaunchGroup &lg = p->groups[gi];
@@ -799,11 +820,16 @@ bool valid_precision(int precision) {
     return precision == SOFT_FP64 || precision == SOFT_FP32 || precision == SOFT_FP32_SPLIT;
 }
 
+// Known flags, and SOFT_DD_RECURRENCE only with FP64.
+bool valid_flags(unsigned flags, int precision) {
+    return !(flags & ~kKnownFlags) && (!(flags & SOFT_DD_RECURRENCE) || precision == SOFT_FP64);
+}
+
 // Host side of a plan: its tables, function table and DWT work lists in
 // one block laid out as on the device, plus the offsets of its parts.
 struct HostTables {
     std::vector<unsigned char> host;
-    size_t funcs_off = 0, cosb_off = 0, lcs_off = 0, lbin_off = 0, total = 0;
+    size_t funcs_off = 0, cosb_off = 0, cosb_lo_off = 0, lcs_off = 0, lbin_off = 0, total = 0;
     std::vector<BandLayout> lays;
     std::vector<std::vector<WorkItem>> lists;
 };
@@ -952,6 +978,8 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
     off = align256(off + sizeof(FuncInfo) * n);
     const size_t cosb_off = ht.cosb_off = off;
     off = align256(off + sizeof(double) * jtot);
+    const size_t cosb_lo_off = ht.cosb_lo_off = off;
+    off = align256(off + sizeof(double) * jtot);
     const size_t lcs_off = ht.lcs_off = off;
     off = align256(off + sizeof(double4) * jtot);
     const size_t lbin_off = ht.lbin_off = off;
@@ -964,12 +992,13 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
     std::vector<unsigned char> &host = ht.host;
     host.assign(total, 0);
     double *cosb_h = reinterpret_cast<double *>(host.data() + cosb_off);
+    double *cosb_lo_h = reinterpret_cast<double *>(host.data() + cosb_lo_off);
     double4 *lcs_h = reinterpret_cast<double4 *>(host.data() + lcs_off);
     double2 *lbin_h = reinterpret_cast<double2 *>(host.data() + lbin_off);
     for (size_t bi = 0; bi < p->bands.size(); ++bi) {
         const Band &b = p->bands[bi];
-        const int rc = fill_band(b, lays[bi], host.data() + b.tab_off, cosb_h + b.jbase, lcs_h + b.jbase,
-                                 lbin_h + b.gbase);
+        const int rc = fill_band(b, lays[bi], host.data() + b.tab_off, cosb_h + b.jbase, cosb_lo_h + b.jbase,
+                                 lcs_h + b.jbase, lbin_h + b.gbase);
         if (rc != SOFT_OK) return rc;
     }
     std::memcpy(host.data() + funcs_off, p->funcs.data(), sizeof(FuncInfo) * n);
@@ -1040,14 +1069,15 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         }
         const size_t total = ht.total;
         const std::vector<unsigned char> &host = ht.host;
-        const size_t funcs_off = ht.funcs_off, cosb_off = ht.cosb_off, lcs_off = ht.lcs_off,
-                     lbin_off = ht.lbin_off;
+        const size_t funcs_off = ht.funcs_off, cosb_off = ht.cosb_off, cosb_lo_off = ht.cosb_lo_off,
+                     lcs_off = ht.lcs_off, lbin_off = ht.lbin_off;
         const std::vector<BandLayout> &lays = ht.lays;
 
         const size_t rec_rows = (size_t)p->rows_total + soft::kPadRows;
         if (hipMalloc(&p->tables, total) != hipSuccess || hipMalloc(&p->S, p->s_total * p->csize) != hipSuccess ||
             (p->t1_elems && hipMalloc(&p->t1, p->t1_elems * p->csize) != hipSuccess) ||
             hipMalloc(&p->rec, rec_rows * sizeof(double2)) != hipSuccess ||
+            (plan_dd(p) && hipMalloc(&p->rec_lo, rec_rows * sizeof(double2)) != hipSuccess) ||
             hipMalloc(&p->rscale, rec_rows * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->seed, p->seed_total * sizeof(double)) != hipSuccess ||
             hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
@@ -1055,7 +1085,8 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
             free_plan(p);
             return SOFT_ERR_OOM;
         }
-        p->ws_bytes = total + (p->s_total + p->t1_elems) * p->csize + rec_rows * (sizeof(double2) + sizeof(double)) +
+        p->ws_bytes = total + (p->s_total + p->t1_elems) * p->csize +
+                      rec_rows * ((plan_dd(p) ? 2 : 1) * sizeof(double2) + sizeof(double)) +
                       p->seed_total * sizeof(double);
 
         // Band views with device pointers (kernel arguments of the FFT passes
@@ -1063,7 +1094,9 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         const double *cosb_d = reinterpret_cast<const double *>(p->tables + cosb_off);
         const double4 *lcs_d = reinterpret_cast<const double4 *>(p->tables + lcs_off);
         const double2 *lbin_d = reinterpret_cast<const double2 *>(p->tables + lbin_off);
+        const double *cosb_lo_d = reinterpret_cast<const double *>(p->tables + cosb_lo_off);
         p->dtab = soft::DwtTables{cosb_d, p->seed, p->rscale, p->rec};
+        p->ddtab = soft::DdTables{cosb_lo_d, p->rec_lo};
         for (size_t bi = 0; bi < p->bands.size(); ++bi) {
             Band &b = p->bands[bi];
             const BandLayout &lay = lays[bi];
@@ -1097,9 +1130,12 @@ int make_plan(const int *Bs, int n, int precision, unsigned flags, soft_plan_t *
         hipError_t e = hipMemcpy(p->tables, host.data(), total, hipMemcpyHostToDevice);
         // Padding rows are read (never used) by prefetches; give them defined values.
         if (e == hipSuccess) e = hipMemset(p->rec, 0, rec_rows * sizeof(double2));
+        if (e == hipSuccess && p->rec_lo) e = hipMemset(p->rec_lo, 0, rec_rows * sizeof(double2));
         if (e == hipSuccess) e = hipMemset(p->rscale, 0, rec_rows * sizeof(double));
         for (const Band &b : p->bands) {
-            if (e == hipSuccess) e = soft::launch_fill_recurrence(b.view, p->rec, p->rscale, 0);
+            if (e == hipSuccess)
+                e = plan_dd(p) ? soft::launch_fill_recurrence_dd(b.view, p->rec, p->rec_lo, p->rscale, 0)
+                               : soft::launch_fill_recurrence(b.view, p->rec, p->rscale, 0);
             if (e == hipSuccess) e = soft::launch_fill_seeds(b.view, p->seed + b.seed_base, 0);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -1166,7 +1202,7 @@ int scratch_address(void **out) {
 extern "C" {
 
 int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out) {
-    if (!out || B < 1 || batch < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!out || B < 1 || batch < 1 || !valid_precision(precision) || !valid_flags(flags, precision)) return SOFT_ERR_INVALID;
     if (!is_pow2(B) || B > kMaxB || batch > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     std::vector<int> Bs;
     try {
@@ -1178,7 +1214,7 @@ int soft_plan(int B, int batch, int precision, unsigned flags, soft_plan_t *out)
 }
 
 int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, soft_plan_t *out) {
-    if (!out || !B_list || n < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!out || !B_list || n < 1 || !valid_precision(precision) || !valid_flags(flags, precision)) return SOFT_ERR_INVALID;
     for (int i = 0; i < n; ++i)
         if (B_list[i] < 1) return SOFT_ERR_INVALID;
     if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
@@ -1188,7 +1224,7 @@ int soft_plan_uneven(const int *B_list, int n, int precision, unsigned flags, so
 }
 
 int soft_plan_check(const int *B_list, int n, int precision, unsigned flags) {
-    if (!B_list || n < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!B_list || n < 1 || !valid_precision(precision) || !valid_flags(flags, precision)) return SOFT_ERR_INVALID;
     for (int i = 0; i < n; ++i)
         if (B_list[i] < 1) return SOFT_ERR_INVALID;
     if (n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
@@ -1225,6 +1261,7 @@ int soft_plan_describe(soft_plan_t p, char *buf, size_t len) {
     std::string d = "{\"precision\": " + std::to_string(p->precision) + ", \"functions\": " + std::to_string(p->n) +
                     ", \"workspace_bytes\": " + std::to_string(p->ws_bytes) +
                     ", \"inplace_ok\": " + ((p->flags & SOFT_INPLACE_OK) ? "true" : "false") +
+                    ", \"dd_recurrence\": " + (plan_dd(p) ? "true" : "false") +
                     ", \"tuned_from_cache\": " + (p->tune_cached ? "true" : "false") + ", \"bands\": [";
     for (size_t bi = 0; bi < p->bands.size(); ++bi)
         d += std::string(bi ? ", " : "") + "{\"B\": " + std::to_string(p->bands[bi].B) +
@@ -1250,12 +1287,12 @@ int soft_plan_set_dwt_shape(soft_plan_t p, int launch, int direction, int waves,
         return SOFT_ERR_INVALID;
     LaunchGroup &lg = p->groups[launch];
     if (waves == 0 && subsets == 0) {  // the Clenshaw forms
-        if (lg.nmax > kMaxClenshawN) return SOFT_ERR_INVALID;
+        if (lg.nmax > kMaxClenshawN || plan_dd(p)) return SOFT_ERR_INVALID;
         (direction == 0 ? lg.nw_f : lg.nw_i) = 0;
         (direction == 0 ? lg.nsub_f : lg.nsub_i) = 0;
         return SOFT_OK;
     }
-    if (!known_shape(waves, subsets) || waves * subsets * 64 < lg.rows) return SOFT_ERR_INVALID;
+    if (!known_shape(waves, subsets, plan_dd(p)) || waves * subsets * 64 < lg.rows) return SOFT_ERR_INVALID;
     (direction == 0 ? lg.nw_f : lg.nw_i) = waves;
     (direction == 0 ? lg.nsub_f : lg.nsub_i) = subsets;
     return SOFT_OK;
@@ -1336,7 +1373,7 @@ int soft_plan_destroy(soft_plan_t p) {
 }
 
 int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out) {
-    if (!out || B < 1 || n < 1 || (flags & ~kKnownFlags) || !valid_precision(precision)) return SOFT_ERR_INVALID;
+    if (!out || B < 1 || n < 1 || !valid_precision(precision) || !valid_flags(flags, precision)) return SOFT_ERR_INVALID;
     if (!is_pow2(B) || B > 512 || n > kMaxFunctions) return SOFT_ERR_UNSUPPORTED;
     soft_match_s *m = new (std::nothrow) soft_match_s;
     if (!m) return SOFT_ERR_OOM;

@@ -229,6 +229,14 @@ struct DwtTables {
                           // restrict argument, so its loads can use the scalar cache)
 };
 
+// The low parts of a SOFT_DD_RECURRENCE plan's tables (the DWT kernels'
+// double-double recurrence): cos(beta_j) - cosb[j] band by band, and
+// (alpha_l, gamma_l) - rec per row.
+struct DdTables {
+    const double *cosb_lo;
+    const double2 *rec_lo;
+};
+
 // Device-side view of one band (all functions of one bandwidth).
 struct PlanView {
     int B, N, G;
@@ -284,6 +292,9 @@ int gamma_argmax_blocks(int N, int csize);
 // Plan-time fill of the rescaled recurrence table of one band (rows from
 // goff[g]; rec and rscale are the plan-wide tables).
 hipError_t launch_fill_recurrence(const PlanView &p, double2 *rec, double *rscale, hipStream_t s);
+// The same in double-double (rec + reclo; rscale rounded from a double-double product).
+hipError_t launch_fill_recurrence_dd(const PlanView &p, double2 *rec, double2 *reclo, double *rscale,
+                                     hipStream_t s);
 
 // Plan-time fill of one band's seed table: seed[g*N + j] = d(l0, l0, m'; b_j)
 // for every group g of the band (N = 2B entries per group).
@@ -296,15 +307,16 @@ hipError_t launch_fill_seeds(const PlanView &p, double *seed, hipStream_t s);
 // apply_v, V_B applied), or adds to them with accum; the inverse reads them
 // and writes S, with streaming stores when stream.  jm selects a beta half
 // (JMap); xr runs the extended-range seeds of the 2B = 2048 band (the shapes
-// 8x2, 16x1, 4x4 and 8x4 only).
+// 8x2, 16x1, 4x4 and 8x4 only); a non-null dd runs the recurrence in
+// double-double with its tables (FP64, shapes 1x1, 2x1, 4x1, 2x2, 4x2, 4x4).
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
-                          bool accum, const JMap &jm, bool xr, hipStream_t s);
+                          bool accum, const JMap &jm, bool xr, const DdTables *dd, hipStream_t s);
 template <int PR>
 hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *coeffs, typename PrecT<PR>::C *S, bool apply_v,
-                          bool stream, const JMap &jm, bool xr, hipStream_t s);
+                          bool stream, const JMap &jm, bool xr, const DdTables *dd, hipStream_t s);
 
 // The same inverse DWT by Clenshaw's backward summation (clenshaw.hip): one
 // block of nmax rounded up to 64 lanes per work item, nmax/2 x 128 bytes of

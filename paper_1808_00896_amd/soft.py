@@ -28,6 +28,7 @@ SOFT_PLAN_TUNE = 1
 SOFT_INPLACE_OK = 2
 SOFT_PLAN_GRAPH = 4
 SOFT_BETA_HALVES = 8
+SOFT_DD_RECURRENCE = 16
 SOFT_OK = 0
 SOFT_ERR_INVALID = -1
 SOFT_ERR_UNSUPPORTED = -2
@@ -328,9 +329,10 @@ def _precision(precision):
     return int(precision)
 
 
-def _flags(tune, inplace_ok, graph=False, beta_halves=False):
+def _flags(tune, inplace_ok, graph=False, beta_halves=False, dd=False):
     return (SOFT_PLAN_TUNE if tune else 0) | (SOFT_INPLACE_OK if inplace_ok else 0) | \
-        (SOFT_PLAN_GRAPH if graph else 0) | (SOFT_BETA_HALVES if beta_halves else 0)
+        (SOFT_PLAN_GRAPH if graph else 0) | (SOFT_BETA_HALVES if beta_halves else 0) | \
+        (SOFT_DD_RECURRENCE if dd else 0)
 
 
 class _PlanBase:
@@ -448,16 +450,18 @@ class Plan(_PlanBase):
     (forward and adjoint_inverse then overwrite their input grid); ``graph``
     replays each call kind as a captured HIP graph (SOFT_PLAN_GRAPH);
     ``beta_halves`` holds the per-order-pair samples for half of the beta
-    samples at a time (SOFT_BETA_HALVES, 2B >= 128; always at B = 1024).
+    samples at a time (SOFT_BETA_HALVES, 2B >= 128; always at B = 1024);
+    ``dd`` runs the DWT's Wigner-d recurrence in double-double
+    (SOFT_DD_RECURRENCE, fp64 only).
     Calls are asynchronous on the current torch stream.
     """
 
     def __init__(self, B, batch=1, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False,
-                 beta_halves=False):
+                 beta_halves=False, dd=False):
         self._init_device(device, precision)
         self.inplace_ok = bool(inplace_ok)
         with torch.cuda.device(self.device):
-            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok, graph, beta_halves))
+            self.handle = soft_plan(B, batch, self.precision, _flags(tune, inplace_ok, graph, beta_halves, dd))
         self.B, self.batch, self.N = B, batch, 2 * B
         self.nc = num_coeffs(B)
 
@@ -478,12 +482,13 @@ class UnevenPlan(_PlanBase):
     """
 
     def __init__(self, Bs, device=None, precision="fp64", tune=False, inplace_ok=False, graph=False,
-                 beta_halves=False):
+                 beta_halves=False, dd=False):
         self._init_device(device, precision)
         self.inplace_ok = bool(inplace_ok)
         self.Bs = [int(b) for b in Bs]
         with torch.cuda.device(self.device):
-            self.handle = soft_plan_uneven(self.Bs, self.precision, _flags(tune, inplace_ok, graph, beta_halves))
+            self.handle = soft_plan_uneven(self.Bs, self.precision,
+                                           _flags(tune, inplace_ok, graph, beta_halves, dd))
         self.grid_offsets, self.coeff_offsets = soft_plan_offsets(self.handle, len(self.Bs))
 
     def grid_shape(self):

@@ -22,9 +22,14 @@ int main() {
         {1}, {2}, {4}, {8}, {16}, {32}, {64}, {128}, {256}, {512}, {16, 16, 16},
         {1, 2, 4, 8, 16, 32, 64, 128}, {128, 4, 64, 4, 32, 1}, {512, 2, 256}, {1024}};
     for (const auto &bs : cases)
-        for (int prec = 0; prec < 3; ++prec)
+        for (int prec = 0; prec < 3; ++prec) {
             for (unsigned flags : {0u, 2u, 4u, 8u, 10u})
                 expect(soft_plan_check(bs.data(), (int)bs.size(), prec, flags), SOFT_OK, "soft_plan_check");
+            // the double-double recurrence: FP64 plans only
+            for (unsigned flags : {16u, 26u})
+                expect(soft_plan_check(bs.data(), (int)bs.size(), prec, flags), prec == 0 ? SOFT_OK : SOFT_ERR_INVALID,
+                       "soft_plan_check dd");
+        }
     std::vector<int> many(300);
     for (size_t i = 0; i < many.size(); ++i) many[i] = 1 << (i % 8);
     expect(soft_plan_check(many.data(), (int)many.size(), 2, 0), SOFT_OK, "300 functions");
@@ -34,7 +39,7 @@ int main() {
     expect(soft_plan_check(odd, 0, 0, 0), SOFT_ERR_INVALID, "n = 0");
     expect(soft_plan_check(zero, 2, 0, 0), SOFT_ERR_INVALID, "B = 0");
     expect(soft_plan_check(odd, 1, 3, 0), SOFT_ERR_INVALID, "precision");
-    expect(soft_plan_check(odd, 1, 0, 16u), SOFT_ERR_INVALID, "flag");
+    expect(soft_plan_check(odd, 1, 0, 32u), SOFT_ERR_INVALID, "flag");
     expect(soft_plan_check(odd, 2, 0, 0), SOFT_ERR_UNSUPPORTED, "B = 12");
     expect(soft_plan_check(big, 1, 0, 0), SOFT_ERR_UNSUPPORTED, "B = 2048");
     soft_plan_t h = nullptr;

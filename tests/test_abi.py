@@ -47,7 +47,10 @@ def test_argument_errors_need_no_gpu(L):
     h = ctypes.c_void_p()
     assert L.soft_plan(0, 1, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
-    assert L.soft_plan(8, 1, 0, 16, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 1, 0, 32, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    # the double-double recurrence is an FP64 option
+    assert L.soft_plan(8, 1, soft.SOFT_FP32, soft.SOFT_DD_RECURRENCE, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan(8, 1, soft.SOFT_FP32_SPLIT, soft.SOFT_DD_RECURRENCE, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 1, 0, 0x80000000, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_describe(None, None, 0) == soft.SOFT_ERR_INVALID
     assert L.soft_plan(8, 1, 7, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
@@ -70,7 +73,7 @@ def test_uneven_argument_errors_need_no_gpu(L):
     assert L.soft_plan_uneven(None, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_uneven(arr, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_uneven(arr, 3, 3, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
-    assert L.soft_plan_uneven(arr, 3, 0, 16, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_plan_uneven(arr, 3, 0, 32, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_plan_uneven(arr, 3, 0, 0, None) == soft.SOFT_ERR_INVALID
     bad = (ctypes.c_int * 3)(8, 0, 4)
     assert L.soft_plan_uneven(bad, 3, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
@@ -91,7 +94,7 @@ def test_match_argument_errors_need_no_gpu(L):
     assert L.soft_match_plan(0, 4, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(8, 0, 0, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(8, 4, 5, 0, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
-    assert L.soft_match_plan(8, 4, 0, 16, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
+    assert L.soft_match_plan(8, 4, 0, 32, ctypes.byref(h)) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(8, 4, 0, 0, None) == soft.SOFT_ERR_INVALID
     assert L.soft_match_plan(24, 4, 2, 0, ctypes.byref(h)) == soft.SOFT_ERR_UNSUPPORTED
     assert h.value is None

@@ -23,8 +23,9 @@ pytestmark = pytest.mark.gpu
 
 B = 1024
 SLICES = (0, 488, 1365, 1560)
-TOL = {"fp64": 1e-9, "fp32": 2e-6, "fp32_split": 2e-6}
-SHAPES = {"fp64": ([4, 4], [4, 4]), "fp32": ([4, 4], [8, 2]), "fp32_split": ([4, 4], [16, 1])}
+TOL = {"fp64": 1e-9, "fp64_dd": 1e-14, "fp32": 2e-6, "fp32_split": 2e-6}
+SHAPES = {"fp64": ([4, 4], [4, 4]), "fp64_dd": ([4, 4], [4, 4]), "fp32": ([4, 4], [8, 2]),
+          "fp32_split": ([4, 4], [16, 1])}
 
 
 @pytest.fixture(scope="module")
@@ -49,10 +50,13 @@ def _max_rel(a, b, chunk=1 << 27):
     return num / den
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32_split", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64_dd", "fp32_split", "fp32"])
 def test_B1024(oracle, dev, coeffs, prec):
-    c = coeffs if prec == "fp64" else coeffs.astype(np.complex64)
-    with soft.Plan(B, precision=prec, inplace_ok=True) as p:
+    """fp64_dd: the double-double recurrence (SOFT_DD_RECURRENCE), which
+    brings the first beta slice from about 7e-13 to the FP64 floor."""
+    dd = prec.endswith("_dd")
+    c = coeffs if prec.startswith("fp64") else coeffs.astype(np.complex64)
+    with soft.Plan(B, precision=prec.replace("_dd", ""), inplace_ok=True, dd=dd) as p:
         d = p.describe()["dwt_launches"][0]
         assert d["beta_halves"] == 2
         assert (d["forward"], d["inverse"]) == SHAPES[prec]
