@@ -200,11 +200,11 @@ UNEVEN_SET = (16, 32, 64, 128)
 TUNE = True  # plans time their DWT launch shapes at creation (outside the timed region)
 
 
-def make_plan(Bs, prec, uniform, inplace=False, graph=False):
+def make_plan(Bs, prec, uniform, inplace=False, graph=False, dd=False):
     from paper_1808_00896_amd import soft
     if uniform:
-        return soft.Plan(Bs[0], batch=len(Bs), precision=prec, tune=TUNE, inplace_ok=inplace, graph=graph)
-    return soft.UnevenPlan(Bs, precision=prec, tune=TUNE, inplace_ok=inplace, graph=graph)
+        return soft.Plan(Bs[0], batch=len(Bs), precision=prec, tune=TUNE, inplace_ok=inplace, graph=graph, dd=dd)
+    return soft.UnevenPlan(Bs, precision=prec, tune=TUNE, inplace_ok=inplace, graph=graph, dd=dd)
 
 
 def workload_key(Bs, prec, uniform):
@@ -296,7 +296,8 @@ def relerr_dev(a, b, chunk=1 << 27):
     return num / den
 
 
-def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, fwd_grid=None, inplace=False, graph=False):
+def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, fwd_grid=None, inplace=False, graph=False,
+            fwd_sample=None, dd=False):
     """Time `steps` fwd+inv of the functions Bs in precision prec.
 
     c_host: coefficients (complex128, flat), rounded to the plan's precision
@@ -307,11 +308,16 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, fwd_grid=None, inplac
     forward then reads a copy).  graph: a SOFT_PLAN_GRAPH plan (each call a
     replay of its captured kernels; the per-stage pass before the timed
     region runs eagerly, since stage timing needs events between kernels).
+    fwd_sample: a device grid (flat) of seeded input for the accuracy report:
+    after the timed region the plan's forward reads it (rounded to this
+    precision), untimed.  dd: a SOFT_DD_RECURRENCE plan (the double-double
+    recurrence; its workload key, and so its traffic record, is its own).
     Returns (record, outputs): outputs holds the device tensors grid, c2
-    (flat), fwd_in (flat) and the plan offsets.
+    (flat), fwd_in (flat), the plan offsets and, with fwd_sample, sample_in
+    (what the forward read) and sample_out (its coefficients).
     """
     import torch
-    plan = make_plan(Bs, prec, uniform, inplace, graph)
+    plan = make_plan(Bs, prec, uniform, inplace, graph, dd)
     dt = plan.dtype
     c = torch.from_numpy(c_host).to(DEV).to(dt).reshape(plan.coeff_shape())
     fwd_in = None if fwd_grid is None else fwd_grid.to(dt).reshape(plan.grid_shape())
@@ -322,8 +328,8 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, fwd_grid=None, inplac
         plan.inverse(c, out=r["grid"])
         plan.forward(r["grid"].clone(), out=r["c2"])
     n = len(Bs)
-    key = workload_key(Bs, prec, uniform)
-    res = {"functions": n, "precision": prec, "steps": steps,
+    key = workload_key(Bs, prec, uniform) + ("_dd" if dd else "")
+    res = {"functions": n, "precision": prec, "steps": steps, "dd_recurrence": bool(dd),
            "value": round(steps * n / r["seconds"], 3), "unit": "function fwd+inv/s",
            "ms_per_step": round(r["seconds"] / steps * 1e3, 4),
            "step_ms": percentiles(r["step_ms"]),
@@ -341,6 +347,11 @@ def run_leg(Bs, prec, steps, warmup, c_host, uniform=True, fwd_grid=None, inplac
     out = {"grid": r["grid"].reshape(-1), "c2": r["c2"].reshape(-1),
            "fwd_in": (r["grid"] if fwd_in is None else fwd_in).reshape(-1),
            "grid_offsets": offs, "coeff_offsets": coffs}
+    if fwd_sample is not None:
+        out["sample_in"] = fwd_sample.to(dt).reshape(-1)
+        # a SOFT_INPLACE_OK forward overwrites what it reads: give it a copy
+        src = out["sample_in"].clone() if inplace else out["sample_in"]
+        out["sample_out"] = plan.forward(src.reshape(plan.grid_shape())).reshape(-1)
     plan.close()
     del c
     return res, out
@@ -357,11 +368,14 @@ def host(t):
 SAMPLES = {}
 
 
-def add_full_sample(leg, B, c_in, grid_gpu, fwd_in, c_gpu):
-    """A whole function: the inverse of c_in and the forward of fwd_in (host
-    complex128, exactly what the GPU read) against the oracle in full."""
+def add_full_sample(leg, B, c_in, grid_gpu, fwd_in, c_gpu, oracle_prec="f64"):
+    """A whole function: the inverse of c_in and the forward of fwd_in (a
+    seeded input grid, host complex128, exactly what the GPU read) against the
+    oracle in full; FP64 legs use the long-double oracle ("f80"), whose own
+    error is far below theirs (the double oracle's forward of a random grid
+    errs by about 1.7e-13 at B = 128)."""
     SAMPLES.setdefault(leg, []).append({"kind": "full", "B": B, "c_in": c_in, "grid_gpu": grid_gpu,
-                                        "fwd_in": fwd_in, "c_gpu": c_gpu})
+                                        "fwd_in": fwd_in, "c_gpu": c_gpu, "prec": oracle_prec})
 
 
 def coeff_indices(B, pairs):
@@ -386,19 +400,22 @@ def sample_slices(B):
     return [0, (2 * B) // 3, 2 * B - 1]
 
 
-def add_sampled(leg, B, c_in, grid_dev, c2_dev, fwd_in_tag):
+def add_sampled(leg, B, c_in, grid_dev, c2_dev, fwd_in_tag, oracle_prec="f64", slices=None, pairs=None):
     """Sampled at large B: beta slices of the GPU inverse and order pairs of
-    the GPU forward (whose input, a host grid of HOST_GRIDS[fwd_in_tag], the
-    oracle reads)."""
+    the GPU forward of a seeded input grid (HOST_GRIDS[fwd_in_tag], which the
+    oracle reads); oracle_prec "f80" scores the slices against the
+    long-double oracle (the pairs stay with the double one: a long-double
+    forward_pairs at B = 512 takes about half a minute per pair)."""
     import torch
     N = 2 * B
     g = grid_dev.reshape(N, N, N)
-    slices = {j: host(g[:, j, :]) for j in sample_slices(B)}
-    pairs = sample_pairs(B)
+    slices = {j: host(g[:, j, :]) for j in (sample_slices(B) if slices is None else slices)}
+    pairs = sample_pairs(B) if pairs is None else pairs
     idx = torch.from_numpy(coeff_indices(B, pairs).reshape(-1)).to(c2_dev.device)
     cg = host(c2_dev.reshape(-1)[idx]).reshape(len(pairs), B)
     SAMPLES.setdefault(leg, []).append({"kind": "sampled", "B": B, "c_in": c_in, "slices": slices,
-                                        "pairs": pairs, "c_pairs": cg, "fwd_in": fwd_in_tag})
+                                        "pairs": pairs, "c_pairs": cg, "fwd_in": fwd_in_tag,
+                                        "prec": oracle_prec})
 
 
 HOST_GRIDS = {}
@@ -459,26 +476,30 @@ def score_samples(O, cache):
         for s in samples:
             B = s["B"]
             kc = ckey(B, s["c_in"])
+            op = s.get("prec", "f64")
             if s["kind"] == "full":
-                gi = memo(("inv",) + kc, lambda: O.inverse(B, s["c_in"]))
-                cf = memo(("fwd",) + ckey(B, s["fwd_in"]), lambda: O.forward(B, s["fwd_in"]))
-                rep.append({"B": B, "inverse": err_report(s["grid_gpu"], gi),
-                            "forward": err_report(s["c_gpu"], cf, B)})
+                gi = memo(("inv", op) + kc, lambda: O.inverse(B, s["c_in"], op))
+                cf = memo(("fwd", op) + ckey(B, s["fwd_in"]), lambda: O.forward(B, s["fwd_in"], op))
+                inv, fwd = err_report(s["grid_gpu"], gi), err_report(s["c_gpu"], cf, B)
+                inv["oracle"] = fwd["oracle"] = op
+                rep.append({"B": B, "inverse": inv, "forward": fwd})
             else:
                 inv = {}
                 worst = {"max_rel": 0.0, "l2_num": 0.0, "l2_den": 0.0}
                 for j, sl in s["slices"].items():
-                    want = memo(("slice", j) + kc, lambda: O.inverse_slice(B, s["c_in"], j))
+                    want = memo(("slice", j, op) + kc, lambda: O.inverse_slice(B, s["c_in"], j, op))
                     e = np.abs(sl - want)
                     worst["max_rel"] = max(worst["max_rel"], e.max() / np.abs(want).max())
                     worst["l2_num"] += float(np.sum(e ** 2))
                     worst["l2_den"] += float(np.sum(np.abs(want) ** 2))
                 inv = {"max_rel": sig(worst["max_rel"]), "l2_rel": sig(np.sqrt(worst["l2_num"] / worst["l2_den"])),
-                       "sampled": f"beta slices {sorted(s['slices'])} (each max-normed)"}
+                       "sampled": f"beta slices {sorted(s['slices'])} (each max-normed)", "oracle": op}
                 g = HOST_GRIDS[s["fwd_in"]]
                 want = memo(("pairs", s["fwd_in"], tuple(s["pairs"])),
                             lambda: O.forward_pairs(B, g, s["pairs"]))
-                rep.append({"B": B, "inverse": inv, "forward": pairs_report(s["c_pairs"], want, s["pairs"])})
+                fwd = pairs_report(s["c_pairs"], want, s["pairs"])
+                fwd["oracle"] = "f64"
+                rep.append({"B": B, "inverse": inv, "forward": fwd})
         out[leg] = rep
     return out
 
@@ -487,18 +508,29 @@ def score_samples(O, cache):
 # Legs of the metric
 # ---------------------------------------------------------------------------
 
-def leg_single(B, prec, steps, warmup, c_host, name, legs, sampled=False, keep_grid_tag=None):
-    """One function of bandwidth B: timed, then its accuracy sample."""
+def sample_grid(B):
+    """The seeded random grid whose forward a leg of bandwidth B reports
+    against the oracle (on the device, complex128, flat)."""
+    import torch
+    from paper_1808_00896_amd import inputs
+    return torch.from_numpy(inputs.grid_random(B, 700 + B).reshape(-1)).to(DEV)
+
+
+def leg_single(B, prec, steps, warmup, c_host, name, legs, sampled=False, grid_tag=None):
+    """One function of bandwidth B: timed, then its accuracy sample (the
+    inverse of c_host and the forward of a seeded random grid; sampled:
+    grid_tag names that grid, as read, in HOST_GRIDS)."""
     log(f"{name}: B={B} {prec} steps={steps}")
-    res, out = run_leg([B], prec, steps, warmup, c_host)
+    res, out = run_leg([B], prec, steps, warmup, c_host, fwd_sample=sample_grid(B))
     legs[name] = res
     c_in = c_host.astype(np.complex64).astype(np.complex128) if prec != "fp64" else c_host
+    fin = host(out.pop("sample_in")).reshape((2 * B,) * 3)
+    op = "f80" if prec == "fp64" else "f64"
     if sampled:
-        if keep_grid_tag:
-            HOST_GRIDS[keep_grid_tag] = host(out["fwd_in"]).reshape((2 * B,) * 3)
-        add_sampled(name, B, c_in, out["grid"], out["c2"], keep_grid_tag)
+        HOST_GRIDS[grid_tag] = fin
+        add_sampled(name, B, c_in, out["grid"], out["sample_out"], grid_tag, oracle_prec=op)
     else:
-        add_full_sample(name, B, c_in, host(out["grid"]), host(out["fwd_in"]).reshape((2 * B,) * 3), host(out["c2"]))
+        add_full_sample(name, B, c_in, host(out["grid"]), fin, host(out["sample_out"]), oracle_prec=op)
     return res, out
 
 
@@ -521,7 +553,7 @@ def main_legs(args, legs):
     legs[f"B{SMALL_B}_fp64_graph"] = r
     c256 = inputs.coeffs_decay(MID_B, 2)
     leg_single(MID_B, "fp64", max(10, args.steps // 5), 2, c256, f"B{MID_B}_fp64", legs, sampled=True,
-               keep_grid_tag=f"B{MID_B}_fp64_grid")
+               grid_tag=f"B{MID_B}_fp64_sample")
     return main, main_grid, c_host
 
 
@@ -532,21 +564,22 @@ def batch_legs(args, legs, B, c_host, main_grid):
     nb = args.batch
     cb = np.tile(c_host, nb)
     gb = main_grid.repeat(nb)
+    gs = sample_grid(B).repeat(nb)  # every function's forward sample reads the same seeded grid
     for prec in ("fp64", "fp32", "fp32_split"):
         name = f"B{B}_batch{nb}_{prec}"
         log(f"{name}")
         res, out = run_leg([B] * nb, prec, max(5, args.steps // 5), 2, cb,
-                           fwd_grid=None if prec == "fp64" else gb)
+                           fwd_grid=None if prec == "fp64" else gb, fwd_sample=gs)
         legs[name] = res
         rnd = (lambda a: a.astype(np.complex64).astype(np.complex128)) if prec != "fp64" else (lambda a: a)
         n3, nc = (2 * B) ** 3, num_coeffs(B)
         for f in (0, nb - 1):
             add_full_sample(name, B, rnd(c_host), host(out["grid"][f * n3:(f + 1) * n3]),
-                            host(out["fwd_in"][f * n3:(f + 1) * n3]).reshape((2 * B,) * 3),
-                            host(out["c2"][f * nc:(f + 1) * nc]))
+                            host(out["sample_in"][f * n3:(f + 1) * n3]).reshape((2 * B,) * 3),
+                            host(out["sample_out"][f * nc:(f + 1) * nc]), oracle_prec="f80" if prec == "fp64" else "f64")
         del out
         torch.cuda.empty_cache()
-    del gb
+    del gb, gs
 
 
 def b512_legs(args, legs):
@@ -557,17 +590,18 @@ def b512_legs(args, legs):
     B = BIG_B
     c5 = inputs.coeffs_decay(B, 3)
     r5, out5 = leg_single(B, "fp64", args.b512_steps, 1, c5, f"B{B}_fp64", legs, sampled=True,
-                          keep_grid_tag=f"B{B}_fp64_grid")
+                          grid_tag=f"B{B}_fp64_sample")
     g64 = out5["grid"]
-    HOST_GRIDS[f"B{B}_fp64_grid_c64"] = HOST_GRIDS[f"B{B}_fp64_grid"].astype(np.complex64).astype(np.complex128)
+    del out5["sample_out"]
+    HOST_GRIDS[f"B{B}_c64_sample"] = HOST_GRIDS[f"B{B}_fp64_sample"].astype(np.complex64).astype(np.complex128)
     c5r = c5.astype(np.complex64).astype(np.complex128)
     for prec in ("fp32", "fp32_split"):
         name = f"B{B}_{prec}"
         log(name)
-        r, out = run_leg([B], prec, args.b512_steps, 1, c5, fwd_grid=g64)
+        r, out = run_leg([B], prec, args.b512_steps, 1, c5, fwd_grid=g64, fwd_sample=sample_grid(B))
         r["inverse_err_vs_fp64_gpu"] = relerr_dev(out["grid"], g64)
         legs[name] = r
-        add_sampled(name, B, c5r, out["grid"], out["c2"], f"B{B}_fp64_grid_c64")
+        add_sampled(name, B, c5r, out["grid"], out["sample_out"], f"B{B}_c64_sample")
         del out
         torch.cuda.empty_cache()
     for prec in ("fp32", "fp32_split"):
@@ -579,6 +613,18 @@ def b512_legs(args, legs):
     r["speedup_vs_fp64"] = round(r["value"] / r5["value"], 3)
     legs[f"B{B}_fp64_inplace"] = r
     del out, out5, g64
+    torch.cuda.empty_cache()
+    # the double-double recurrence (SOFT_DD_RECURRENCE): the first and last
+    # beta slices (where the FP64 recurrence errs most) against the
+    # long-double oracle; the FP64 leg's order pairs of the same grid
+    name = f"B{B}_fp64_dd"
+    log(name)
+    r, out = run_leg([B], "fp64", args.b512_steps, 1, c5, dd=True, fwd_sample=sample_grid(B))
+    r["speedup_vs_fp64"] = round(r["value"] / r5["value"], 3)
+    legs[name] = r
+    add_sampled(name, B, c5, out["grid"], out["sample_out"], f"B{B}_fp64_sample", oracle_prec="f80",
+                slices=[0, 2 * B - 1])
+    del out
     torch.cuda.empty_cache()
 
 
@@ -593,18 +639,23 @@ def uneven_legs(args, legs):
     log(f"uneven: {n} functions, B in {UNEVEN_SET}, {cu.size} coefficients")
     picks = [Bs.index(b) for b in sorted(set(Bs))]
     g64 = None
+    # forward samples: a seeded random grid for each picked function, zeros elsewhere
+    go0 = np.concatenate([[0], np.cumsum([(2 * b) ** 3 for b in Bs])])  # grids back to back
+    gs = torch.zeros(int(go0[-1]), dtype=torch.complex128, device=DEV)
+    for f in picks:
+        gs[go0[f]:go0[f + 1]] = sample_grid(Bs[f])
     for prec in ("fp64", "fp32", "fp32_split"):
         name = f"uneven{n}_{prec}"
         log(name)
-        r, out = run_leg(Bs, prec, args.uneven_steps, 1, cu, uniform=False, fwd_grid=g64)
+        r, out = run_leg(Bs, prec, args.uneven_steps, 1, cu, uniform=False, fwd_grid=g64, fwd_sample=gs)
         legs[name] = r
         go, co = out["grid_offsets"], out["coeff_offsets"]
         for f in picks:
             B = Bs[f]
             c_in = cs[f] if prec == "fp64" else cs[f].astype(np.complex64).astype(np.complex128)
             add_full_sample(name, B, c_in, host(out["grid"][go[f]:go[f + 1]]),
-                            host(out["fwd_in"][go[f]:go[f + 1]]).reshape((2 * B,) * 3),
-                            host(out["c2"][co[f]:co[f + 1]]))
+                            host(out["sample_in"][go[f]:go[f + 1]]).reshape((2 * B,) * 3),
+                            host(out["sample_out"][co[f]:co[f + 1]]), oracle_prec="f80" if prec == "fp64" else "f64")
         if prec == "fp64":
             g64 = out["grid"].clone()
             ru = r
@@ -621,7 +672,7 @@ def uneven_legs(args, legs):
     for k in list(legs):
         if k.startswith("uneven"):
             legs[k]["bandwidths"] = {str(b): Bs.count(b) for b in sorted(set(Bs))}
-    del g64
+    del g64, gs
     torch.cuda.empty_cache()
 
 
@@ -708,8 +759,9 @@ def match_leg(steps, B=128, n=64):
 def cpu_baseline(B, budget_s=12.0, max_reps=3):
     """The FP64 oracle timed on the host cores on a bounded sample of the
     headline workload (inverse of the headline coefficients, forward of the
-    GPU's grid, up to max_reps times); its results then score every leg's
-    accuracy samples.  Returns (baseline record, accuracy record)."""
+    headline leg's seeded sample grid, up to max_reps times); its results
+    then score every leg's accuracy samples.  Returns (baseline record,
+    accuracy record)."""
     from oracle import oracle as O
     main = SAMPLES.get(f"B{B}_fp64", [None])[0]
     reps, t = 0, 0.0
@@ -720,11 +772,11 @@ def cpu_baseline(B, budget_s=12.0, max_reps=3):
         c = O.forward(B, main["fwd_in"])
         t += time.perf_counter() - t0
         reps += 1
-    cache[("inv",) + fingerprint(B, main["c_in"])] = g
-    cache[("fwd",) + fingerprint(B, main["fwd_in"])] = c
+    cache[("inv", "f64") + fingerprint(B, main["c_in"])] = g
+    cache[("fwd", "f64") + fingerprint(B, main["fwd_in"])] = c
     base = {"value": round(reps / t, 4), "unit": "fwd+inv/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{reps} x (inverse + forward) at B={B}, FP64 oracle (OpenMP): the headline coefficients "
-                      f"and the GPU's grid of them", "seconds": round(t, 2)}
+            "sample": f"{reps} x (inverse + forward) at B={B}, FP64 oracle (OpenMP): the inverse of the headline "
+                      f"coefficients and the forward of a seeded random grid", "seconds": round(t, 2)}
     t0 = time.perf_counter()
     acc = score_samples(O, cache)
     log(f"oracle scoring of {sum(len(v) for v in acc.values())} samples: {time.perf_counter() - t0:.1f} s")
