@@ -142,9 +142,10 @@ typedef enum {
  *                   and of the contraction (Sect. 5 names B = 512 as the size
  *                   where double precision alone falls short on its CPU
  *                   design, which used extended precision).  Costs about
- *                   fifteen times the recurrence's arithmetic; the DWT launch
- *                   shapes are the FP64 defaults 1x1, 2x1, 4x1, 2x2, 4x2 and
- *                   4x4, and the Clenshaw forms are not available.
+ *                   fifteen times the recurrence's arithmetic (1.7 times the
+ *                   FP64 transform time at B = 512); the DWT launch shapes
+ *                   are those of soft_plan_set_dwt_shape's list for it, and
+ *                   the Clenshaw forms are not available.
  */
 enum {
     SOFT_PLAN_TUNE = 1u,
@@ -266,8 +267,8 @@ int soft_plan_describe(soft_plan_t plan, char *buf, size_t len);
  *              adjoint-Clenshaw evaluation: each lane runs the three-term
  *              recurrence forward and the sums over beta are reduced across
  *              lanes).  soft_plan_describe reports it as [0, 0].
- *              A SOFT_DD_RECURRENCE plan takes 1x1, 2x1, 4x1, 2x2, 4x2 and
- *              4x4 only (no Clenshaw form).
+ *              A SOFT_DD_RECURRENCE plan takes 1x1, 2x1, 4x1, 8x1, 2x2, 4x2,
+ *              8x2, 16x1 and 4x4 only (no Clenshaw form).
  * Takes effect for later calls.  Returns SOFT_OK or SOFT_ERR_INVALID.
  */
 int soft_plan_set_dwt_shape(soft_plan_t plan, int launch, int direction, int waves, int subsets);

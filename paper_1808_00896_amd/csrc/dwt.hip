@@ -974,8 +974,8 @@ hipError_t launch_fill_recurrence_dd(const PlanView &p, double2 *rec, double2 *r
 // 8x1, 1x2, 2x2, 4x2, 8x2, 16x1, 4x4, 8x4; a shape covers items with beta
 // rows (2B, or jm.n) <= waves*subsets*64.  The extended-range (xr) forms
 // exist for the shapes that cover a beta half of 2B = 2048 or all of it.
-// The double-double recurrence (dd, FP64 only) is built for the FP64
-// default shapes 1x1, 2x1, 4x1, 2x2, 4x2, 4x4 (and 4x4 xr).
+// The double-double recurrence (dd, FP64 only) is built for the shapes
+// 1x1, 2x1, 4x1, 8x1, 2x2, 4x2, 8x2, 16x1 and 4x4 (and 4x4, 8x2, 16x1 xr).
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,
@@ -1012,7 +1012,12 @@ hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitem
         SOFT_DWT_FWD(2, 2, false, true)
         SOFT_DWT_FWD(4, 2, false, true)
         SOFT_DWT_FWD(4, 4, false, true)
+        SOFT_DWT_FWD(8, 1, false, true)
+        SOFT_DWT_FWD(8, 2, false, true)
+        SOFT_DWT_FWD(16, 1, false, true)
         SOFT_DWT_FWD(4, 4, true, true)
+        SOFT_DWT_FWD(8, 2, true, true)
+        SOFT_DWT_FWD(16, 1, true, true)
     }
 #undef SOFT_DWT_FWD
     return hipErrorInvalidValue;
@@ -1054,7 +1059,12 @@ hipError_t launch_dwt_inv(const DwtTables &tab, const WorkItem *items, int nitem
         SOFT_DWT_INV(2, 2, false, true)
         SOFT_DWT_INV(4, 2, false, true)
         SOFT_DWT_INV(4, 4, false, true)
+        SOFT_DWT_INV(8, 1, false, true)
+        SOFT_DWT_INV(8, 2, false, true)
+        SOFT_DWT_INV(16, 1, false, true)
         SOFT_DWT_INV(4, 4, true, true)
+        SOFT_DWT_INV(8, 2, true, true)
+        SOFT_DWT_INV(16, 1, true, true)
     }
 #undef SOFT_DWT_INV
     return hipErrorInvalidValue;

@@ -275,7 +275,10 @@ int fill_band(const Band &b, const BandLayout &lay, unsigned char *base, double 
 // wave) for N beta rows (2B, or a beta half of 2B = 2048), forward and
 // inverse: the fastest shape measured per length on MI355X (SOFT_PLAN_TUNE
 // re-measures on the plan itself).
-std::pair<int, int> shape_for(int N, bool forward, int precision) {
+std::pair<int, int> shape_for(int N, bool forward, int precision, bool dd) {
+    // the double-double recurrence (more registers per lane): fewer subsets per wave
+    if (dd && N == 256) return {2, 2};
+    if (dd && N == 1024) return {8, 2};
     if (N <= 32) return {1, 1};
     if (N == 64) return forward ? std::make_pair(1, 1) : std::make_pair(2, 1);
     if (N == 128) return {2, 1};
@@ -588,8 +591,8 @@ constexpr int kDwtShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {2, 2},
 constexpr int kMaxB = 1024;
 constexpr int kMaxClenshawN = 1024;
 
-// The shapes built with the double-double recurrence (FP64 defaults).
-constexpr int kDdShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {2, 2}, {4, 2}, {4, 4}};
+// The shapes built with the double-double recurrence.
+constexpr int kDdShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}, {8, 2}, {16, 1}, {4, 4}};
 
 bool known_shape(int waves, int subsets, bool dd) {
     if (dd) {
@@ -960,8 +963,8 @@ int build_host(soft_plan_s *p, const int *Bs, int n, int precision, unsigned fla
         }
         lg.rows = lg.nmax / lg.chunks;
         const int len = keys[gi] ? lg.rows : 64;
-        std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision);
-        std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision);
+        std::tie(lg.nw_f, lg.nsub_f) = shape_for(len, true, precision, plan_dd(p));
+        std::tie(lg.nw_i, lg.nsub_i) = shape_for(len, false, precision, plan_dd(p));
         lg.nitems = (int)lists[gi].size();
         p->groups.push_back(lg);
     }
@@ -1020,6 +1023,8 @@ int check_host(const soft_plan_s *p, const HostTables &ht) {
         if ((size_t)lg.nitems != ht.lists[gi].size()) return SOFT_ERR_INVALID;
         if ((lg.nw_f && lg.nw_f * lg.nsub_f * 64 < lg.rows) || (lg.nw_i && lg.nw_i * lg.nsub_i * 64 < lg.rows))
             return SOFT_ERR_INVALID;
+        if (!known_shape(lg.nw_f, lg.nsub_f, plan_dd(p)) || !known_shape(lg.nw_i, lg.nsub_i, plan_dd(p)))
+            return SOFT_ERR_INVALID;  // every default shape is a built one
         if (lg.chunks > 1 && (lg.bands.size() != 1 || p->bands[lg.bands[0]].chunks != lg.chunks))
             return SOFT_ERR_INVALID;
         for (const WorkItem &w : ht.lists[gi]) {

@@ -308,7 +308,8 @@ hipError_t launch_fill_seeds(const PlanView &p, double *seed, hipStream_t s);
 // and writes S, with streaming stores when stream.  jm selects a beta half
 // (JMap); xr runs the extended-range seeds of the 2B = 2048 band (the shapes
 // 8x2, 16x1, 4x4 and 8x4 only); a non-null dd runs the recurrence in
-// double-double with its tables (FP64, shapes 1x1, 2x1, 4x1, 2x2, 4x2, 4x4).
+// double-double with its tables (FP64; shapes 1x1, 2x1, 4x1, 8x1, 2x2, 4x2,
+// 8x2, 16x1, 4x4; xr: 4x4, 8x2, 16x1).
 template <int PR>
 hipError_t launch_dwt_fwd(const DwtTables &tab, const WorkItem *items, int nitems, int nw, int nsub,
                           const typename PrecT<PR>::C *S, typename PrecT<PR>::C *coeffs, bool apply_v,

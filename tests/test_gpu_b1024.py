@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 B = 1024
 SLICES = (0, 488, 1365, 1560)
 TOL = {"fp64": 1e-9, "fp64_dd": 1e-14, "fp32": 2e-6, "fp32_split": 2e-6}
-SHAPES = {"fp64": ([4, 4], [4, 4]), "fp64_dd": ([4, 4], [4, 4]), "fp32": ([4, 4], [8, 2]),
+SHAPES = {"fp64": ([4, 4], [4, 4]), "fp64_dd": ([8, 2], [8, 2]), "fp32": ([4, 4], [8, 2]),
           "fp32_split": ([4, 4], [16, 1])}
 
 

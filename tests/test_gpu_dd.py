@@ -19,7 +19,7 @@ from paper_1808_00896_amd import inputs, soft
 
 pytestmark = pytest.mark.gpu
 
-DD_SHAPES = [(1, 1), (2, 1), (4, 1), (2, 2), (4, 2), (4, 4)]
+DD_SHAPES = [(1, 1), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2), (8, 2), (16, 1), (4, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -91,7 +91,7 @@ def test_every_dd_shape(oracle, dev, B):
             cf = host(p.forward(to_dev(gr, dev)))
             assert relerr(g, want_g) <= 2e-15, sh
             assert relerr(cf, want_c) <= 2e-15, sh
-        for sh in ((8, 1), (8, 2), (16, 1), (8, 4), (0, 0)):
+        for sh in ((1, 2), (8, 4), (0, 0)):
             for d in (0, 1):
                 with pytest.raises(soft.SoftError):
                     p.set_dwt_shape(0, d, *sh)

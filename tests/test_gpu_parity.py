@@ -187,3 +187,17 @@ def test_plan_errors_on_gpu(dev):
         p.forward(torch.zeros((8, 8, 8), dtype=torch.complex64, device=dev))
     p.close()
     p.close()
+
+
+def test_plan_out_of_memory_is_reported(dev):
+    """A plan whose workspace cannot fit (64 functions at B = 512: 1.1 TB of
+    per-order-pair samples) returns SOFT_ERR_OOM, frees what it took, and the
+    device then runs a transform as before."""
+    with pytest.raises(soft.SoftError) as err:
+        soft.Plan(512, batch=64)
+    assert err.value.status == soft.SOFT_ERR_OOM
+    B = 8
+    c = inputs.coeffs_uniform(B, 7)
+    with soft.Plan(B) as p:
+        c2 = to_host(p.forward(p.inverse(to_dev(c, dev))))
+    assert relerr(c2, c) <= TOL64
