@@ -540,6 +540,39 @@ def test_quadratic_refinement_moves_toward_off_grid_rotation(oracle):
     assert np.allclose(got, want, atol=1e-12)
 
 
+def test_quadratic_refinement_wraps_clamps_and_keeps_end_samples(oracle):
+    """The read-out's edge cases: alpha and gamma are periodic (a vertex at
+    i = -0.3 is found from the neighbours across i = 0 and i = 2B - 1); a step
+    past half a sample is clamped to 1/2; at the first and last beta samples
+    beta is not moved; a symmetric peak, or an axis that bends up, is not
+    moved."""
+    B = 8
+    N = 2 * B
+    i, j, k = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    di = np.minimum(np.abs(i + 0.3), np.abs(i + 0.3 - N))  # periodic distance to i = -0.3
+    par = -(di ** 2) - (j - 0.0) ** 2 - 0.25 * np.abs(k - 9.0)  # beta peaked at j = 0, gamma a tent
+    idx = oracle.argmax_real(par)
+    assert idx == (0 * N + 0) * N + 9
+    a, b, g = oracle.refine_quadratic(B, par, idx)
+    assert np.isclose(g, -0.3 * np.pi / B)  # i = 0 moved by -0.3 through i = 2B - 1
+    assert np.isclose(b, np.pi / (4 * B))  # the first beta sample stays
+    assert np.isclose(a, 9 * np.pi / B)  # a symmetric tent: step 0
+    # along the last axis (read out as the first angle): the vertex of the
+    # parabola through (3, 0), (4, 1), (5, 0.99) is 4 + 0.99 / 2.02 ...
+    g2 = np.zeros((N, N, N))
+    g2[2, 5, 3], g2[2, 5, 4], g2[2, 5, 5] = 0.0, 1.0, 0.99
+    a2, _, _ = oracle.refine_quadratic(B, g2, (2 * N + 5) * N + 4)
+    assert np.isclose(a2, (4 + 0.99 / 2.02) * np.pi / B)
+    # ... and through (3, 0), (4, 1), (5, 1.5) it would lie 1.5 samples on: clamped to 1/2
+    g2[2, 5, 5] = 1.5
+    a3, _, _ = oracle.refine_quadratic(B, g2, (2 * N + 5) * N + 4)
+    assert np.isclose(a3, 4.5 * np.pi / B)
+    # an axis that bends up (2, 1, 2) is not moved
+    g2[2, 5, 3], g2[2, 5, 5] = 2.0, 2.0
+    a4, _, _ = oracle.refine_quadratic(B, g2, (2 * N + 5) * N + 4)
+    assert np.isclose(a4, 4 * np.pi / B)
+
+
 def test_corr_eval_is_the_inverse_at_grid_points(oracle):
     """corr_eval at (alpha_i, beta_j, gamma_k) equals the inverse transform's
     grid value there, and one coefficient f°(1, 1, 0) gives the closed form
