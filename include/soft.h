@@ -189,12 +189,12 @@ typedef enum {
  * Allocates the plan's device workspace (per function, about 2 (2B)^3
  * complex elements for the FFT intermediate and the per-order-pair beta
  * samples, or about (2B)^3 with SOFT_INPLACE_OK, half of that for the
- * samples at 2B = 2048; per distinct bandwidth,
- * 12 bytes per recurrence row, about B^3/6 rows, and the 8-byte seeds d(l0, l0, m'; b_j) of every symmetry group at
- * every beta sample, B(B+1)/2 x 2B of them) and its tables (quadrature
- * weights, Wigner-d seed constants, FFT twiddles, symmetry groups, work
- * lists) on the current HIP device; later
- * calls must run with the same device current.  Synchronous.
+ * samples at 2B = 2048; per distinct bandwidth, 24 bytes per recurrence
+ * row (40 with SOFT_DD_RECURRENCE), about B^3/6 rows, and the 8-byte seeds
+ * d(l0, l0, m'; b_j) of every symmetry group at every beta sample,
+ * B(B+1)/2 x 2B of them) and its tables (quadrature weights, Wigner-d seed
+ * constants, FFT twiddles, symmetry groups, work lists) on the current HIP
+ * device; later calls must run with the same device current.  Synchronous.
  * Returns SOFT_OK, SOFT_ERR_INVALID, SOFT_ERR_UNSUPPORTED, SOFT_ERR_OOM or
  * SOFT_ERR_HIP.
  */
@@ -402,8 +402,9 @@ typedef struct soft_match_s *soft_match_t;
  *   out  receives the handle; unchanged on error.
  * Owns a soft_plan of n functions of bandwidth B (made with the same flags:
  * with SOFT_INPLACE_OK it holds no FFT intermediate, and soft_adjoint_inverse
- * on it overwrites its input grid), one set of n coefficient vectors, and the
- * argmax partial results (16 bytes per pair and scanned block).
+ * on it overwrites its input grid), one set of n coefficient vectors, the
+ * argmax partial results (16 bytes per pair and scanned block), and the
+ * workspace of soft_match_polish (80 bytes per pair plus at most 160 KB).
  * Synchronous.  Returns as soft_plan.
  */
 int soft_match_plan(int B, int n, int precision, unsigned flags, soft_match_t *out);
@@ -548,8 +549,12 @@ int soft_match_refine(soft_match_t match, const void *grid, const long long *ind
  *   angles  device, n x 3 double (written): the polished (a, b, c), b in
  *           [0, pi], a and c in [0, 2 pi).
  *   value   device, n double (written): Re C at the polished rotation.
- * One block per pair; allocates nothing.  Returns SOFT_OK, SOFT_ERR_INVALID
- * or SOFT_ERR_HIP.
+ * Each step is one launch that evaluates the ten points over chunks of the
+ * symmetry groups (blocks of (chunk, pair), about 2048 in all) and one that
+ * sums the chunks and takes the step (a thread per pair).  The per-pair state
+ * and chunk sums live in the head's workspace (made by soft_match_plan), so
+ * calls on one head must not overlap; allocates nothing.  Returns SOFT_OK,
+ * SOFT_ERR_INVALID or SOFT_ERR_HIP.
  */
 int soft_match_polish(soft_match_t match, const void *coeffs, const double *start, int iters, double *angles,
                       double *value, hipStream_t stream);

@@ -675,9 +675,10 @@ hipError_t tune_dwt_prec(soft_plan_s *p, void *coeffs) {
 }
 
 // Autotune cache (SOFT_TUNE_CACHE names a file): the launch shapes a tuned
-// plan chose, keyed by the device architecture, the precision, whether the
-// plan runs beta halves, and its bandwidths with their function counts.  The
-// file is a JSON object with one entry per line,
+// plan chose, keyed by the device architecture, the precision (with "_dd"
+// for the double-double recurrence), whether the plan runs beta halves, and
+// its bandwidths with their function counts.  The file is a JSON object with
+// one entry per line,
 //   "gfx950|fp64|whole|128x1": [[4, 1, 4, 1]],
 // one [forward waves, subsets, inverse waves, subsets] per DWT launch in
 // plan order.  A plan whose key is present, with one valid shape per launch,
