@@ -30,7 +30,9 @@
 // In the FP32 modes the partial sums over one k-slot (16 beta samples) or one
 // panel (16 degrees) are FP32 and are combined in FP64.  The split mode's
 // tail products (d - hi(d), about 2^-24 of d) run on bf16 matrix cores, four
-// FP32 k steps per v_mfma_f32_16x16x16_bf16.
+// FP32 k steps per v_mfma_f32_16x16x16_bf16.  FP64 plans made with
+// SOFT_DD_RECURRENCE run the recurrence in double-double (the DD_ forms of
+// the kernels) and round each value once into the same FP64 contraction.
 #include "soft_internal.h"
 
 namespace soft {
@@ -560,7 +562,8 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
 // Four accumulators keep four MFMA chains in flight (in the FP32 modes each
 // covers 16 beta samples; the split mode keeps the lo products apart).
 // Lane row k of the launch's beta rows (all 2B, or one beta half of jm) is
-// beta sample beta_of(jm, k); XR: extended-range seeds (2B = 2048).
+// beta sample beta_of(jm, k); XR: extended-range seeds (2B = 2048); DD_: the
+// double-double recurrence with the low parts in ddt.
 template <int NW, int NSUB, int PR, bool XR, bool DD_>
 __global__ __launch_bounds__(NW * 64) void k_dwt_fwd(DwtTables tab, const double2 *__restrict__ rec,
                                                     const WorkItem *__restrict__ items, int nitems,
