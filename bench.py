@@ -22,10 +22,10 @@ while it times the oracle: in full at B <= 128, on sampled beta slices and
 order pairs at B = 256 and 512.
 
 --summarize-rocprof WORKLOAD turns the rocprofv3 runs of one workload
-(kernel trace, FETCH_SIZE and WRITE_SIZE counters, under
-gpurun_out/prof/WORKLOAD/) into the summaries under profiles/ and the
-per-launch HBM bytes in profiles/traffic.json; PROFILE_RECIPE below gives the
-commands.
+(kernel trace, FETCH_SIZE and WRITE_SIZE counters, and shader counters of
+the matrix cores and the LDS, under gpurun_out/prof/WORKLOAD/) into the
+summaries under profiles/ and the per-launch HBM bytes in
+profiles/traffic.json; PROFILE_RECIPE below gives the commands.
 """
 import argparse
 import csv
@@ -61,8 +61,27 @@ PROFILE_RECIPE = (
     "python bench.py --only {w} --steps 2 --warmup 1 --no-cpu-baseline --calibrate-copy",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/{w}/write -o run -- "
     "python bench.py --only {w} --steps 2 --warmup 1 --no-cpu-baseline --calibrate-copy",
+    "rocprofv3 --pmc {sq} --output-format csv -d gpurun_out/prof/{w}/sq -o run -- "
+    "python bench.py --only {w} --steps 2 --warmup 1 --no-cpu-baseline",
     "python bench.py --summarize-rocprof {w}",
 )
+
+# Shader counters of the fourth pass (at most 8 SQ and 2 GRBM counters in one
+# pass): the matrix-core instructions and their operations of the plan's
+# precision (MOPS: units of 512 flop), the matrix cores' busy cycles, the
+# LDS instructions and bank-conflict cycles, the FP64 vector FMAs (the
+# recurrence) and the GPU's busy cycles.
+SQ_COUNTERS = {
+    "fp64": "SQ_INSTS_VALU_MFMA_F64 SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_FMA_F64 "
+            "SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
+    "fp32": "SQ_INSTS_VALU_MFMA_F32 SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_BF16 "
+            "SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_FMA_F64 SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_BUSY_CYCLES "
+            "GRBM_GUI_ACTIVE",
+}
+
+
+def sq_counters_of(workload):
+    return SQ_COUNTERS["fp64" if workload.startswith("fp64") else "fp32"]
 
 
 def log(msg):
@@ -1011,7 +1030,7 @@ def summarize_rocprof(workload, trace_steps=10, pmc_steps=2):
     run before them)."""
     base = os.path.join(ROOT, "gpurun_out", "prof", workload)
     srcs = f"fft.hip+soft_internal.h {source_digest('fft')}, dwt.hip+soft_internal.h {source_digest('dwt')}"
-    cmds = [c.format(w=workload) for c in PROFILE_RECIPE]
+    cmds = [c.format(w=workload, sq=sq_counters_of(workload)) for c in PROFILE_RECIPE]
     Bs, prec = _workload_bands(workload)
     work = stage_work(Bs, prec)
     stats = _csv_rows(os.path.join(base, "trace", "**", "*kernel_stats.csv"))
@@ -1117,6 +1136,73 @@ def summarize_rocprof(workload, trace_steps=10, pmc_steps=2):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(traffic, fh, indent=1, sort_keys=True)
         fh.write("\n")
+    summarize_sq(workload, base, cmds[3], srcs, avg_of, work, pmc_steps)
+
+
+def summarize_sq(workload, base, cmd, srcs, avg_of, work, pmc_steps):
+    """profiles/<workload>_sq_counters.txt from the shader-counter pass: per
+    stage and launch, the matrix-core operations executed (MOPS x 512 flop)
+    against the contraction's algorithmic flops 8 B N_c per function (their
+    ratio counts the padded lanes: absent members, rows past a group's last
+    degree, the split mode's tail), the matrix cores' busy share (busy cycles
+    over the launch's duration x 2.4 GHz x 1024 SIMDs), the FP64 vector FMA
+    flops (64 lanes x 2 per instruction: the recurrence) against the
+    recurrence's algorithmic (5/3) B (B^3 - B), LDS instructions and
+    bank-conflict cycles per LDS instruction."""
+    rows = _csv_rows(os.path.join(base, "sq", "**", "*counter_collection.csv"))
+    if not rows:
+        log("no shader-counter run found")
+        return
+    vals = {}
+    for r in rows:
+        key = (int(r["Dispatch_Id"]), r["Counter_Name"])
+        vals.setdefault(key, [r, 0.0])
+        vals[key][1] += float(r["Counter_Value"])
+    by_disp = {}
+    for (d, name), (r, v) in vals.items():
+        by_disp.setdefault(d, {"Kernel_Name": r["Kernel_Name"], "Dispatch_Id": d})[name] = v
+    disp = list(by_disp.values())
+    names = sq_counters_of(workload).split()
+    mops = [n for n in names if "MOPS" in n]
+    Bs, _ = _workload_bands(workload)
+    contraction = sum(8.0 * B * num_coeffs(B) for B in Bs)
+    recurrence = sum(5.0 / 3.0 * B * (B ** 3 - B) for B in Bs)
+    lines = [f"# shader counters per launch (rocprofv3 --pmc): workload {workload}",
+             f"# command: {cmd}",
+             f"# kernel sources: {srcs}",
+             f"# per stage, the mean over the launches of the last {pmc_steps} timed steps; avg_us from the kernel trace",
+             "# mfma_GF: matrix-core operations executed, sum of " + " + ".join(mops) + " x 512 flop",
+             "# busy: SQ_VALU_MFMA_BUSY_CYCLES / (avg_us x 2400 cycles/us x 1024 SIMDs)",
+             "# fma64_GF: SQ_INSTS_VALU_FMA_F64 x 128 flop; rec_GF: the recurrence's algorithmic flops",
+             f"{'stage':14s} {'avg_us':>8s} {'contr_GF':>8s} {'mfma_GF':>8s} {'ratio':>6s} {'busy':>6s} "
+             f"{'rec_GF':>7s} {'fma64_GF':>8s} {'lds_M':>7s} {'confl/lds':>9s}"]
+    for st, (_, avg) in avg_of.items():
+        per_step = calls_per_step(workload, st)
+        d = _last_dispatches(disp, st, pmc_steps * per_step)
+        if not d:
+            continue
+
+        def mean(n):
+            return sum(x.get(n, 0.0) for x in d) / len(d)
+
+        mf = sum(mean(n) for n in mops) * 512.0
+        dwt = st.startswith("dwt")
+        algo = contraction / per_step if dwt else 0.0
+        rec_f = recurrence / per_step if dwt else 0.0
+        busy = mean("SQ_VALU_MFMA_BUSY_CYCLES") / (avg * 2400.0 * 1024)
+        lds = mean("SQ_INSTS_LDS")
+        confl = mean("SQ_LDS_BANK_CONFLICT") / lds if lds else 0.0
+        ratio = f"{mf / algo:6.3f}" if algo else f"{'-':>6s}"
+        lines.append(f"{st:14s} {avg:8.2f} {algo / 1e9:8.3f} {mf / 1e9:8.3f} {ratio} {busy:6.3f} "
+                     f"{rec_f / 1e9:7.3f} {mean('SQ_INSTS_VALU_FMA_F64') * 128 / 1e9:8.3f} {lds / 1e6:7.2f} "
+                     f"{confl:9.3f}")
+    lines.append("# raw means per launch:")
+    for st in avg_of:
+        d = _last_dispatches(disp, st, pmc_steps * calls_per_step(workload, st))
+        if d:
+            lines.append(f"#   {st}: " + ", ".join(f"{n} {sum(x.get(n, 0.0) for x in d) / len(d):.4g}" for n in names))
+    with open(os.path.join(ROOT, "profiles", f"{workload}_sq_counters.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def _workload_bands(workload):
