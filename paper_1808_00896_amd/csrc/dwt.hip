@@ -449,7 +449,16 @@ __device__ __forceinline__ void fwd_item_panels(double (&panel)[NW][16 * kRowFwd
                 panel_fill<PR, kRowFwd, XR, DD_>(pan + lane, c, cl, x[h], xl[h], ecur[h], eprev[h], ecl[h], epl[h], xs[h]);
                 double a[16];
 #pragma unroll
-                for (int s = 0; s < 16; ++s) a[s] = pan[col * kRowFwd + 4 * s + krow];
+                for (int s = 0; s < 16; ++s) {
+                    a[s] = pan[col * kRowFwd + 4 * s + krow];
+                    // With one subset the compiler pairs these reads into
+                    // ds_read2_b64 (offsets 32 bytes apart), whose two halves
+                    // meet on the same banks: 2.9 conflict cycles per LDS
+                    // instruction (rocprofv3 SQ_LDS_BANK_CONFLICT) and a forward
+                    // 5-7 % slower at B = 64 ... 256.  An empty asm with a memory
+                    // clobber between them keeps them single ds_read_b64.
+                    if constexpr (NSUB == 1) asm volatile("" ::: "memory");
+                }
                 if (h == NSUB - 1) {
                     lds_wait_all();
 #pragma unroll
@@ -781,7 +790,11 @@ __device__ __forceinline__ void inv_panel(double (&panel)[NW][16 * kRowInv], con
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) a[t][s] = pan[(s + 4 * krow) * kRowInv + 16 * t + col];
+                for (int s = 0; s < 4; ++s) {
+                    a[t][s] = pan[(s + 4 * krow) * kRowInv + 16 * t + col];
+                    // single ds_read_b64s, as in the forward (1-4 % faster with one subset)
+                    if constexpr (NSUB == 1) asm volatile("" ::: "memory");
+                }
             if (h == NSUB - 1) {
                 lds_wait_all();
 #pragma unroll
