@@ -129,6 +129,45 @@ def test_uneven_matches_oracle(oracle, dev, prec):
         assert relerr(cr[coff[f]:coff[f + 1]], oracle.forward(B, gs[f])) <= TOL[prec], (f, B)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_split"])
+def test_uneven256_config_against_oracle(oracle, dev, prec):
+    """The 256-function batch of bandwidths drawn from {16, 32, 64, 128}
+    (seed 4, the throughput configuration), in a tuned plan as timed: the
+    round trip of every function, and for the first function of each
+    bandwidth its inverse, and the forward of a seeded random grid, against
+    the oracle (FP64) on the same input as the device sees it."""
+    Bs, cs = inputs.uneven_batch(256, [16, 32, 64, 128], seed=4)
+    picks = [Bs.index(b) for b in sorted(set(Bs))]
+    with soft.UnevenPlan(Bs, precision=prec, tune=True) as p:
+        goff, coff = p.grid_offsets, p.coeff_offsets
+        cflat = to_dev(np.concatenate(cs), dev, prec)
+        gflat = p.inverse(cflat)
+        c2 = p.forward(gflat)
+        # round trip, every function, compared on the device
+        worst = 0.0
+        for f in range(len(Bs)):
+            a, b = c2[coff[f]:coff[f + 1]], cflat[coff[f]:coff[f + 1]]
+            worst = max(worst, float((a - b).abs().max() / b.abs().max()))
+        print(f"{prec}: worst round trip over {len(Bs)} functions {worst:.3e}")
+        assert worst <= TOL[prec]
+        grids = {f: to_host(gflat[goff[f]:goff[f + 1]]) for f in picks}
+        # forward of seeded random grids in the picked functions' slots
+        gin = torch.zeros_like(gflat)
+        rnd = {f: rounded(inputs.grid_random(Bs[f], 400 + f), prec) for f in picks}
+        for f in picks:
+            gin[goff[f]:goff[f + 1]] = to_dev(rnd[f].reshape(-1), dev, prec)
+        cr = p.forward(gin)
+        fwd = {f: to_host(cr[coff[f]:coff[f + 1]]) for f in picks}
+        del cflat, gflat, c2, gin, cr
+    torch.cuda.empty_cache()
+    for f in picks:
+        B = Bs[f]
+        ei = relerr(grids[f].reshape((2 * B,) * 3), oracle.inverse(B, rounded(cs[f], prec)))
+        ef = relerr(fwd[f], oracle.forward(B, rnd[f]))
+        print(f"{prec} B={B} (function {f}): inverse {ei:.3e} forward {ef:.3e}")
+        assert ei <= TOL[prec] and ef <= TOL[prec], (f, B, ei, ef)
+
+
 def test_uneven_offsets_and_sizes(dev):
     Bs = [4, 1, 8, 4]
     with soft.UnevenPlan(Bs) as p:
