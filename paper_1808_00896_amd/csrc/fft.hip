@@ -241,9 +241,16 @@ struct Tile {
     // 49.0 ms) and the in-grid inverse alpha pass at 2B = 1024 (8.5 -> 8.1 ms),
     // while the passes above 128 VGPRs only gain barriers (forward alpha 7.6
     // -> 8.7 ms; forcing 128 VGPRs made them spill and slower still).
+    // At 2B = 256 the complex128 tile's whole buffer (70 KB) leaves two
+    // blocks per CU; in halves (35 KB) three share a CU (the kernels use
+    // 122-152 VGPRs).  Measured at B = 128 that pays for the passes through
+    // the plan's intermediate except the forward gamma pass (alpha forward
+    // 96 -> 92 us, the inverse passes 101 -> 99 us, the step 0.604 -> 0.599
+    // ms; the forward gamma pass 88 -> 91 us, so it keeps the whole tile).
     static constexpr bool BIG = (size_t)T * Shape<N>::RS * sizeof(C) > 96 * 1024;
     static constexpr bool RH_PAYS = KIND == GAMMA_FWD || (KIND == ALPHA_INV && INGRID && N == 1024);
-    static constexpr int RH = Shape<N>::P > 1 && BIG && T % 2 == 0 && NT <= 512 && RH_PAYS ? 2 : 1;
+    static constexpr bool THREE = N == 256 && sizeof(C) == 16 && !INGRID && KIND != GAMMA_FWD;
+    static constexpr int RH = Shape<N>::P > 1 && ((BIG && RH_PAYS) || THREE) && T % 2 == 0 && NT <= 512 ? 2 : 1;
     static constexpr int LDS = Shape<N>::P > 1 ? (T / RH) * Shape<N>::RS : 1;
 };
 
