@@ -1229,8 +1229,10 @@ def calls_per_step(workload, stage):
     return len({0 if b * 2 <= 64 else b for b in bands})
 
 
-ONLY_LEGS = ("fp64_B128_n1", "fp64_B512_n1", "fp32_split_B512_n1", "fp32_B512_n1", "fp32_split_B128_n16",
-             "fp32_B128_n16", "fp64_B128_n16", "fp64_uneven256", "fp32_split_uneven256")
+ONLY_LEGS = ("fp64_B128_n1", "fp64_B256_n1", "fp64_B512_n1", "fp32_split_B512_n1", "fp32_B512_n1",
+             "fp32_split_B128_n16", "fp32_B128_n16", "fp64_B128_n16", "fp64_uneven256", "fp32_split_uneven256")
+# Coefficient seed of a one-bandwidth workload, as its leg draws it.
+ONLY_SEED = {128: 1, 256: 2, 512: 3}
 
 
 def run_only(args):
@@ -1239,7 +1241,7 @@ def run_only(args):
     Bs, prec = _workload_bands(args.only)
     uniform = len(set(Bs)) == 1 and not args.only.startswith(prec + "_uneven")
     if uniform:
-        c = np.tile(inputs.coeffs_decay(Bs[0], 1 if Bs[0] <= 256 else 3), len(Bs))
+        c = np.tile(inputs.coeffs_decay(Bs[0], ONLY_SEED.get(Bs[0], 1)), len(Bs))
     else:
         _, cs = inputs.uneven_batch(len(Bs), [16, 32, 64, 128], seed=4)
         c = np.concatenate(cs)
