@@ -1229,7 +1229,7 @@ def calls_per_step(workload, stage):
     return len({0 if b * 2 <= 64 else b for b in bands})
 
 
-ONLY_LEGS = ("fp64_B128_n1", "fp64_B256_n1", "fp64_B512_n1", "fp32_split_B512_n1", "fp32_B512_n1",
+ONLY_LEGS = ("fp64_B16_n1", "fp64_B128_n1", "fp64_B256_n1", "fp64_B512_n1", "fp32_split_B512_n1", "fp32_B512_n1",
              "fp32_split_B128_n16", "fp32_B128_n16", "fp64_B128_n16", "fp64_uneven256", "fp32_split_uneven256")
 # Coefficient seed of a one-bandwidth workload, as its leg draws it.
 ONLY_SEED = {128: 1, 256: 2, 512: 3}
@@ -1240,7 +1240,9 @@ def run_only(args):
     from paper_1808_00896_amd import inputs
     Bs, prec = _workload_bands(args.only)
     uniform = len(set(Bs)) == 1 and not args.only.startswith(prec + "_uneven")
-    if uniform:
+    if uniform and Bs[0] == SMALL_B:
+        c = np.tile(inputs.coeffs_uniform(SMALL_B, 0), len(Bs))
+    elif uniform:
         c = np.tile(inputs.coeffs_decay(Bs[0], ONLY_SEED.get(Bs[0], 1)), len(Bs))
     else:
         _, cs = inputs.uneven_batch(len(Bs), [16, 32, 64, 128], seed=4)
