@@ -136,3 +136,13 @@ def test_workload_bands():
     assert bench.calls_per_step("fp64_uneven256", "fft_alpha_fwd") == 4
     assert bench.calls_per_step("fp64_uneven256", "dwt_fwd") == 3
     assert bench.calls_per_step("fp64_B512_n1", "dwt_fwd") == 1
+
+
+def test_only_workloads_parse_and_match_their_legs():
+    """Every workload `--only` accepts names its bands and precision, and a
+    one-bandwidth workload draws the coefficients its bench leg draws."""
+    for w in bench.ONLY_LEGS:
+        Bs, prec = bench._workload_bands(w)
+        assert prec in ("fp64", "fp32", "fp32_split") and Bs and all(b & (b - 1) == 0 for b in Bs), w
+    assert bench.ONLY_SEED == {128: 1, 256: 2, 512: 3}
+    assert "fp64_B16_n1" in bench.ONLY_LEGS and bench.SMALL_B == 16
